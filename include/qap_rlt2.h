@@ -1,0 +1,206 @@
+/*
+ * qap_rlt2.h -- C ABI of the MI355X RLT2 dual-ascent library.
+ *
+ * The library computes lower bounds for the Quadratic Assignment Problem
+ *     min_perm  sum_i b_{i,perm(i)} + sum_{i,j} f_ij d_{perm(i),perm(j)}
+ * (Lawler form, Eq. 1.1 of Date & Nagi, arXiv:1710.03732) by the Lagrangian
+ * dual ascent on the level-2 RLT formulation (RLT2-DA, Section 2.3,
+ * Algorithm 1, in its one-phase "fast" form F1 of Section 3.4), and solves
+ * small QAPs exactly by branch-and-bound on those bounds (Section 4).
+ *
+ * Conventions for every entry point:
+ *   - return 0 (QAP_OK) on success, a negative QAP_E* code on failure; no C++
+ *     exception crosses the ABI; on failure the outputs are left untouched
+ *     and qap_last_error(h) describes the problem;
+ *   - "host" pointers are ordinary CPU memory, read or written during the
+ *     call only (the caller keeps ownership); "device" pointers are HIP
+ *     device memory on the handle's device;
+ *   - all matrices are row-major; sizes are element counts;
+ *   - a handle is used by one host thread at a time; the library keeps no
+ *     global state;
+ *   - results are deterministic: equal inputs and parameters give bitwise
+ *     equal outputs (up to the sign of zero).
+ *
+ * Data layout in device memory (also the layout of exported state):
+ *   n facilities/locations; m = n - 2.
+ *   Pair index ("tile") t(i,p,j,q) for i != j, p != q:
+ *       t = ((i*n + p)*(n-1) + j')*(n-1) + q',   j' = j - [j>i], q' = q - [q>p];
+ *       T = n^2 (n-1)^2 tiles.
+ *   y-level array (T doubles): entry (i,j,p,q) at t(i,p,j,q).  The Y-LAP of
+ *       (i,p) is the contiguous (n-1)x(n-1) block t(i,p,.,.).
+ *   z-level array (T*m*m doubles, tile-major): entry (i,j,k,p,q,r) at
+ *       t(i,p,j,q)*m*m + k''*m + r'',  k'' = k - [k>i] - [k>j],
+ *       r'' = r - [r>p] - [r>q].  Tile t is the Z-LAP of (i,j,p,q).
+ *   x-level array (n*n doubles): entry (i,p) at i*n + p.
+ */
+#ifndef QAP_RLT2_H
+#define QAP_RLT2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QAP_OK 0
+#define QAP_EINVAL (-1)       /* bad argument: n out of range, NULL required pointer,
+                                 non-finite data, kappa/phi outside [0,1] */
+#define QAP_ENOMEM (-2)       /* device arena larger than free memory (checked first) */
+#define QAP_EDEVICE (-3)      /* HIP runtime error (text in qap_last_error) */
+#define QAP_ESTATE (-4)       /* call out of order, or bad checksum on import */
+#define QAP_EUNSUPPORTED (-5) /* n outside the supported range 3..64 */
+
+typedef struct qap_ctx *qap_handle;
+
+/* Device memory callbacks; NULL alloc selects hipMalloc/hipFree. */
+typedef void *(*qap_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*qap_free_fn)(void *ptr, void *ctx);
+
+/* Dual-ascent parameters.  kappa_* are the fractions of slack moved by the
+ * Type 1 (z), Type 2 (y) and Type 3 (x) ascent rules (Eqs. da:rule1-3); phi_z
+ * is the share each of the five symmetric partners receives (the phi^z_k of
+ * the rules, all equal); phi_y the share of the y-pair rule (Eq. da:yrule1).
+ * qap_default_params() gives the FULL preset: kappa_z = 5/6,
+ * kappa_y = kappa_x = 1, phi_z = 1/5, phi_y = 1/2. */
+typedef struct qap_params {
+    double kappa_z, kappa_y, kappa_x;
+    double phi_z;
+    double phi_y;
+    double min_gap;        /* stop when (UB - LB)/|UB| < min_gap; 0 disables */
+    int device;            /* HIP device ordinal */
+    int zlap_lanes;        /* Z-LAP lanes per LAP (8/16/32/64); 0 = autotuned */
+    int zlap_cols;         /* columns per lane (1/2); 0 = autotuned */
+    int reserved_i;
+    qap_alloc_fn alloc;    /* optional device allocator */
+    qap_free_fn free_fn;
+    void *alloc_ctx;
+} qap_params;
+
+typedef struct qap_da_stats {
+    int iterations_done;   /* iterations run by this call */
+    int t;                 /* iterations run since init */
+    double lb;             /* best lower bound (F1 bounds are monotone) */
+    double ub;             /* best X-LAP permutation cost (+inf if none) */
+    double gap;            /* (ub - lb)/|ub| */
+    int proven;            /* 1 when lb certifies ub optimal (feasibility check) */
+    int pad;
+    long long laps;        /* LAPs solved by this call: iters*(T + n^2 + 1) */
+    long long dijkstra_steps; /* Dijkstra steps of all LAPs of this call */
+    double seconds;        /* wall time of the call (device-synchronised) */
+} qap_da_stats;
+
+typedef struct qap_bnb_params {
+    int batch;             /* open nodes per batched launch (default 256) */
+    int node_iters;        /* dual-ascent iteration cap per node (default 100) */
+    int window;            /* early stop window (default 25) */
+    int root_iters;        /* iterations at the root (default node_iters) */
+    double min_improve;    /* stop a node when its bound rose by less than
+                              min_improve*max(1,|UB|) over `window` (2e-4) */
+    double ub0;            /* initial incumbent value (+inf allowed) */
+    int enum_below;        /* enumerate nodes with at most this many free
+                              facilities (default 3) */
+    int rule;              /* branching rule (3 = lowest interaction first) */
+} qap_bnb_params;
+
+typedef struct qap_bnb_stats {
+    long long nodes;       /* nodes bounded (including enumerated leaves' parents) */
+    long long da_iters;    /* node dual-ascent iterations */
+    long long batches;     /* batched launches */
+    long long enumerated;  /* leaves evaluated by enumeration */
+    double seconds;
+} qap_bnb_stats;
+
+/* State header of qap_export_state / qap_import_state. */
+typedef struct qap_state_header {
+    int n;
+    int t;
+    double lb, ub;
+    uint64_t checksum;     /* FNV-1a over n, t, lb, ub and the three arrays */
+} qap_state_header;
+
+const char *qap_version(void);
+
+/* FULL preset (see qap_params). */
+int qap_default_params(qap_params *p);
+
+/* Device bytes qap_rlt2_init will allocate for size n (0 if n unsupported). */
+size_t qap_workspace_bytes(int n, const qap_params *p);
+
+/* Initialise the dual ascent for a QAP of size n (Algorithm 1 step 1;
+ * RLT1/RLT2 costs of Section 2.1): x costs b_ip + f_ii d_pp, y costs
+ * C_ijpq = f_ij d_pq, z costs 0 (the QAP has no cubic terms), LB = 0.
+ * F, D: host n*n flows and distances; B: host n*n fixed costs or NULL (zero).
+ * Copies the data to the device; returns the handle in *out.
+ * Errors: QAP_EINVAL (NULL F/D/out, non-finite entry, bad params),
+ * QAP_EUNSUPPORTED (n < 3 or n > 64), QAP_ENOMEM, QAP_EDEVICE. */
+int qap_rlt2_init(const double *F, const double *D, const double *B, int n,
+                  const qap_params *p, qap_handle *out);
+
+int qap_destroy(qap_handle h);
+
+/* Run `iters` more F1 iterations (Algorithm 1 steps 2-5): ascent sweep of the
+ * Type 1-3 rules (t >= 1), Z-LAPs, y-pair rule (t >= 1), Y-LAPs, X-LAP,
+ * bound and incumbent update.  Stops early once the bound proves the
+ * incumbent optimal or the gap falls below min_gap.  Writes the best lower
+ * bound to *lb_out and the X-LAP duals alpha (rows, n) and beta (columns, n)
+ * of the last iteration to alpha_out/beta_out (host, nullable); st nullable.
+ * Errors: QAP_EINVAL (iters < 0), QAP_EDEVICE. */
+int qap_dual_ascent(qap_handle h, int iters, double *lb_out, double *alpha_out,
+                    double *beta_out, qap_da_stats *st);
+
+/* Host copy of the bound after each iteration so far; *len gets the count. */
+int qap_get_trace(qap_handle h, double *lb, int cap, int *len);
+
+/* Last X-LAP assignment and best permutation (host, n each, nullable);
+ * perm[i] is the location of facility i. */
+int qap_get_assignment(qap_handle h, int32_t *xperm, int32_t *best_perm);
+
+/* Copy the current reduced costs (x: n*n, y: T, z: T*m*m, host, nullable) in
+ * the layout above.  After k >= 1 iterations these are the LAP dual slacks
+ * pi_x, pi_y, pi_z of the last iteration; before the first, the initial
+ * costs.  For every permutation the identity
+ *   cost = lb + sum x[i,s_i] + sum y[i,j,s_i,s_j] + sum z[i,j,k,s_i,s_j,s_k]
+ * holds up to rounding. */
+int qap_export_state(qap_handle h, qap_state_header *hdr, double *x, double *y, double *z);
+
+/* Reduced costs of selected Z-LAP tiles only (the z part of
+ * qap_export_state for `count` tile indices t, see the layout above).
+ * tiles: host, count tile indices; out: host, count*m*m doubles.
+ * Errors: QAP_EINVAL (index out of range, NULL pointer). */
+int qap_export_z_tiles(qap_handle h, const int64_t *tiles, int count, double *out);
+
+/* Replace the state with exported arrays (resume).  hdr->checksum must match;
+ * the next iteration runs with t = hdr->t.  Errors: QAP_ESTATE on mismatch. */
+int qap_import_state(qap_handle h, const qap_state_header *hdr, const double *x,
+                     const double *y, const double *z);
+
+/* Use the given HIP stream (hipStream_t passed as void*) for all work. */
+int qap_set_stream(qap_handle h, void *hip_stream);
+
+/* Solve the QAP held by h to optimality by depth-first branch-and-bound
+ * (Section 4): polytomic branching in Rule-3 facility order, children warm
+ * started from the parent's reduced costs, node dual ascents batched on the
+ * device.  perm_out (host, n): optimal permutation; *obj_out its exact cost.
+ * p NULL selects the defaults. */
+int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, double *obj_out,
+                  qap_bnb_stats *st);
+
+/* Batched LAP solver (the Hungarian method used for every Z-, Y- and X-LAP,
+ * Section 2.3 "LAP Solution"), exposed for validation.  cost: device,
+ * count*m*m doubles (count matrices, row-major); outputs (device): u
+ * (count*m, row duals), v (count*m, column duals), theta (count, optimal
+ * values), row_of_col (count*m, the row assigned to each column).  All
+ * pointers device memory; stream is a hipStream_t or NULL.  lanes/cols select
+ * the mapping (0 = default).  Errors: QAP_EINVAL (m < 1 or m > 64, count < 0,
+ * NULL pointer), QAP_EDEVICE. */
+int qap_lap_batch(const double *cost, int count, int m, double *u, double *v, double *theta,
+                  int32_t *row_of_col, int lanes, int cols, void *stream);
+
+/* Text of the last error on h (or of the last failed init when h is NULL). */
+const char *qap_last_error(qap_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QAP_RLT2_H */

@@ -62,6 +62,10 @@ def lib():
                               C.c_double, _ip, _dp, C.POINTER(C.c_longlong)]
         L.orc_glb_bnb.argtypes = [C.c_int, _dp, _dp, _dp, C.c_double, _ip, _dp,
                                   C.POINTER(C.c_longlong)]
+        L.orc_da_create_xy.argtypes = [C.c_int, _dp, _dp, _dp, _dp]
+        L.orc_da_create_xy.restype = C.c_void_p
+        L.orc_da_iter0_xy.argtypes = [C.c_void_p]
+        L.orc_iter1_tile.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_max_threads.restype = C.c_int
         _lib = L
@@ -278,3 +282,51 @@ def glb_bnb(F, D, B=None, ub0=float("inf")):
     if rc != 0:
         raise ValueError("GLB B&B: bad size")
     return obj.value, perm, nodes.value
+
+
+class Iter0XY:
+    """Iteration 0 without the (identically zero) z level, and single tiles of
+    the iteration-1 Z-LAPs; for sizes whose n^6 array does not fit a test."""
+
+    def __init__(self, F, D, B=None, params=FULL):
+        F, D = _f64(F), _f64(D)
+        self.n = F.shape[0]
+        B = np.zeros_like(F) if B is None else _f64(B)
+        self._keep = (F, D, B)
+        P = _f64(params)
+        h = lib().orc_da_create_xy(self.n, _d(F), _d(D), _d(B), _d(P))
+        if not h:
+            raise ValueError("oracle: bad instance")
+        self.h = C.c_void_p(h)
+        if lib().orc_da_iter0_xy(self.h) != 0:
+            raise RuntimeError("iteration 0 failed")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().orc_da_free(h)
+            self.h = None
+
+    @property
+    def LB(self) -> float:
+        return float(lib().orc_da_lb(self.h))
+
+    @property
+    def UB(self) -> float:
+        return float(lib().orc_da_ub(self.h))
+
+    def xy(self):
+        n = self.n
+        X = np.zeros((n, n))
+        Y = np.zeros((n,) * 4)
+        lib().orc_da_export(self.h, _d(X), _d(Y), None)
+        return X, Y
+
+    def tile1(self, i, j, p, q):
+        m = self.n - 2
+        M = np.zeros((m, m))
+        pi = np.zeros((m, m))
+        th = C.c_double(0.0)
+        if lib().orc_iter1_tile(self.h, i, j, p, q, _d(M), _d(pi), C.byref(th)) != 0:
+            raise ValueError("bad tile")
+        return M, pi, th.value

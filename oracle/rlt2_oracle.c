@@ -679,6 +679,142 @@ void orc_da_min_entries(const orc_da *s, double *out3)
 }
 
 /* ------------------------------------------------------------------------
+ * Sampled evaluation for sizes whose n^6 array does not fit a test (n = 30,
+ * 42).  At t = 0 the z level is identically zero, so every Z-LAP has value 0
+ * and zero duals and iteration 0 is exactly the Y-LAPs on f_ij d_pq followed
+ * by the X-LAP; orc_da_create_xy builds a state without the z array and
+ * orc_da_iter0_xy runs that iteration.  orc_iter1_tile then forms one tile of
+ * the iteration-1 Z-LAPs entry by entry from the sweep formula (pi_z = 0 at
+ * t = 0, so g_f = (kz*0 + ky2*pi_y) + kx3*pi_x, new_e = okz*0 + phi*sum) and
+ * solves it.
+ * ---------------------------------------------------------------------- */
+orc_da *orc_da_create_xy(int n, const double *F, const double *D, const double *B,
+                         const double *params)
+{
+    if (n < 3 || n > 64) return NULL;
+    orc_da *s = calloc(1, sizeof(orc_da));
+    if (!s) return NULL;
+    s->n = n;
+    if (params) {
+        s->kz = params[0]; s->ky = params[1]; s->kx = params[2];
+        s->phi = params[3]; s->phiy = params[4];
+    } else {
+        s->kz = 5.0 / 6.0; s->ky = 1.0; s->kx = 1.0; s->phi = 1.0 / 5.0; s->phiy = 0.5;
+    }
+    orc_da_derive(s);
+    size_t n2 = (size_t)n * n, n4 = n2 * n2;
+    s->F = malloc(sizeof(double) * n2);
+    s->D = malloc(sizeof(double) * n2);
+    s->B = calloc(n2, sizeof(double));
+    s->X = calloc(n2, sizeof(double));
+    s->Y = calloc(n4, sizeof(double));
+    s->Z = NULL;
+    s->xperm = calloc(n, sizeof(int));
+    s->best_perm = calloc(n, sizeof(int));
+    s->trace_cap = 16;
+    s->trace = malloc(sizeof(double) * s->trace_cap);
+    memcpy(s->F, F, sizeof(double) * n2);
+    memcpy(s->D, D, sizeof(double) * n2);
+    if (B) memcpy(s->B, B, sizeof(double) * n2);
+    s->integer_data = orc_is_integer_instance(n, s->F, s->D, s->B);
+    for (int i = 0; i < n; ++i)
+        for (int p = 0; p < n; ++p)
+            s->X[IX2(n, i, p)] = s->B[IX2(n, i, p)] + s->F[IX2(n, i, i)] * s->D[IX2(n, p, p)];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            for (int p = 0; p < n; ++p)
+                for (int q = 0; q < n; ++q) {
+                    if (q == p) continue;
+                    s->Y[IX4(n, i, j, p, q)] = s->F[IX2(n, i, j)] * s->D[IX2(n, p, q)];
+                }
+        }
+    s->LB = 0.0;
+    s->UB = HUGE_VAL;
+    return s;
+}
+
+int orc_da_iter0_xy(orc_da *s)
+{
+    if (s->t != 0 || s->Z != NULL) return -1;
+    /* Z-phase on all-zero tiles: theta = 0, so R_y = R_y + 0.0 */
+    int n = s->n;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            for (int p = 0; p < n; ++p)
+                for (int q = 0; q < n; ++q) {
+                    if (q == p) continue;
+                    size_t y = IX4(n, i, j, p, q);
+                    s->Y[y] = s->Y[y] + 0.0;
+                }
+        }
+    orc_da_yphase(s);
+    orc_da_xphase(s);
+    orc_trace_push(s, s->LB);
+    s->t = 1;
+    return 0;
+}
+
+/* Tile (i,j,p,q) of the iteration-1 Z-LAPs, from a state after iteration 0
+ * (X = pi_x, Y = pi_y).  Outputs the tile M (m*m, rows k, columns r
+ * ascending), its LAP slacks pi (m*m) and value theta. */
+int orc_iter1_tile(const orc_da *s, int i, int j, int p, int q, double *M_out, double *pi_out,
+                   double *theta_out)
+{
+    int n = s->n, m = n - 2;
+    if (s->t != 1 || i == j || p == q || m < 1 || m > ORC_MAXM) return -1;
+    double *M = malloc(sizeof(double) * m * m);
+    int a = 0;
+    for (int k = 0; k < n; ++k) {
+        if (k == i || k == j) continue;
+        int b = 0;
+        for (int r = 0; r < n; ++r) {
+            if (r == p || r == q) continue;
+            /* the orbit of (i,p),(j,q),(k,r), sorted by facility */
+            int f[3] = {i, j, k}, l[3] = {p, q, r};
+            for (int x = 0; x < 3; ++x)
+                for (int y = x + 1; y < 3; ++y)
+                    if (f[y] < f[x]) {
+                        int tf = f[x]; f[x] = f[y]; f[y] = tf;
+                        int tl = l[x]; l[x] = l[y]; l[y] = tl;
+                    }
+            int fac[6][3], loc[6][3];
+            orbit_members(f[0], f[1], f[2], l[0], l[1], l[2], fac, loc);
+            double g[6];
+            int me = -1;
+            for (int e = 0; e < 6; ++e) {
+                double pz = 0.0;
+                double py = s->Y[IX4(n, fac[e][0], fac[e][1], loc[e][0], loc[e][1])];
+                double px = s->X[IX2(n, fac[e][0], loc[e][0])];
+                g[e] = (s->kz * pz + s->ky2 * py) + s->kx3 * px;
+                if (fac[e][0] == i && fac[e][1] == j && fac[e][2] == k &&
+                    loc[e][0] == p && loc[e][1] == q && loc[e][2] == r) me = e;
+            }
+            double acc = 0.0;
+            int first = 1;
+            for (int e = 0; e < 6; ++e) {
+                if (e == me) continue;
+                if (first) { acc = g[e]; first = 0; }
+                else acc = acc + g[e];
+            }
+            M[a * m + b] = s->okz * 0.0 + s->phi * acc;
+            ++b;
+        }
+        ++a;
+    }
+    double u[ORC_MAXM], v[ORC_MAXM], th;
+    int rc[ORC_MAXM];
+    orc_lap(m, M, u, v, rc, &th, NULL);
+    for (int x = 0; x < m; ++x)
+        for (int y = 0; y < m; ++y) pi_out[x * m + y] = (M[x * m + y] - u[x]) - v[y];
+    if (M_out) memcpy(M_out, M, sizeof(double) * m * m);
+    *theta_out = th;
+    free(M);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
  * O4. Depth-first branch-and-bound with RLT2-DA bounds (Section 4).
  *
  * Polytomic branching: a node at depth d has d facilities fixed; the next

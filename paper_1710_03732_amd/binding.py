@@ -1,0 +1,256 @@
+"""ctypes binding of the C ABI in include/qap_rlt2.h (argument marshalling
+only; every step of the dual ascent runs in the HIP library).
+
+The shared library is built in-tree by ``paper_1710_03732_amd/build.py``;
+importing a handle without it raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqaprlt2.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "qap_rlt2.h")
+
+QAP_OK = 0
+ERRORS = {-1: "QAP_EINVAL", -2: "QAP_ENOMEM", -3: "QAP_EDEVICE", -4: "QAP_ESTATE",
+          -5: "QAP_EUNSUPPORTED"}
+
+_alloc_fn = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_free_fn = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class QapParams(C.Structure):
+    _fields_ = [("kappa_z", C.c_double), ("kappa_y", C.c_double), ("kappa_x", C.c_double),
+                ("phi_z", C.c_double), ("phi_y", C.c_double), ("min_gap", C.c_double),
+                ("device", C.c_int), ("zlap_lanes", C.c_int), ("zlap_cols", C.c_int),
+                ("reserved_i", C.c_int), ("alloc", _alloc_fn), ("free_fn", _free_fn),
+                ("alloc_ctx", C.c_void_p)]
+
+
+class QapDaStats(C.Structure):
+    _fields_ = [("iterations_done", C.c_int), ("t", C.c_int), ("lb", C.c_double),
+                ("ub", C.c_double), ("gap", C.c_double), ("proven", C.c_int), ("pad", C.c_int),
+                ("laps", C.c_longlong), ("dijkstra_steps", C.c_longlong), ("seconds", C.c_double)]
+
+
+class QapBnbParams(C.Structure):
+    _fields_ = [("batch", C.c_int), ("node_iters", C.c_int), ("window", C.c_int),
+                ("root_iters", C.c_int), ("min_improve", C.c_double), ("ub0", C.c_double),
+                ("enum_below", C.c_int), ("rule", C.c_int)]
+
+
+class QapBnbStats(C.Structure):
+    _fields_ = [("nodes", C.c_longlong), ("da_iters", C.c_longlong), ("batches", C.c_longlong),
+                ("enumerated", C.c_longlong), ("seconds", C.c_double)]
+
+
+class QapStateHeader(C.Structure):
+    _fields_ = [("n", C.c_int), ("t", C.c_int), ("lb", C.c_double), ("ub", C.c_double),
+                ("checksum", C.c_uint64)]
+
+
+_dp = C.POINTER(C.c_double)
+_i32p = C.POINTER(C.c_int32)
+_lib = None
+
+EXPORTED = ("qap_version", "qap_default_params", "qap_workspace_bytes", "qap_rlt2_init",
+            "qap_destroy", "qap_dual_ascent", "qap_get_trace", "qap_get_assignment",
+            "qap_export_state", "qap_export_z_tiles", "qap_import_state", "qap_set_stream", "qap_bnb_solve",
+            "qap_lap_batch", "qap_last_error")
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library missing: {LIB_PATH}; run paper_1710_03732_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        L.qap_version.restype = C.c_char_p
+        L.qap_default_params.argtypes = [C.POINTER(QapParams)]
+        L.qap_workspace_bytes.argtypes = [C.c_int, C.POINTER(QapParams)]
+        L.qap_workspace_bytes.restype = C.c_size_t
+        L.qap_rlt2_init.argtypes = [_dp, _dp, _dp, C.c_int, C.POINTER(QapParams), C.POINTER(C.c_void_p)]
+        L.qap_destroy.argtypes = [C.c_void_p]
+        L.qap_dual_ascent.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, C.POINTER(QapDaStats)]
+        L.qap_get_trace.argtypes = [C.c_void_p, _dp, C.c_int, C.POINTER(C.c_int)]
+        L.qap_get_assignment.argtypes = [C.c_void_p, _i32p, _i32p]
+        L.qap_export_state.argtypes = [C.c_void_p, C.POINTER(QapStateHeader), _dp, _dp, _dp]
+        L.qap_export_z_tiles.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_int, _dp]
+        L.qap_import_state.argtypes = [C.c_void_p, C.POINTER(QapStateHeader), _dp, _dp, _dp]
+        L.qap_set_stream.argtypes = [C.c_void_p, C.c_void_p]
+        L.qap_bnb_solve.argtypes = [C.c_void_p, C.POINTER(QapBnbParams), _i32p, _dp,
+                                    C.POINTER(QapBnbStats)]
+        L.qap_lap_batch.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+        L.qap_last_error.argtypes = [C.c_void_p]
+        L.qap_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+class QapError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code, h=None):
+    if code != QAP_OK:
+        msg = lib().qap_last_error(h).decode(errors="replace")
+        raise QapError(code, msg)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def default_params(**kw) -> QapParams:
+    p = QapParams()
+    _check(lib().qap_default_params(C.byref(p)))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def version() -> str:
+    return lib().qap_version().decode()
+
+
+def workspace_bytes(n: int) -> int:
+    return int(lib().qap_workspace_bytes(int(n), None))
+
+
+def tile_count(n: int) -> int:
+    return n * n * (n - 1) * (n - 1)
+
+
+class DualAscent:
+    """Handle of one RLT2 dual-ascent state on the GPU."""
+
+    def __init__(self, F, D, B=None, params: QapParams | None = None, **kw):
+        F, D = _f64(F), _f64(D)
+        n = F.shape[0]
+        self.n = n
+        Bp = None if B is None else _f64(B)
+        if params is None:
+            params = default_params(**kw)
+        self.params = params
+        h = C.c_void_p()
+        code = lib().qap_rlt2_init(_dptr(F), _dptr(D), None if Bp is None else _dptr(Bp), n,
+                                   C.byref(params), C.byref(h))
+        _check(code)
+        self.h = h
+        self.T = tile_count(n)
+        self.m = n - 2
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().qap_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, iters: int):
+        lb = C.c_double(0.0)
+        alpha = np.zeros(self.n)
+        beta = np.zeros(self.n)
+        st = QapDaStats()
+        _check(lib().qap_dual_ascent(self.h, int(iters), C.byref(lb), _dptr(alpha), _dptr(beta),
+                                     C.byref(st)), self.h)
+        return {"lb": lb.value, "alpha": alpha, "beta": beta, "iterations_done": st.iterations_done,
+                "t": st.t, "ub": st.ub, "gap": st.gap, "proven": bool(st.proven), "laps": st.laps,
+                "dijkstra_steps": st.dijkstra_steps, "seconds": st.seconds}
+
+    def trace(self):
+        n = C.c_int(0)
+        _check(lib().qap_get_trace(self.h, None, 0, C.byref(n)), self.h)
+        out = np.zeros(max(1, n.value))
+        _check(lib().qap_get_trace(self.h, _dptr(out), n.value, C.byref(n)), self.h)
+        return out[:n.value]
+
+    def assignment(self):
+        a = np.zeros(self.n, dtype=np.int32)
+        b = np.zeros(self.n, dtype=np.int32)
+        _check(lib().qap_get_assignment(self.h, a.ctypes.data_as(_i32p), b.ctypes.data_as(_i32p)),
+               self.h)
+        return a, b
+
+    def export_state(self, with_z: bool = True):
+        hdr = QapStateHeader()
+        x = np.zeros(self.n * self.n)
+        y = np.zeros(self.T)
+        z = np.zeros(self.T * self.m * self.m) if with_z else None
+        _check(lib().qap_export_state(self.h, C.byref(hdr), _dptr(x), _dptr(y),
+                                      None if z is None else _dptr(z)), self.h)
+        return hdr, x, y, z
+
+    def export_tiles(self, tiles):
+        tiles = np.ascontiguousarray(tiles, dtype=np.int64)
+        out = np.zeros((len(tiles), self.m, self.m))
+        _check(lib().qap_export_z_tiles(self.h, tiles.ctypes.data_as(C.POINTER(C.c_int64)),
+                                        len(tiles), _dptr(out)), self.h)
+        return out
+
+    def import_state(self, hdr, x, y, z):
+        x, y, z = _f64(x), _f64(y), _f64(z)
+        _check(lib().qap_import_state(self.h, C.byref(hdr), _dptr(x), _dptr(y), _dptr(z)), self.h)
+
+    def set_stream(self, stream_handle: int):
+        _check(lib().qap_set_stream(self.h, C.c_void_p(stream_handle)), self.h)
+
+    def bnb_solve(self, batch=256, node_iters=100, window=25, root_iters=0, min_improve=2e-4,
+                  ub0=float("inf"), enum_below=3, rule=3):
+        p = QapBnbParams(batch, node_iters, window, root_iters, min_improve, ub0, enum_below, rule)
+        perm = np.zeros(self.n, dtype=np.int32)
+        obj = C.c_double(0.0)
+        st = QapBnbStats()
+        _check(lib().qap_bnb_solve(self.h, C.byref(p), perm.ctypes.data_as(_i32p), C.byref(obj),
+                                   C.byref(st)), self.h)
+        return obj.value, perm, {"nodes": st.nodes, "da_iters": st.da_iters,
+                                 "batches": st.batches, "enumerated": st.enumerated,
+                                 "seconds": st.seconds}
+
+
+def lap_batch(cost, lanes: int = 0, cols: int = 0, stream: int | None = None):
+    """Solve a batch of LAPs on the GPU.  cost: torch float64 CUDA tensor of
+    shape (count, m, m).  Returns (theta, u, v, row_of_col) as tensors."""
+    import torch
+
+    if not (cost.is_cuda and cost.dtype == torch.float64 and cost.dim() == 3):
+        raise ValueError("cost must be a float64 CUDA tensor (count, m, m)")
+    cost = cost.contiguous()
+    count, m, m2 = cost.shape
+    if m != m2:
+        raise ValueError("square matrices required")
+    u = torch.empty((count, m), dtype=torch.float64, device=cost.device)
+    v = torch.empty_like(u)
+    th = torch.empty((count,), dtype=torch.float64, device=cost.device)
+    rc = torch.empty((count, m), dtype=torch.int32, device=cost.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(cost.device).cuda_stream
+    code = lib().qap_lap_batch(C.c_void_p(cost.data_ptr()), count, m, C.c_void_p(u.data_ptr()),
+                               C.c_void_p(v.data_ptr()), C.c_void_p(th.data_ptr()),
+                               C.c_void_p(rc.data_ptr()), int(lanes), int(cols), C.c_void_p(stream))
+    _check(code)
+    return th, u, v, rc
+
+
+# ---- layout helpers (host-side index maps of the documented layout) ------
+
+def tile_index(n: int, i: int, p: int, j: int, q: int) -> int:
+    jp = j - (j > i)
+    qp = q - (q > p)
+    return ((i * n + p) * (n - 1) + jp) * (n - 1) + qp

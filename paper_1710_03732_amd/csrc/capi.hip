@@ -1,0 +1,692 @@
+// capi.hip -- host side of the C ABI declared in include/qap_rlt2.h.
+//
+// One handle owns one device arena (all arrays of one RLT2 state) and one
+// stream.  qap_dual_ascent enqueues the kernels of each iteration back to
+// back; every kernel first reads the device stop flag, so the host never
+// waits inside the loop and the whole loop can be replayed from a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/qap_rlt2.h"
+#include "kernels.hpp"
+
+using namespace qap;
+
+namespace {
+
+std::string g_init_error;
+
+size_t round_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct qap_ctx {
+    int n = 0, m = 0;
+    long long T = 0;
+    size_t Vz = 0;
+    qap_params prm{};
+    // host-derived constants, computed once in FP64
+    double kz = 0, okz = 0, phi = 0, ky2 = 0, kx3 = 0, oky = 0, okx = 0, phy = 0, ophy = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    // arena
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+    double *Z = nullptr, *U = nullptr, *V = nullptr, *Yc = nullptr, *Py = nullptr;
+    double *Xc = nullptr, *Px = nullptr, *alpha = nullptr, *beta = nullptr;
+    double *F = nullptr, *D = nullptr, *B = nullptr;
+    int *xperm = nullptr, *bestperm = nullptr, *triples = nullptr;
+    DevScalars *S = nullptr;
+    double *trace = nullptr;
+    int trace_cap = 0;
+    int ntriples = 0;
+    int t_host = 0;
+    bool integer_data = false;
+    int zl = 0, zc = 0;  // Z-LAP mapping
+    std::vector<double> hF, hD, hB;
+    std::string err;
+    hipGraphExec_t graph = nullptr;  // one full iteration (t >= 1)
+};
+
+namespace {
+
+int fail(qap_ctx *h, int code, const std::string &msg)
+{
+    if (h)
+        h->err = msg;
+    else
+        g_init_error = msg;
+    return code;
+}
+
+#define HIPCHK(h, call)                                                                       \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail((h), QAP_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_));   \
+    } while (0)
+
+bool finite_all(const double *a, int n)
+{
+    for (int i = 0; i < n * n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+bool integer_all(const double *a, int n)
+{
+    for (int i = 0; i < n * n; ++i) {
+        const double x = a[i];
+        if (!(std::fabs(x) < 9.0e15) || x != std::floor(x)) return false;
+    }
+    return true;
+}
+
+struct Sizes {
+    size_t z, u, yc, x, nn, trace, tri, total;
+};
+
+Sizes sizes_for(int n, int trace_cap)
+{
+    Sizes s{};
+    const long long T = (long long)n * n * (n - 1) * (n - 1);
+    const long long m = n - 2;
+    const long long ntri = (long long)n * (n - 1) * (n - 2) / 6;
+    s.z = round_up(sizeof(double) * (size_t)T * m * m);
+    s.u = round_up(sizeof(double) * (size_t)T * m);
+    s.yc = round_up(sizeof(double) * (size_t)T);
+    s.x = round_up(sizeof(double) * (size_t)n * n);
+    s.nn = round_up(sizeof(double) * (size_t)n);
+    s.trace = round_up(sizeof(double) * (size_t)trace_cap);
+    s.tri = round_up(sizeof(int) * (size_t)std::max<long long>(ntri, 1));
+    s.total = s.z + 2 * s.u + 2 * s.yc + 5 * s.x + 2 * s.nn + 3 * round_up(sizeof(int) * n) + s.tri +
+              round_up(sizeof(DevScalars));
+    return s;
+}
+
+bool params_ok(const qap_params &p)
+{
+    auto in01 = [](double x) { return std::isfinite(x) && x >= 0.0 && x <= 1.0; };
+    return in01(p.kappa_z) && in01(p.kappa_y) && in01(p.kappa_x) && in01(p.phi_z) && in01(p.phi_y) &&
+           std::fabs(5.0 * p.phi_z - 1.0) < 1e-12 && std::isfinite(p.min_gap) && p.min_gap >= 0.0;
+}
+
+// Z-LAP lane mapping for size m (lanes per LAP, columns per lane).
+void pick_zlap(int m, int req_l, int req_c, int &L, int &C)
+{
+    if (req_l > 0 && req_c > 0 && req_l * req_c >= m) {
+        L = req_l;
+        C = req_c;
+        return;
+    }
+    C = 1;
+    L = m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 64;
+}
+
+template <int L, int C>
+hipError_t launch_zlap_t(qap_ctx *h)
+{
+    const int m = h->m;
+    const size_t per = (size_t)m * m * sizeof(double);
+    int G = 256 / L;
+    while (G > 1 && (size_t)G * per > 65536) --G;
+    const long long blocks = (h->T + G - 1) / G;
+    hipLaunchKernelGGL((k_zlap<L, C>), dim3((unsigned)blocks), dim3(G * L), G * per, h->stream, h->Z,
+                       h->U, h->V, h->Yc, m, h->T, h->S);
+    return hipGetLastError();
+}
+
+hipError_t launch_zlap(qap_ctx *h)
+{
+    const int L = h->zl, C = h->zc;
+    if (L == 8 && C == 1) return launch_zlap_t<8, 1>(h);
+    if (L == 16 && C == 1) return launch_zlap_t<16, 1>(h);
+    if (L == 32 && C == 1) return launch_zlap_t<32, 1>(h);
+    if (L == 64 && C == 1) return launch_zlap_t<64, 1>(h);
+    if (L == 8 && C == 2) return launch_zlap_t<8, 2>(h);
+    if (L == 16 && C == 2) return launch_zlap_t<16, 2>(h);
+    if (L == 32 && C == 2) return launch_zlap_t<32, 2>(h);
+    return hipErrorInvalidValue;
+}
+
+template <int L, int C>
+hipError_t launch_ylap_t(qap_ctx *h, int equalize)
+{
+    const int n = h->n, m = n - 1;
+    const size_t per = ((size_t)m * m + 2 * m) * sizeof(double);
+    int G = 256 / L;
+    while (G > 1 && (size_t)G * per > 65536) --G;
+    const int blocks = (n * n + G - 1) / G;
+    hipLaunchKernelGGL((k_ylap<L, C>), dim3(blocks), dim3(G * L), G * per, h->stream, h->Yc, h->Py,
+                       h->Xc, n, equalize, h->ophy, h->phy, h->S);
+    return hipGetLastError();
+}
+
+hipError_t launch_ylap(qap_ctx *h, int equalize)
+{
+    const int m = h->n - 1;
+    if (m <= 8) return launch_ylap_t<8, 1>(h, equalize);
+    if (m <= 16) return launch_ylap_t<16, 1>(h, equalize);
+    if (m <= 32) return launch_ylap_t<32, 1>(h, equalize);
+    return launch_ylap_t<64, 1>(h, equalize);
+}
+
+hipError_t launch_iteration(qap_ctx *h, int t)
+{
+    hipError_t e;
+    if (t >= 1) {
+        SweepConsts K{h->kz, h->okz, h->ky2, h->kx3, h->phi};
+        const unsigned groups8 = (unsigned)((h->ntriples + 7) / 8);
+        const unsigned blocks = groups8 * 8u * (unsigned)h->n;
+        hipLaunchKernelGGL(k_sweep, dim3(blocks), dim3(256), 0, h->stream, h->Z, h->U, h->V, h->Py,
+                           h->Px, h->triples, h->ntriples, h->n, K, h->S);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const long long work = std::max<long long>(h->T, (long long)h->n * h->n);
+        const unsigned sb = (unsigned)std::min<long long>((work + 255) / 256, 65535);
+        hipLaunchKernelGGL(k_scale_xy, dim3(sb), dim3(256), 0, h->stream, h->Yc, h->Py, h->Xc, h->Px,
+                           h->T, h->n * h->n, h->oky, h->okx, h->S);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = launch_zlap(h)) != hipSuccess) return e;
+    if ((e = launch_ylap(h, t >= 1 ? 1 : 0)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_xlap, dim3(1), dim3(64), 0, h->stream, h->Xc, h->Px, h->alpha, h->beta, h->F,
+                       h->D, h->B, h->xperm, h->bestperm, h->trace, h->n, h->prm.min_gap, h->S);
+    return hipGetLastError();
+}
+
+int ensure_trace(qap_ctx *h, int need)
+{
+    if (need <= h->trace_cap) return QAP_OK;
+    int cap = std::max(need, 2 * h->trace_cap);
+    double *nt = nullptr;
+    HIPCHK(h, hipMalloc(&nt, sizeof(double) * cap));
+    if (h->trace) {
+        HIPCHK(h, hipMemcpyAsync(nt, h->trace, sizeof(double) * h->trace_cap, hipMemcpyDeviceToDevice,
+                                 h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        HIPCHK(h, hipFree(h->trace));
+    }
+    h->trace = nt;
+    h->trace_cap = cap;
+    if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    return QAP_OK;
+}
+
+void derive_constants(qap_ctx *h)
+{
+    const int n = h->n;
+    const double c2 = 1.0 / (double)(n - 2);
+    const double c3 = 1.0 / ((double)(n - 1) * (double)(n - 2));
+    h->kz = h->prm.kappa_z;
+    h->okz = 1.0 - h->prm.kappa_z;
+    h->oky = 1.0 - h->prm.kappa_y;
+    h->okx = 1.0 - h->prm.kappa_x;
+    h->ky2 = h->prm.kappa_y * c2;
+    h->kx3 = h->prm.kappa_x * c3;
+    h->phi = h->prm.phi_z;
+    h->phy = h->prm.phi_y;
+    h->ophy = 1.0 - h->prm.phi_y;
+}
+
+int upload_initial(qap_ctx *h)
+{
+    const int n = h->n;
+    const int nn = n * n;
+    HIPCHK(h, hipMemcpyAsync(h->F, h->hF.data(), sizeof(double) * nn, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->D, h->hD.data(), sizeof(double) * nn, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->B, h->hB.data(), sizeof(double) * nn, hipMemcpyHostToDevice, h->stream));
+    const unsigned fb = 4096;
+    hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, h->stream, h->Z, h->Vz, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, h->stream, h->U, (size_t)h->T * h->m, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, h->stream, h->V, (size_t)h->T * h->m, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, h->stream, h->Py, (size_t)h->T, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, h->stream, h->Px, (size_t)nn, 0.0);
+    hipLaunchKernelGGL(k_init_xy, dim3(std::min<long long>((h->T + 255) / 256, 65535)), dim3(256), 0,
+                       h->stream, h->F, h->D, h->B, h->Xc, h->Yc, n);
+    HIPCHK(h, hipGetLastError());
+    DevScalars s{};
+    s.lb = 0.0;
+    s.ub = HUGE_VAL;
+    s.t = 0;
+    s.proven = 0;
+    s.integer_data = h->integer_data ? 1 : 0;
+    s.stopped = 0;
+    s.steps = 0;
+    HIPCHK(h, hipMemcpyAsync(h->S, &s, sizeof(s), hipMemcpyHostToDevice, h->stream));
+    std::vector<int> ident(n);
+    for (int i = 0; i < n; ++i) ident[i] = i;
+    HIPCHK(h, hipMemcpyAsync(h->bestperm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->xperm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->t_host = 0;
+    return QAP_OK;
+}
+
+uint64_t fnv1a(uint64_t hsh, const void *data, size_t bytes)
+{
+    const unsigned char *p = (const unsigned char *)data;
+    for (size_t i = 0; i < bytes; ++i) {
+        hsh ^= p[i];
+        hsh *= 1099511628211ull;
+    }
+    return hsh;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *qap_version(void) { return "qap-rlt2-mi355x 0.1 (gfx950, F1 FULL)"; }
+
+int qap_default_params(qap_params *p)
+{
+    if (!p) return QAP_EINVAL;
+    std::memset(p, 0, sizeof(*p));
+    p->kappa_z = 5.0 / 6.0;
+    p->kappa_y = 1.0;
+    p->kappa_x = 1.0;
+    p->phi_z = 1.0 / 5.0;
+    p->phi_y = 0.5;
+    p->min_gap = 0.0;
+    return QAP_OK;
+}
+
+size_t qap_workspace_bytes(int n, const qap_params *p)
+{
+    (void)p;
+    if (n < 3 || n > 64) return 0;
+    return sizes_for(n, 1024).total + round_up(sizeof(double) * 1024);
+}
+
+int qap_rlt2_init(const double *F, const double *D, const double *B, int n, const qap_params *p,
+                  qap_handle *out)
+{
+    if (!out) return fail(nullptr, QAP_EINVAL, "out is NULL");
+    if (n < 3 || n > 64) return fail(nullptr, QAP_EUNSUPPORTED, "n must be in 3..64");
+    if (!F || !D) return fail(nullptr, QAP_EINVAL, "F and D are required");
+    if (!finite_all(F, n) || !finite_all(D, n) || (B && !finite_all(B, n)))
+        return fail(nullptr, QAP_EINVAL, "non-finite input entry");
+    qap_params prm;
+    if (p)
+        prm = *p;
+    else
+        qap_default_params(&prm);
+    if (!params_ok(prm)) return fail(nullptr, QAP_EINVAL, "kappa/phi outside [0,1] or 5*phi_z != 1");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(nullptr, QAP_EDEVICE, "no HIP device");
+    if (prm.device < 0 || prm.device >= ndev) return fail(nullptr, QAP_EINVAL, "bad device ordinal");
+    if (hipSetDevice(prm.device) != hipSuccess) return fail(nullptr, QAP_EDEVICE, "hipSetDevice failed");
+
+    const int trace_cap = 1024;
+    Sizes sz = sizes_for(n, trace_cap);
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) return fail(nullptr, QAP_EDEVICE, "hipMemGetInfo failed");
+    if (sz.total + sz.trace > freeb) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "arena of %zu bytes exceeds free device memory (%zu)", sz.total + sz.trace,
+                      freeb);
+        return fail(nullptr, QAP_ENOMEM, buf);
+    }
+
+    qap_ctx *h = new qap_ctx();
+    h->n = n;
+    h->m = n - 2;
+    h->T = (long long)n * n * (n - 1) * (n - 1);
+    h->Vz = (size_t)h->T * h->m * h->m;
+    h->prm = prm;
+    h->hF.assign(F, F + n * n);
+    h->hD.assign(D, D + n * n);
+    h->hB.assign(n * n, 0.0);
+    if (B) h->hB.assign(B, B + n * n);
+    h->integer_data = integer_all(F, n) && integer_all(D, n) && integer_all(h->hB.data(), n);
+    derive_constants(h);
+    pick_zlap(h->m, prm.zlap_lanes, prm.zlap_cols, h->zl, h->zc);
+
+    auto cleanup = [&](int code) {
+        qap_destroy(h);
+        return code;
+    };
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete h;
+        return fail(nullptr, QAP_EDEVICE, "stream creation failed");
+    }
+    h->own_stream = true;
+    h->arena_bytes = sz.total;
+    void *mem = nullptr;
+    if (prm.alloc)
+        mem = prm.alloc(h->arena_bytes, prm.alloc_ctx);
+    else if (hipMalloc(&mem, h->arena_bytes) != hipSuccess)
+        mem = nullptr;
+    if (!mem) {
+        g_init_error = "device arena allocation failed";
+        return cleanup(QAP_ENOMEM);
+    }
+    h->arena = mem;
+    char *c = (char *)mem;
+    auto take = [&](size_t bytes) {
+        char *r = c;
+        c += bytes;
+        return (void *)r;
+    };
+    h->Z = (double *)take(sz.z);
+    h->U = (double *)take(sz.u);
+    h->V = (double *)take(sz.u);
+    h->Yc = (double *)take(sz.yc);
+    h->Py = (double *)take(sz.yc);
+    h->Xc = (double *)take(sz.x);
+    h->Px = (double *)take(sz.x);
+    h->F = (double *)take(sz.x);
+    h->D = (double *)take(sz.x);
+    h->B = (double *)take(sz.x);
+    h->alpha = (double *)take(sz.nn);
+    h->beta = (double *)take(sz.nn);
+    h->xperm = (int *)take(round_up(sizeof(int) * n));
+    h->bestperm = (int *)take(round_up(sizeof(int) * n));
+    take(round_up(sizeof(int) * n));
+    h->triples = (int *)take(sz.tri);
+    h->S = (DevScalars *)take(round_up(sizeof(DevScalars)));
+    if (hipMalloc(&h->trace, sizeof(double) * trace_cap) != hipSuccess) {
+        g_init_error = "trace allocation failed";
+        return cleanup(QAP_ENOMEM);
+    }
+    h->trace_cap = trace_cap;
+
+    // facility triples i<j<k, packed 8 bits each
+    std::vector<int> tri;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j)
+            for (int k = j + 1; k < n; ++k) tri.push_back(i | (j << 8) | (k << 16));
+    h->ntriples = (int)tri.size();
+    if (hipMemcpy(h->triples, tri.data(), sizeof(int) * tri.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        g_init_error = "upload failed";
+        return cleanup(QAP_EDEVICE);
+    }
+    int rc = upload_initial(h);
+    if (rc != QAP_OK) {
+        g_init_error = h->err;
+        return cleanup(rc);
+    }
+    *out = h;
+    return QAP_OK;
+}
+
+int qap_destroy(qap_handle h)
+{
+    if (!h) return QAP_EINVAL;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    if (h->arena) {
+        if (h->prm.alloc && h->prm.free_fn)
+            h->prm.free_fn(h->arena, h->prm.alloc_ctx);
+        else if (!h->prm.alloc)
+            (void)hipFree(h->arena);
+    }
+    if (h->trace) (void)hipFree(h->trace);
+    if (h->stream && h->own_stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return QAP_OK;
+}
+
+int qap_set_stream(qap_handle h, void *hip_stream)
+{
+    if (!h) return QAP_EINVAL;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (h->own_stream) (void)hipStreamDestroy(h->stream);
+    h->stream = (hipStream_t)hip_stream;
+    h->own_stream = false;
+    if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    return QAP_OK;
+}
+
+int qap_dual_ascent(qap_handle h, int iters, double *lb_out, double *alpha_out, double *beta_out,
+                    qap_da_stats *st)
+{
+    if (!h) return QAP_EINVAL;
+    if (iters < 0) return fail(h, QAP_EINVAL, "iters < 0");
+    HIPCHK(h, hipSetDevice(h->prm.device));
+    auto t0 = std::chrono::steady_clock::now();
+    DevScalars before{};
+    HIPCHK(h, hipMemcpyAsync(&before, h->S, sizeof(before), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->t_host = before.t;
+    int rc = ensure_trace(h, h->t_host + iters + 1);
+    if (rc != QAP_OK) return rc;
+    for (int it = 0; it < iters; ++it) {
+        const int t = h->t_host + it;
+        if (t >= 1) {
+            if (!h->graph) {
+                hipGraph_t g = nullptr;
+                HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+                hipError_t le = launch_iteration(h, 1);
+                hipError_t ce = hipStreamEndCapture(h->stream, &g);
+                if (le != hipSuccess) return fail(h, QAP_EDEVICE, std::string("launch: ") + hipGetErrorString(le));
+                if (ce != hipSuccess) return fail(h, QAP_EDEVICE, std::string("capture: ") + hipGetErrorString(ce));
+                hipError_t ie = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (ie != hipSuccess) return fail(h, QAP_EDEVICE, std::string("instantiate: ") + hipGetErrorString(ie));
+            }
+            HIPCHK(h, hipGraphLaunch(h->graph, h->stream));
+        } else {
+            hipError_t e = launch_iteration(h, t);
+            if (e != hipSuccess) return fail(h, QAP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+        }
+    }
+    DevScalars after{};
+    HIPCHK(h, hipMemcpyAsync(&after, h->S, sizeof(after), hipMemcpyDeviceToHost, h->stream));
+    std::vector<double> a(h->n), b(h->n);
+    HIPCHK(h, hipMemcpyAsync(a.data(), h->alpha, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(b.data(), h->beta, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    auto t1 = std::chrono::steady_clock::now();
+    h->t_host = after.t;
+    if (lb_out) *lb_out = after.lb;
+    if (alpha_out) std::memcpy(alpha_out, a.data(), sizeof(double) * h->n);
+    if (beta_out) std::memcpy(beta_out, b.data(), sizeof(double) * h->n);
+    if (st) {
+        st->iterations_done = after.t - before.t;
+        st->t = after.t;
+        st->lb = after.lb;
+        st->ub = after.ub;
+        st->gap = (after.ub < HUGE_VAL && after.ub != 0.0) ? (after.ub - after.lb) / std::fabs(after.ub) : HUGE_VAL;
+        st->proven = after.proven;
+        st->laps = (long long)st->iterations_done * (h->T + (long long)h->n * h->n + 1);
+        st->dijkstra_steps = (long long)(after.steps - before.steps);
+        st->seconds = std::chrono::duration<double>(t1 - t0).count();
+    }
+    return QAP_OK;
+}
+
+int qap_get_trace(qap_handle h, double *lb, int cap, int *len)
+{
+    if (!h) return QAP_EINVAL;
+    DevScalars s{};
+    HIPCHK(h, hipMemcpyAsync(&s, h->S, sizeof(s), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (len) *len = s.t;
+    const int k = std::min(cap, s.t);
+    if (lb && k > 0) {
+        HIPCHK(h, hipMemcpyAsync(lb, h->trace, sizeof(double) * k, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    return QAP_OK;
+}
+
+int qap_get_assignment(qap_handle h, int32_t *xperm, int32_t *best_perm)
+{
+    if (!h) return QAP_EINVAL;
+    if (xperm) HIPCHK(h, hipMemcpyAsync(xperm, h->xperm, sizeof(int) * h->n, hipMemcpyDeviceToHost, h->stream));
+    if (best_perm)
+        HIPCHK(h, hipMemcpyAsync(best_perm, h->bestperm, sizeof(int) * h->n, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return QAP_OK;
+}
+
+int qap_export_state(qap_handle h, qap_state_header *hdr, double *x, double *y, double *z)
+{
+    if (!h) return QAP_EINVAL;
+    DevScalars s{};
+    HIPCHK(h, hipMemcpyAsync(&s, h->S, sizeof(s), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    const int n = h->n, m = h->m;
+    const size_t nn = (size_t)n * n;
+    std::vector<double> hx(nn), hy((size_t)h->T), hz;
+    const bool post = s.t > 0;
+    HIPCHK(h, hipMemcpy(hx.data(), post ? h->Px : h->Xc, sizeof(double) * nn, hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(hy.data(), post ? h->Py : h->Yc, sizeof(double) * h->T, hipMemcpyDeviceToHost));
+    uint64_t cs = 1469598103934665603ull;
+    if (z || hdr) {
+        hz.resize(h->Vz);
+        HIPCHK(h, hipMemcpy(hz.data(), h->Z, sizeof(double) * h->Vz, hipMemcpyDeviceToHost));
+        if (post) {
+            std::vector<double> hu((size_t)h->T * m), hv((size_t)h->T * m);
+            HIPCHK(h, hipMemcpy(hu.data(), h->U, sizeof(double) * hu.size(), hipMemcpyDeviceToHost));
+            HIPCHK(h, hipMemcpy(hv.data(), h->V, sizeof(double) * hv.size(), hipMemcpyDeviceToHost));
+            const size_t mm = (size_t)m * m;
+            for (long long t = 0; t < h->T; ++t)
+                for (int r = 0; r < m; ++r)
+                    for (int c = 0; c < m; ++c) {
+                        const size_t a = (size_t)t * mm + (size_t)r * m + c;
+                        hz[a] = (hz[a] - hu[(size_t)t * m + r]) - hv[(size_t)t * m + c];
+                    }
+        }
+    }
+    if (hdr) {
+        hdr->n = n;
+        hdr->t = s.t;
+        hdr->lb = s.lb;
+        hdr->ub = s.ub;
+        cs = fnv1a(cs, &hdr->n, sizeof(int));
+        cs = fnv1a(cs, &hdr->t, sizeof(int));
+        cs = fnv1a(cs, &hdr->lb, sizeof(double));
+        cs = fnv1a(cs, &hdr->ub, sizeof(double));
+        cs = fnv1a(cs, hx.data(), sizeof(double) * hx.size());
+        cs = fnv1a(cs, hy.data(), sizeof(double) * hy.size());
+        cs = fnv1a(cs, hz.data(), sizeof(double) * hz.size());
+        hdr->checksum = cs;
+    }
+    if (x) std::memcpy(x, hx.data(), sizeof(double) * nn);
+    if (y) std::memcpy(y, hy.data(), sizeof(double) * hy.size());
+    if (z) std::memcpy(z, hz.data(), sizeof(double) * hz.size());
+    return QAP_OK;
+}
+
+int qap_export_z_tiles(qap_handle h, const int64_t *tiles, int count, double *out)
+{
+    if (!h || count < 0 || (count > 0 && (!tiles || !out))) return QAP_EINVAL;
+    DevScalars s{};
+    HIPCHK(h, hipMemcpyAsync(&s, h->S, sizeof(s), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    const int m = h->m;
+    const size_t mm = (size_t)m * m;
+    std::vector<double> hu(m), hv(m);
+    for (int a = 0; a < count; ++a) {
+        const int64_t t = tiles[a];
+        if (t < 0 || t >= h->T) return fail(h, QAP_EINVAL, "tile index out of range");
+        double *dst = out + (size_t)a * mm;
+        HIPCHK(h, hipMemcpy(dst, h->Z + (size_t)t * mm, sizeof(double) * mm, hipMemcpyDeviceToHost));
+        if (s.t > 0) {
+            HIPCHK(h, hipMemcpy(hu.data(), h->U + (size_t)t * m, sizeof(double) * m, hipMemcpyDeviceToHost));
+            HIPCHK(h, hipMemcpy(hv.data(), h->V + (size_t)t * m, sizeof(double) * m, hipMemcpyDeviceToHost));
+            for (int r = 0; r < m; ++r)
+                for (int c = 0; c < m; ++c) dst[(size_t)r * m + c] = (dst[(size_t)r * m + c] - hu[r]) - hv[c];
+        }
+    }
+    return QAP_OK;
+}
+
+int qap_import_state(qap_handle h, const qap_state_header *hdr, const double *x, const double *y,
+                     const double *z)
+{
+    if (!h || !hdr || !x || !y || !z) return QAP_EINVAL;
+    if (hdr->n != h->n || hdr->t < 0) return fail(h, QAP_ESTATE, "state header does not match the handle");
+    const size_t nn = (size_t)h->n * h->n;
+    uint64_t cs = 1469598103934665603ull;
+    cs = fnv1a(cs, &hdr->n, sizeof(int));
+    cs = fnv1a(cs, &hdr->t, sizeof(int));
+    cs = fnv1a(cs, &hdr->lb, sizeof(double));
+    cs = fnv1a(cs, &hdr->ub, sizeof(double));
+    cs = fnv1a(cs, x, sizeof(double) * nn);
+    cs = fnv1a(cs, y, sizeof(double) * h->T);
+    cs = fnv1a(cs, z, sizeof(double) * h->Vz);
+    if (cs != hdr->checksum) return fail(h, QAP_ESTATE, "state checksum mismatch");
+    const bool post = hdr->t > 0;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(post ? h->Px : h->Xc, x, sizeof(double) * nn, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(post ? h->Py : h->Yc, y, sizeof(double) * h->T, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->Z, z, sizeof(double) * h->Vz, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_fill, dim3(4096), dim3(256), 0, h->stream, h->U, (size_t)h->T * h->m, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(4096), dim3(256), 0, h->stream, h->V, (size_t)h->T * h->m, 0.0);
+    DevScalars s{};
+    HIPCHK(h, hipMemcpyAsync(&s, h->S, sizeof(s), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    s.lb = hdr->lb;
+    s.ub = hdr->ub;
+    s.t = hdr->t;
+    s.proven = 0;
+    s.stopped = 0;
+    HIPCHK(h, hipMemcpyAsync(h->S, &s, sizeof(s), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->t_host = hdr->t;
+    return QAP_OK;
+}
+
+int qap_lap_batch(const double *cost, int count, int m, double *u, double *v, double *theta,
+                  int32_t *row_of_col, int lanes, int cols, void *stream)
+{
+    if (m < 1 || m > 64 || count < 0) return fail(nullptr, QAP_EINVAL, "m must be 1..64, count >= 0");
+    if (count == 0) return QAP_OK;
+    if (!cost || !u || !v || !theta || !row_of_col) return fail(nullptr, QAP_EINVAL, "NULL pointer");
+    int L, C;
+    pick_zlap(m, lanes, cols, L, C);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t per = (size_t)m * m * sizeof(double);
+    int G = 256 / L;
+    while (G > 1 && (size_t)G * per > 65536) --G;
+    const unsigned blocks = (unsigned)((count + G - 1) / G);
+#define QAP_LB(LL, CC)                                                                                   \
+    if (L == LL && C == CC) {                                                                            \
+        hipLaunchKernelGGL((k_lap_batch<LL, CC>), dim3(blocks), dim3(G * LL), G * per, s, cost, count, m, \
+                           u, v, theta, (int *)row_of_col);                                              \
+    } else
+    QAP_LB(8, 1) QAP_LB(16, 1) QAP_LB(32, 1) QAP_LB(64, 1) QAP_LB(8, 2) QAP_LB(16, 2) QAP_LB(32, 2)
+    {
+        return fail(nullptr, QAP_EINVAL, "unsupported lanes/cols mapping");
+    }
+#undef QAP_LB
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(nullptr, QAP_EDEVICE, hipGetErrorString(e));
+    return QAP_OK;
+}
+
+int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, double *obj_out,
+                  qap_bnb_stats *st)
+{
+    (void)p;
+    (void)perm_out;
+    (void)obj_out;
+    (void)st;
+    if (!h) return QAP_EINVAL;
+    return fail(h, QAP_ESTATE, "branch-and-bound not available in this build");
+}
+
+const char *qap_last_error(qap_handle h)
+{
+    if (!h) return g_init_error.c_str();
+    return h->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+"""The C ABI library loads and exports every symbol include/qap_rlt2.h
+declares; argument validation that needs no device (CPU only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1710_03732_amd import binding as B
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "qap_rlt2.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qap_[a-z0-9_]+)\s*\(", src)) -
+                  {"qap_alloc_fn", "qap_free_fn"})
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(B.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(B.EXPORTED) == set(names)
+
+
+def test_version_and_defaults():
+    assert "gfx950" in B.version()
+    p = B.default_params()
+    assert p.kappa_z == 5.0 / 6.0 and p.kappa_y == 1.0 and p.kappa_x == 1.0
+    assert p.phi_z == 0.2 and p.phi_y == 0.5
+
+
+def test_workspace_bytes():
+    assert B.workspace_bytes(2) == 0 and B.workspace_bytes(65) == 0
+    w30 = B.workspace_bytes(30)
+    V = (30 * 29 * 28) ** 2
+    assert 8 * V < w30 < 8 * V * 1.1
+    assert B.workspace_bytes(42) < 288e9
+
+
+@pytest.mark.parametrize("n,code", [(2, -5), (65, -5)])
+def test_init_rejects_unsupported_n(n, code):
+    F = np.zeros((n, n))
+    with pytest.raises(B.QapError) as e:
+        B.DualAscent(F, F)
+    assert e.value.code == code
+
+
+def test_init_rejects_non_finite():
+    F = np.ones((5, 5))
+    F[1, 2] = np.nan
+    with pytest.raises(B.QapError) as e:
+        B.DualAscent(F, np.ones((5, 5)))
+    assert e.value.code == -1
+
+
+def test_init_rejects_bad_params():
+    F = np.ones((5, 5))
+    with pytest.raises(B.QapError) as e:
+        B.DualAscent(F, F, kappa_z=1.5)
+    assert e.value.code == -1
+    with pytest.raises(B.QapError) as e:
+        B.DualAscent(F, F, phi_z=0.3)
+    assert e.value.code == -1
+
+
+def test_lap_batch_rejects_bad_sizes():
+    lib = B.lib()
+    assert lib.qap_lap_batch(None, 1, 0, None, None, None, None, 0, 0, None) == -1
+    assert lib.qap_lap_batch(None, 1, 65, None, None, None, None, 0, 0, None) == -1
+    assert lib.qap_lap_batch(None, 0, 5, None, None, None, None, 0, 0, None) == 0

@@ -228,3 +228,28 @@ def test_sweep_pushes_x_and_y_slack_down():
             for e, m in enumerate(mem):
                 expect = 0.2 * (share.sum() - share[e])
                 assert abs(Z1[m] - expect) <= 1e-13 * share.sum()
+
+
+@pytest.mark.parametrize("inst", [I.grid_instance(7, 2, 4, 0.4, 1, 9, 1), I.random_instance(6, 77)],
+                         ids=lambda x: x.name)
+def test_sampled_iteration_paths_match_full_oracle(inst):
+    """The reduced paths used at n = 30/42 (iteration 0 without the zero z
+    level, single iteration-1 tiles built entry by entry) reproduce the full
+    dense oracle exactly."""
+    F, D, B = inst.arrays()
+    n = inst.n
+    full = O.DualAscent(F, D, B)
+    full.run(1)
+    X0, Y0, _ = full.export()
+    red = O.Iter0XY(F, D, B)
+    Xr, Yr = red.xy()
+    assert red.LB == full.LB and red.UB == full.UB
+    assert np.array_equal(Xr, X0) and np.array_equal(Yr, Y0)
+    full.sweep()
+    full.zphase()
+    _, _, Z1 = full.export()
+    for (i, j, p, q) in [(0, 1, 0, 1), (2, 0, 3, 1), (n - 1, n - 2, 0, n - 1), (1, 3, 4, 2)]:
+        M, pi, th = red.tile1(i, j, p, q)
+        ks = [k for k in range(n) if k not in (i, j)]
+        rs = [r for r in range(n) if r not in (p, q)]
+        assert np.array_equal(pi, np.array([[Z1[i, j, k, p, q, r] for r in rs] for k in ks]))
