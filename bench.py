@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark: F1 RLT2 dual-ascent iterations/s and LAPs/s on one MI355X.
+
+Workload (default): the n = 30 root dual ascent of a dense symmetric QAP,
+F and D ~ U{0..99} with zero diagonals, seed 0 (synthetic stand-in for the
+Taillard-a family); FULL scheme, all n^2 (n-1)^2 = 756,900 Z-LAPs of size 28,
+900 Y-LAPs of size 29 and one X-LAP of size 30 per iteration, FP64.
+
+A step is one dual-ascent iteration (ascent sweep over the 593.4 M-entry z
+array, Z-, Y- and X-LAPs).  W warmup iterations (including iteration 0, whose
+z level is zero) run first; the K timed iterations are bracketed by
+torch.cuda.synchronize() and the library's kernels run on torch's current
+stream, each phase between HIP events recorded on that stream.
+
+Prints one JSON line.  `roofline` is for the kernel with the largest device
+time; its `achieved` is algorithmic bytes per launch / average launch time.
+`cpu_baseline` times the CPU oracle (all OpenMP threads) on one iteration of
+the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def algorithmic_bytes(n: int) -> dict:
+    """Minimal HBM bytes per launch of each phase (FP64, compact layout)."""
+    m = n - 2
+    T = n * n * (n - 1) * (n - 1)
+    V = T * m * m
+    nn = n * n
+    return {
+        # reads the z array and Theta, writes xi/psi (2 T m) and Theta
+        "zlap": 8 * (V + 2 * T * m + 2 * T),
+        # reads and writes the z array, reads xi/psi, pi_y, pi_x; the x/y
+        # scaling reads pi_y and writes R_y
+        "sweep": 8 * (2 * V + 2 * T * m + T + nn) + 8 * (2 * T + 2 * nn),
+        # reads R_y and its partner entries, writes pi_y, updates R_x
+        "ylap": 8 * (3 * T + 2 * nn),
+        "xlap": 8 * (5 * nn),
+    }
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for name in ("lap_wave.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1710_03732_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, launches_bytes: int):
+    """HBM traffic of the dominant kernel from the committed rocprofv3 PMC
+    summary (FETCH_SIZE / WRITE_SIZE scaled by the copy-kernel factor), or None
+    when the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("bytes_per_launch")
+
+
+def cpu_baseline(inst, threads: int | None):
+    from oracle import oracle as O
+
+    if threads:
+        O.set_threads(threads)
+    used = O.max_threads()
+    F, D, B = inst.arrays()
+    cpu = O.DualAscent(F, D, B)
+    cpu.run(1)  # iteration 0 (z level zero), untimed
+    t0 = time.perf_counter()
+    cpu.run(1)  # iteration 1: sweep + all Z/Y/X LAPs
+    el = time.perf_counter() - t0
+    return {"value": 1.0 / el, "unit": "iterations/s", "cores": used, "kind": "oracle",
+            "sample": f"one full F1 iteration (t=1: ascent sweep and all Z/Y/X LAPs) of the "
+                      f"{inst.name} workload after iteration 0, {el:.2f} s on {used} threads",
+            "seconds": el, "lb_after": cpu.LB}
+
+
+def calibrate_copy(nbytes: int = 1 << 31):
+    """A plain device copy of known size, for scaling PMC byte counters."""
+    import torch
+
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return nbytes
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="dense_n30",
+                    help="dense_n30 | grid_n30 | dense_n42 | grid_n15 | ...")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--zlap-lanes", type=int, default=0)
+    ap.add_argument("--zlap-cols", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 2 GiB device copy (PMC counter calibration)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); the multi-GPU "
+              "design is described in DESIGN.md and not built", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1710_03732_amd import binding, instances
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    inst = instances.named(args.workload)
+    F, D, B = inst.arrays()
+    n = inst.n
+    m = n - 2
+    T = n * n * (n - 1) * (n - 1)
+    V = T * m * m
+    laps_per_iter = T + n * n + 1
+
+    if args.calibrate_copy:
+        calibrate_copy()
+
+    stream = torch.cuda.current_stream()
+    da = binding.DualAscent(F, D, B, timing=1, zlap_lanes=args.zlap_lanes,
+                            zlap_cols=args.zlap_cols)
+    da.set_stream(stream.cuda_stream)
+    if args.warmup > 0:
+        da.run(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = da.run(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    done = r["iterations_done"]
+    if done <= 0:
+        print("bench.py: the bound proved optimality during warmup; nothing timed",
+              file=sys.stderr)
+        return 1
+    its = done / el
+    phase_ms = {"sweep": r["ms_sweep"] / done, "zlap": r["ms_zlap"] / done,
+                "ylap": r["ms_ylap"] / done, "xlap": r["ms_xlap"] / done}
+    ab = algorithmic_bytes(n)
+    dom = max(("zlap", "sweep"), key=lambda k: phase_ms[k])
+    dom_s = phase_ms[dom] / 1e3
+    achieved = ab[dom] / dom_s / 1e9
+    traffic = load_traffic(dom, ab[dom])
+    iter_bytes = sum(ab.values())
+    steps_per_zlap = r["dijkstra_steps"] / max(1, done * laps_per_iter)
+
+    out = {
+        "metric": "RLT2 dual-ascent iters/s + LAPs/s at n=30 FP64; time-to-bound warm vs cold",
+        "value": its,
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / done,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{inst.name}: QAP n={n} root dual ascent, "
+                        + ("dense symmetric F,D~U{0..99}, zero diagonals, seed 0"
+                           if inst.name.startswith("dense") else "grid Manhattan D, sparse flows")
+                        + "; F1 one-phase RLT2-DA, FULL scheme (all Z-LAPs)",
+            "n": n,
+            "z_laps_per_iter": T,
+            "laps_per_iter": laps_per_iter,
+            "z_entries": V,
+            "zlap_mapping": f"{da.params.zlap_lanes or 'auto'}x{da.params.zlap_cols or 'auto'}",
+        },
+        "laps_per_s": its * laps_per_iter,
+        "iterations_done": done,
+        "phase_ms_per_iter": phase_ms,
+        "lb_after": r["lb"],
+        "ub": r["ub"],
+        "gap": r["gap"],
+        "dijkstra_steps_per_lap": steps_per_zlap,
+        "iteration_hbm": {"bytes": iter_bytes, "achieved_gbs": iter_bytes / (el / done) / 1e9,
+                          "frac": iter_bytes / (el / done) / 1e9 / HBM_PEAK_GBS},
+        "roofline": {"bound": "hbm", "kernel": {"zlap": "k_zlap", "sweep": "k_sweep+k_scale_xy"}[dom],
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": ab[dom],
+                     "avg_launch_ms": phase_ms[dom]},
+        "time_to_bound": None,
+        "cpu_baseline": None,
+    }
+    da.close()
+    if not args.no_cpu_baseline:
+        torch.cuda.synchronize()
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_threads or None)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

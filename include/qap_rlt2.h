@@ -71,7 +71,9 @@ typedef struct qap_params {
     int device;            /* HIP device ordinal */
     int zlap_lanes;        /* Z-LAP lanes per LAP (8/16/32/64); 0 = autotuned */
     int zlap_cols;         /* columns per lane (1/2); 0 = autotuned */
-    int reserved_i;
+    int timing;            /* 1: launch each kernel between HIP events on the
+                              handle's stream and report per-phase device time
+                              in qap_da_stats (no graph replay) */
     qap_alloc_fn alloc;    /* optional device allocator */
     qap_free_fn free_fn;
     void *alloc_ctx;
@@ -88,6 +90,10 @@ typedef struct qap_da_stats {
     long long laps;        /* LAPs solved by this call: iters*(T + n^2 + 1) */
     long long dijkstra_steps; /* Dijkstra steps of all LAPs of this call */
     double seconds;        /* wall time of the call (device-synchronised) */
+    double ms_sweep;       /* with params.timing: summed device milliseconds of */
+    double ms_zlap;        /* the ascent sweep (+x/y scaling), the Z-LAP kernel, */
+    double ms_ylap;        /* the Y-LAP kernel and the X-LAP kernel over the call */
+    double ms_xlap;
 } qap_da_stats;
 
 typedef struct qap_bnb_params {

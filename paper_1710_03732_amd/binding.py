@@ -27,14 +27,16 @@ class QapParams(C.Structure):
     _fields_ = [("kappa_z", C.c_double), ("kappa_y", C.c_double), ("kappa_x", C.c_double),
                 ("phi_z", C.c_double), ("phi_y", C.c_double), ("min_gap", C.c_double),
                 ("device", C.c_int), ("zlap_lanes", C.c_int), ("zlap_cols", C.c_int),
-                ("reserved_i", C.c_int), ("alloc", _alloc_fn), ("free_fn", _free_fn),
+                ("timing", C.c_int), ("alloc", _alloc_fn), ("free_fn", _free_fn),
                 ("alloc_ctx", C.c_void_p)]
 
 
 class QapDaStats(C.Structure):
     _fields_ = [("iterations_done", C.c_int), ("t", C.c_int), ("lb", C.c_double),
                 ("ub", C.c_double), ("gap", C.c_double), ("proven", C.c_int), ("pad", C.c_int),
-                ("laps", C.c_longlong), ("dijkstra_steps", C.c_longlong), ("seconds", C.c_double)]
+                ("laps", C.c_longlong), ("dijkstra_steps", C.c_longlong), ("seconds", C.c_double),
+                ("ms_sweep", C.c_double), ("ms_zlap", C.c_double), ("ms_ylap", C.c_double),
+                ("ms_xlap", C.c_double)]
 
 
 class QapBnbParams(C.Structure):
@@ -172,7 +174,9 @@ class DualAscent:
                                      C.byref(st)), self.h)
         return {"lb": lb.value, "alpha": alpha, "beta": beta, "iterations_done": st.iterations_done,
                 "t": st.t, "ub": st.ub, "gap": st.gap, "proven": bool(st.proven), "laps": st.laps,
-                "dijkstra_steps": st.dijkstra_steps, "seconds": st.seconds}
+                "dijkstra_steps": st.dijkstra_steps, "seconds": st.seconds,
+                "ms_sweep": st.ms_sweep, "ms_zlap": st.ms_zlap, "ms_ylap": st.ms_ylap,
+                "ms_xlap": st.ms_xlap}
 
     def trace(self):
         n = C.c_int(0)

@@ -39,10 +39,11 @@ struct qap_ctx {
     // arena
     void *arena = nullptr;
     size_t arena_bytes = 0;
-    double *Z = nullptr, *U = nullptr, *V = nullptr, *Yc = nullptr, *Py = nullptr;
+    double *Z = nullptr, *Yc = nullptr, *Py = nullptr;
     double *Xc = nullptr, *Px = nullptr, *alpha = nullptr, *beta = nullptr;
     double *F = nullptr, *D = nullptr, *B = nullptr;
     int *xperm = nullptr, *bestperm = nullptr, *triples = nullptr;
+    unsigned long long *bins = nullptr;  // Dijkstra-step counters
     DevScalars *S = nullptr;
     double *trace = nullptr;
     int trace_cap = 0;
@@ -50,6 +51,7 @@ struct qap_ctx {
     int t_host = 0;
     bool integer_data = false;
     int zl = 0, zc = 0;  // Z-LAP mapping
+    int zlap_waves = 1;  // waves per Z-LAP block
     std::vector<double> hF, hD, hB;
     std::string err;
     hipGraphExec_t graph = nullptr;  // one full iteration (t >= 1)
@@ -106,8 +108,8 @@ Sizes sizes_for(int n, int trace_cap)
     s.nn = round_up(sizeof(double) * (size_t)n);
     s.trace = round_up(sizeof(double) * (size_t)trace_cap);
     s.tri = round_up(sizeof(int) * (size_t)std::max<long long>(ntri, 1));
-    s.total = s.z + 2 * s.u + 2 * s.yc + 5 * s.x + 2 * s.nn + 3 * round_up(sizeof(int) * n) + s.tri +
-              round_up(sizeof(DevScalars));
+    s.total = s.z + 2 * s.yc + 5 * s.x + 2 * s.nn + 3 * round_up(sizeof(int) * n) + s.tri +
+              round_up(sizeof(DevScalars)) + round_up(sizeof(unsigned long long) * kStepBins);
     return s;
 }
 
@@ -121,31 +123,50 @@ bool params_ok(const qap_params &p)
 // Z-LAP lane mapping for size m (lanes per LAP, columns per lane).
 void pick_zlap(int m, int req_l, int req_c, int &L, int &C)
 {
+    if ((req_l == -2 && m <= 32) || req_l == -1) {
+        L = req_l;
+        C = 1;
+        return;
+    }
     if (req_l > 0 && req_c > 0 && req_l * req_c >= m) {
         L = req_l;
         C = req_c;
         return;
     }
+    // small LAPs: 8/16-lane groups; otherwise the scalar-controlled solver
+    // with one 64-lane LAP per wavefront
     C = 1;
-    L = m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 64;
+    L = m <= 8 ? 8 : m <= 16 ? 16 : -1;
 }
 
 template <int L, int C>
 hipError_t launch_zlap_t(qap_ctx *h)
 {
     const int m = h->m;
-    const size_t per = (size_t)m * m * sizeof(double);
-    int G = 256 / L;
-    while (G > 1 && (size_t)G * per > 65536) --G;
+    const size_t per = ((size_t)m * m + 2 * m) * sizeof(double);
+    const int G = h->zlap_waves * (64 / L);  // whole waves per block
     const long long blocks = (h->T + G - 1) / G;
     hipLaunchKernelGGL((k_zlap<L, C>), dim3((unsigned)blocks), dim3(G * L), G * per, h->stream, h->Z,
-                       h->U, h->V, h->Yc, m, h->T, h->S);
+                       h->Yc, m, h->T, h->S, h->bins);
+    return hipGetLastError();
+}
+
+template <int H>
+hipError_t launch_zlap_s(qap_ctx *h)
+{
+    const int m = h->m;
+    const size_t per = ((size_t)m * m + 2 * m) * sizeof(double) * H;
+    const long long blocks = (h->T + H - 1) / H;
+    hipLaunchKernelGGL((k_zlap_s<H>), dim3((unsigned)blocks), dim3(64), per, h->stream, h->Z, h->Yc, m,
+                       h->T, h->S, h->bins);
     return hipGetLastError();
 }
 
 hipError_t launch_zlap(qap_ctx *h)
 {
     const int L = h->zl, C = h->zc;
+    if (L == -2) return launch_zlap_s<2>(h);
+    if (L == -1) return launch_zlap_s<1>(h);
     if (L == 8 && C == 1) return launch_zlap_t<8, 1>(h);
     if (L == 16 && C == 1) return launch_zlap_t<16, 1>(h);
     if (L == 32 && C == 1) return launch_zlap_t<32, 1>(h);
@@ -153,6 +174,8 @@ hipError_t launch_zlap(qap_ctx *h)
     if (L == 8 && C == 2) return launch_zlap_t<8, 2>(h);
     if (L == 16 && C == 2) return launch_zlap_t<16, 2>(h);
     if (L == 32 && C == 2) return launch_zlap_t<32, 2>(h);
+    if (L == 8 && C == 4) return launch_zlap_t<8, 4>(h);
+    if (L == 16 && C == 4) return launch_zlap_t<16, 4>(h);
     return hipErrorInvalidValue;
 }
 
@@ -165,7 +188,7 @@ hipError_t launch_ylap_t(qap_ctx *h, int equalize)
     while (G > 1 && (size_t)G * per > 65536) --G;
     const int blocks = (n * n + G - 1) / G;
     hipLaunchKernelGGL((k_ylap<L, C>), dim3(blocks), dim3(G * L), G * per, h->stream, h->Yc, h->Py,
-                       h->Xc, n, equalize, h->ophy, h->phy, h->S);
+                       h->Xc, n, equalize, h->ophy, h->phy, h->S, h->bins);
     return hipGetLastError();
 }
 
@@ -174,19 +197,20 @@ hipError_t launch_ylap(qap_ctx *h, int equalize)
     const int m = h->n - 1;
     if (m <= 8) return launch_ylap_t<8, 1>(h, equalize);
     if (m <= 16) return launch_ylap_t<16, 1>(h, equalize);
-    if (m <= 32) return launch_ylap_t<32, 1>(h, equalize);
-    return launch_ylap_t<64, 1>(h, equalize);
+    if (m <= 32) return launch_ylap_t<16, 2>(h, equalize);
+    return launch_ylap_t<16, 4>(h, equalize);
 }
 
-hipError_t launch_iteration(qap_ctx *h, int t)
+hipError_t launch_sweep(qap_ctx *h)
 {
     hipError_t e;
-    if (t >= 1) {
+    {
         SweepConsts K{h->kz, h->okz, h->ky2, h->kx3, h->phi};
         const unsigned groups8 = (unsigned)((h->ntriples + 7) / 8);
-        const unsigned blocks = groups8 * 8u * (unsigned)h->n;
-        hipLaunchKernelGGL(k_sweep, dim3(blocks), dim3(256), 0, h->stream, h->Z, h->U, h->V, h->Py,
-                           h->Px, h->triples, h->ntriples, h->n, K, h->S);
+        const int nb = (h->n + SB - 1) / SB;
+        const unsigned blocks = groups8 * 8u * (unsigned)(nb * nb * nb);
+        hipLaunchKernelGGL(k_sweep, dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py, h->Px,
+                           h->triples, h->ntriples, h->n, nb, K, h->S);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const long long work = std::max<long long>(h->T, (long long)h->n * h->n);
         const unsigned sb = (unsigned)std::min<long long>((work + 255) / 256, 65535);
@@ -194,11 +218,38 @@ hipError_t launch_iteration(qap_ctx *h, int t)
                            h->T, h->n * h->n, h->oky, h->okx, h->S);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = launch_zlap(h)) != hipSuccess) return e;
-    if ((e = launch_ylap(h, t >= 1 ? 1 : 0)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+hipError_t launch_xlap(qap_ctx *h)
+{
     hipLaunchKernelGGL(k_xlap, dim3(1), dim3(64), 0, h->stream, h->Xc, h->Px, h->alpha, h->beta, h->F,
                        h->D, h->B, h->xperm, h->bestperm, h->trace, h->n, h->prm.min_gap, h->S);
     return hipGetLastError();
+}
+
+hipError_t launch_iteration(qap_ctx *h, int t)
+{
+    hipError_t e;
+    if (t >= 1 && (e = launch_sweep(h)) != hipSuccess) return e;
+    if ((e = launch_zlap(h)) != hipSuccess) return e;
+    if ((e = launch_ylap(h, t >= 1 ? 1 : 0)) != hipSuccess) return e;
+    return launch_xlap(h);
+}
+
+// Same launches with HIP events between the phases (on the handle's stream).
+hipError_t launch_iteration_timed(qap_ctx *h, int t, hipEvent_t *ev)
+{
+    hipError_t e;
+    if ((e = hipEventRecord(ev[0], h->stream)) != hipSuccess) return e;
+    if (t >= 1 && (e = launch_sweep(h)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev[1], h->stream)) != hipSuccess) return e;
+    if ((e = launch_zlap(h)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev[2], h->stream)) != hipSuccess) return e;
+    if ((e = launch_ylap(h, t >= 1 ? 1 : 0)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev[3], h->stream)) != hipSuccess) return e;
+    if ((e = launch_xlap(h)) != hipSuccess) return e;
+    return hipEventRecord(ev[4], h->stream);
 }
 
 int ensure_trace(qap_ctx *h, int need)
@@ -247,10 +298,9 @@ int upload_initial(qap_ctx *h)
     HIPCHK(h, hipMemcpyAsync(h->B, h->hB.data(), sizeof(double) * nn, hipMemcpyHostToDevice, h->stream));
     const unsigned fb = 4096;
     hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, h->stream, h->Z, h->Vz, 0.0);
-    hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, h->stream, h->U, (size_t)h->T * h->m, 0.0);
-    hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, h->stream, h->V, (size_t)h->T * h->m, 0.0);
     hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, h->stream, h->Py, (size_t)h->T, 0.0);
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, h->stream, h->Px, (size_t)nn, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(16), dim3(256), 0, h->stream, (double *)h->bins, (size_t)kStepBins, 0.0);
     hipLaunchKernelGGL(k_init_xy, dim3(std::min<long long>((h->T + 255) / 256, 65535)), dim3(256), 0,
                        h->stream, h->F, h->D, h->B, h->Xc, h->Yc, n);
     HIPCHK(h, hipGetLastError());
@@ -269,6 +319,19 @@ int upload_initial(qap_ctx *h)
     HIPCHK(h, hipMemcpyAsync(h->xperm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->t_host = 0;
+    return QAP_OK;
+}
+
+// Dijkstra steps so far: the binned counters of the Z/Y kernels plus the X-LAP's.
+int read_steps(qap_ctx *h, const DevScalars &s, unsigned long long &out)
+{
+    std::vector<unsigned long long> b(kStepBins);
+    HIPCHK(h, hipMemcpyAsync(b.data(), h->bins, sizeof(unsigned long long) * kStepBins, hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    unsigned long long tot = s.steps;
+    for (auto x : b) tot += x;
+    out = tot;
     return QAP_OK;
 }
 
@@ -380,8 +443,6 @@ int qap_rlt2_init(const double *F, const double *D, const double *B, int n, cons
         return (void *)r;
     };
     h->Z = (double *)take(sz.z);
-    h->U = (double *)take(sz.u);
-    h->V = (double *)take(sz.u);
     h->Yc = (double *)take(sz.yc);
     h->Py = (double *)take(sz.yc);
     h->Xc = (double *)take(sz.x);
@@ -396,6 +457,7 @@ int qap_rlt2_init(const double *F, const double *D, const double *B, int n, cons
     take(round_up(sizeof(int) * n));
     h->triples = (int *)take(sz.tri);
     h->S = (DevScalars *)take(round_up(sizeof(DevScalars)));
+    h->bins = (unsigned long long *)take(round_up(sizeof(unsigned long long) * kStepBins));
     if (hipMalloc(&h->trace, sizeof(double) * trace_cap) != hipSuccess) {
         g_init_error = "trace allocation failed";
         return cleanup(QAP_ENOMEM);
@@ -463,11 +525,24 @@ int qap_dual_ascent(qap_handle h, int iters, double *lb_out, double *alpha_out, 
     HIPCHK(h, hipMemcpyAsync(&before, h->S, sizeof(before), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->t_host = before.t;
+    unsigned long long steps_before = 0, steps_after = 0;
+    if (st) {
+        int rs = read_steps(h, before, steps_before);
+        if (rs != QAP_OK) return rs;
+    }
     int rc = ensure_trace(h, h->t_host + iters + 1);
     if (rc != QAP_OK) return rc;
+    std::vector<hipEvent_t> evs;
+    if (h->prm.timing) {
+        evs.resize((size_t)5 * iters);
+        for (auto &e : evs) HIPCHK(h, hipEventCreate(&e));
+    }
     for (int it = 0; it < iters; ++it) {
         const int t = h->t_host + it;
-        if (t >= 1) {
+        if (h->prm.timing) {
+            hipError_t e = launch_iteration_timed(h, t, &evs[(size_t)5 * it]);
+            if (e != hipSuccess) return fail(h, QAP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+        } else if (t >= 1) {
             if (!h->graph) {
                 hipGraph_t g = nullptr;
                 HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
@@ -492,6 +567,15 @@ int qap_dual_ascent(qap_handle h, int iters, double *lb_out, double *alpha_out, 
     HIPCHK(h, hipMemcpyAsync(b.data(), h->beta, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     auto t1 = std::chrono::steady_clock::now();
+    double ph[4] = {0, 0, 0, 0};
+    for (int it = 0; it < (h->prm.timing ? iters : 0); ++it) {
+        for (int k = 0; k < 4; ++k) {
+            float ms = 0.f;
+            HIPCHK(h, hipEventElapsedTime(&ms, evs[(size_t)5 * it + k], evs[(size_t)5 * it + k + 1]));
+            ph[k] += ms;
+        }
+    }
+    for (auto &e : evs) (void)hipEventDestroy(e);
     h->t_host = after.t;
     if (lb_out) *lb_out = after.lb;
     if (alpha_out) std::memcpy(alpha_out, a.data(), sizeof(double) * h->n);
@@ -504,8 +588,14 @@ int qap_dual_ascent(qap_handle h, int iters, double *lb_out, double *alpha_out, 
         st->gap = (after.ub < HUGE_VAL && after.ub != 0.0) ? (after.ub - after.lb) / std::fabs(after.ub) : HUGE_VAL;
         st->proven = after.proven;
         st->laps = (long long)st->iterations_done * (h->T + (long long)h->n * h->n + 1);
-        st->dijkstra_steps = (long long)(after.steps - before.steps);
+        int rs = read_steps(h, after, steps_after);
+        if (rs != QAP_OK) return rs;
+        st->dijkstra_steps = (long long)(steps_after - steps_before);
         st->seconds = std::chrono::duration<double>(t1 - t0).count();
+        st->ms_sweep = ph[0];
+        st->ms_zlap = ph[1];
+        st->ms_ylap = ph[2];
+        st->ms_xlap = ph[3];
     }
     return QAP_OK;
 }
@@ -551,18 +641,6 @@ int qap_export_state(qap_handle h, qap_state_header *hdr, double *x, double *y, 
     if (z || hdr) {
         hz.resize(h->Vz);
         HIPCHK(h, hipMemcpy(hz.data(), h->Z, sizeof(double) * h->Vz, hipMemcpyDeviceToHost));
-        if (post) {
-            std::vector<double> hu((size_t)h->T * m), hv((size_t)h->T * m);
-            HIPCHK(h, hipMemcpy(hu.data(), h->U, sizeof(double) * hu.size(), hipMemcpyDeviceToHost));
-            HIPCHK(h, hipMemcpy(hv.data(), h->V, sizeof(double) * hv.size(), hipMemcpyDeviceToHost));
-            const size_t mm = (size_t)m * m;
-            for (long long t = 0; t < h->T; ++t)
-                for (int r = 0; r < m; ++r)
-                    for (int c = 0; c < m; ++c) {
-                        const size_t a = (size_t)t * mm + (size_t)r * m + c;
-                        hz[a] = (hz[a] - hu[(size_t)t * m + r]) - hv[(size_t)t * m + c];
-                    }
-        }
     }
     if (hdr) {
         hdr->n = n;
@@ -587,23 +665,14 @@ int qap_export_state(qap_handle h, qap_state_header *hdr, double *x, double *y, 
 int qap_export_z_tiles(qap_handle h, const int64_t *tiles, int count, double *out)
 {
     if (!h || count < 0 || (count > 0 && (!tiles || !out))) return QAP_EINVAL;
-    DevScalars s{};
-    HIPCHK(h, hipMemcpyAsync(&s, h->S, sizeof(s), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     const int m = h->m;
     const size_t mm = (size_t)m * m;
-    std::vector<double> hu(m), hv(m);
     for (int a = 0; a < count; ++a) {
         const int64_t t = tiles[a];
         if (t < 0 || t >= h->T) return fail(h, QAP_EINVAL, "tile index out of range");
         double *dst = out + (size_t)a * mm;
         HIPCHK(h, hipMemcpy(dst, h->Z + (size_t)t * mm, sizeof(double) * mm, hipMemcpyDeviceToHost));
-        if (s.t > 0) {
-            HIPCHK(h, hipMemcpy(hu.data(), h->U + (size_t)t * m, sizeof(double) * m, hipMemcpyDeviceToHost));
-            HIPCHK(h, hipMemcpy(hv.data(), h->V + (size_t)t * m, sizeof(double) * m, hipMemcpyDeviceToHost));
-            for (int r = 0; r < m; ++r)
-                for (int c = 0; c < m; ++c) dst[(size_t)r * m + c] = (dst[(size_t)r * m + c] - hu[r]) - hv[c];
-        }
     }
     return QAP_OK;
 }
@@ -628,8 +697,6 @@ int qap_import_state(qap_handle h, const qap_state_header *hdr, const double *x,
     HIPCHK(h, hipMemcpy(post ? h->Px : h->Xc, x, sizeof(double) * nn, hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpy(post ? h->Py : h->Yc, y, sizeof(double) * h->T, hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpy(h->Z, z, sizeof(double) * h->Vz, hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(k_fill, dim3(4096), dim3(256), 0, h->stream, h->U, (size_t)h->T * h->m, 0.0);
-    hipLaunchKernelGGL(k_fill, dim3(4096), dim3(256), 0, h->stream, h->V, (size_t)h->T * h->m, 0.0);
     DevScalars s{};
     HIPCHK(h, hipMemcpyAsync(&s, h->S, sizeof(s), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -653,7 +720,7 @@ int qap_lap_batch(const double *cost, int count, int m, double *u, double *v, do
     int L, C;
     pick_zlap(m, lanes, cols, L, C);
     hipStream_t s = (hipStream_t)stream;
-    const size_t per = (size_t)m * m * sizeof(double);
+    const size_t per = ((size_t)m * m + 2 * m) * sizeof(double);
     int G = 256 / L;
     while (G > 1 && (size_t)G * per > 65536) --G;
     const unsigned blocks = (unsigned)((count + G - 1) / G);
@@ -663,7 +730,18 @@ int qap_lap_batch(const double *cost, int count, int m, double *u, double *v, do
                            u, v, theta, (int *)row_of_col);                                              \
     } else
     QAP_LB(8, 1) QAP_LB(16, 1) QAP_LB(32, 1) QAP_LB(64, 1) QAP_LB(8, 2) QAP_LB(16, 2) QAP_LB(32, 2)
-    {
+    QAP_LB(8, 4) QAP_LB(16, 4)
+    if (L == -2 || L == -1) {
+        const int H = -L;
+        const size_t pers = ((size_t)m * m + 2 * m) * sizeof(double) * H;
+        const unsigned bs = (unsigned)((count + H - 1) / H);
+        if (H == 2)
+            hipLaunchKernelGGL((k_lap_batch_s<2>), dim3(bs), dim3(64), pers, s, cost, count, m, u, v, theta,
+                               (int *)row_of_col);
+        else
+            hipLaunchKernelGGL((k_lap_batch_s<1>), dim3(bs), dim3(64), pers, s, cost, count, m, u, v, theta,
+                               (int *)row_of_col);
+    } else {
         return fail(nullptr, QAP_EINVAL, "unsupported lanes/cols mapping");
     }
 #undef QAP_LB

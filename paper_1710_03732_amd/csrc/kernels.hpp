@@ -19,9 +19,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lap_scalar.hpp"
 #include "lap_wave.hpp"
 
 namespace qap {
+
+constexpr int kStepBins = 4096;  // Dijkstra-step counters, spread to avoid atomic contention
 
 struct DevScalars {
     double lb;
@@ -80,76 +83,113 @@ __global__ void k_init_xy(const double *__restrict__ F, const double *__restrict
 // Orbit {A=(i,p), B=(j,q), C=(k,r)}, i<j<k.  Members in canonical order
 // (A,B,C),(A,C,B),(B,A,C),(B,C,A),(C,A,B),(C,B,A); member (P1,P2,P3) is the z
 // entry in tile (P1,P2) at row P3.fac, column P3.loc; its y parent is that
-// tile and its x parent P1.  With pi_z(e) = (R_z(e) - u_row) - v_col from the
-// last Z-LAP duals:
+// tile and its x parent P1.  The z array holds pi_z of the last Z-LAPs:
 //   g_e   = (kz*pi_z(e) + ky2*pi_y(tile(e))) + kx3*pi_x(P1(e))
 //   new_e = okz*pi_z(e) + phi*(left fold of g_f over f != e, canonical order)
 //
-// One block per (facility triple, location p of the first facility); the
-// thread loop covers the (n-1)(n-2) orbits (q, r).  Blocks are numbered so
-// that the n blocks of one triple land on the same XCD back to back: lanes
-// walk r, so members (A,B,C) and (B,A,C) read whole tile rows, members
-// (A,C,B)/(C,A,B) reuse their rows over the q loop inside the block, and
-// members (B,C,A)/(C,B,A) share their cache lines with the neighbouring p
-// blocks of the same triple in that XCD's L2.
-__global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const double *__restrict__ U,
-                                               const double *__restrict__ V,
-                                               const double *__restrict__ Py,
+// For one facility triple the six members form six axis-permuted copies of a
+// 3-D array over the locations (p,q,r): member e is contiguous along its
+// third location.  A block takes one triple and one SB^3 cube of locations
+// and transposes through LDS: load phase (each member read as runs of SB
+// contiguous doubles along its own last axis, g and pi staged in a padded
+// [p][q][r] layout), orbit phase (one thread per orbit), store phase (runs
+// again).  Block numbering keeps all cubes of one triple on one XCD, back to
+// back, so the partial cache lines at run ends merge in that XCD's L2.
+constexpr int SB = 8;                       // cube edge
+constexpr int SB_Q = SB + 1;                // padded q pitch
+constexpr int SB_P = SB * SB_Q + 1;         // padded p pitch
+constexpr int SB_CUBE = SB * SB_P;          // doubles per staged member
+
+__device__ __forceinline__ int cube_idx(int pl, int ql, int rl) { return pl * SB_P + ql * SB_Q + rl; }
+
+__global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const double *__restrict__ Py,
                                                const double *__restrict__ Px,
                                                const int *__restrict__ triples, int ntriples, int n,
-                                               SweepConsts K, const DevScalars *__restrict__ S)
+                                               int nb, SweepConsts K, const DevScalars *__restrict__ S)
 {
     if (S->stopped) return;
+    // g_e staged per orbit position; the orbit phase overwrites it with phi*sum
+    __shared__ double gs[6 * SB_CUBE];
     const unsigned b = blockIdx.x;
     const unsigned xcd = b & 7u, s = b >> 3;
-    const int p = (int)(s % (unsigned)n);
-    const int tri = (int)((s / (unsigned)n) * 8u + xcd);
+    const unsigned nb3 = (unsigned)(nb * nb * nb);
+    const int tri = (int)((s / nb3) * 8u + xcd);
     if (tri >= ntriples) return;
+    const int sub = (int)(s % nb3);
+    const int base[3] = {(sub / (nb * nb)) * SB, ((sub / nb) % nb) * SB, (sub % nb) * SB};
     const int packed = triples[tri];
-    const int i = packed & 0xff, j = (packed >> 8) & 0xff, k = (packed >> 16) & 0xff;
+    const int fi = packed & 0xff, fj = (packed >> 8) & 0xff, fk = (packed >> 16) & 0xff;
     const int m = n - 2;
     const long long mm = (long long)m * m;
-    const int norb = (n - 1) * m;
-    for (int o = threadIdx.x; o < norb; o += blockDim.x) {
-        const int qp = o / m, rr = o % m;
-        const int q = qp + (qp >= p);
-        const int lo = p < q ? p : q, hi = p < q ? q : p;
-        int r = rr;
-        r += (r >= lo);
-        r += (r >= hi);
-        const int fa[3] = {i, j, k};
-        const int la[3] = {p, q, r};
-        // canonical member order as index triples into (A,B,C)
-        const int o1[6] = {0, 0, 1, 1, 2, 2};
-        const int o2[6] = {1, 2, 0, 2, 0, 1};
-        const int o3[6] = {2, 1, 2, 0, 1, 0};
-        long long za[6];
-        double pz[6], g[6];
+    const int F1[6] = {fi, fi, fj, fj, fk, fk};
+    const int F2[6] = {fj, fk, fi, fk, fi, fj};
+    const int F3[6] = {fk, fj, fk, fi, fj, fi};
+    const int X1[6] = {0, 0, 1, 1, 2, 2};
+    const int X2[6] = {1, 2, 0, 2, 0, 1};
+    const int X3[6] = {2, 1, 2, 0, 1, 0};
+    constexpr int PER = (SB * SB * SB) / 256;  // member elements per thread and member
+    long long za[6][PER];
+    int li[6][PER];
+    bool ok[6][PER];
+    double pz[6][PER], py[6][PER], px[6][PER];
+    // addresses of this thread's member-major elements (runs along each
+    // member's own last location axis)
 #pragma unroll
-        for (int e = 0; e < 6; ++e) {
-            const int f1 = fa[o1[e]], l1 = la[o1[e]];
-            const int f2 = fa[o2[e]], l2 = la[o2[e]];
-            const int f3 = fa[o3[e]], l3 = la[o3[e]];
-            const long long t = tile_of(n, f1, l1, f2, l2);
+    for (int e = 0; e < 6; ++e) {
+#pragma unroll
+        for (int w = 0; w < PER; ++w) {
+            const int u = threadIdx.x + 256 * w;
+            const int a3 = u % SB, a2 = (u / SB) % SB, a1 = u / (SB * SB);
+            int loc[3];
+            loc[X1[e]] = base[X1[e]] + a1;
+            loc[X2[e]] = base[X2[e]] + a2;
+            loc[X3[e]] = base[X3[e]] + a3;
+            const int l1 = loc[X1[e]], l2 = loc[X2[e]], l3 = loc[X3[e]];
+            const bool v = l1 < n && l2 < n && l3 < n && l1 != l2 && l1 != l3 && l2 != l3;
+            const int f1 = F1[e], f2 = F2[e], f3 = F3[e];
+            const long long t = v ? tile_of(n, f1, l1, f2, l2) : 0;
             const int row = f3 - (f3 > f1) - (f3 > f2);
-            const int col = l3 - (l3 > l1) - (l3 > l2);
-            za[e] = t * mm + (long long)row * m + col;
-            pz[e] = (Z[za[e]] - U[t * m + row]) - V[t * m + col];
-            g[e] = (K.kz * pz[e] + K.ky2 * Py[t]) + K.kx3 * Px[f1 * n + l1];
+            const int col = v ? (l3 - (l3 > l1) - (l3 > l2)) : 0;
+            ok[e][w] = v;
+            za[e][w] = t * mm + (long long)row * m + col;
+            li[e][w] = cube_idx(loc[0] - base[0], loc[1] - base[1], loc[2] - base[2]);
+            pz[e][w] = Z[za[e][w]];
+            py[e][w] = Py[t];
+            px[e][w] = Px[v ? f1 * n + l1 : 0];
         }
-        const double n0 = ((((g[1] + g[2]) + g[3]) + g[4]) + g[5]);
-        const double n1 = ((((g[0] + g[2]) + g[3]) + g[4]) + g[5]);
-        const double n2 = ((((g[0] + g[1]) + g[3]) + g[4]) + g[5]);
-        const double n3 = ((((g[0] + g[1]) + g[2]) + g[4]) + g[5]);
-        const double n4 = ((((g[0] + g[1]) + g[2]) + g[3]) + g[5]);
-        const double n5 = ((((g[0] + g[1]) + g[2]) + g[3]) + g[4]);
-        Z[za[0]] = K.okz * pz[0] + K.phi * n0;
-        Z[za[1]] = K.okz * pz[1] + K.phi * n1;
-        Z[za[2]] = K.okz * pz[2] + K.phi * n2;
-        Z[za[3]] = K.okz * pz[3] + K.phi * n3;
-        Z[za[4]] = K.okz * pz[4] + K.phi * n4;
-        Z[za[5]] = K.okz * pz[5] + K.phi * n5;
     }
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+#pragma unroll
+        for (int w = 0; w < PER; ++w)
+            if (ok[e][w]) gs[e * SB_CUBE + li[e][w]] = (K.kz * pz[e][w] + K.ky2 * py[e][w]) + K.kx3 * px[e][w];
+    __syncthreads();
+    // orbit phase: phi * (left fold of the partners' g), canonical order
+#pragma unroll
+    for (int w = 0; w < PER; ++w) {
+        const int u = threadIdx.x + 256 * w;
+        const int rl = u % SB, ql = (u / SB) % SB, pl = u / (SB * SB);
+        const int p = base[0] + pl, q = base[1] + ql, r = base[2] + rl;
+        if (p < n && q < n && r < n && p != q && p != r && q != r) {
+            const int c = cube_idx(pl, ql, rl);
+            double g[6];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) g[e] = gs[e * SB_CUBE + c];
+            gs[0 * SB_CUBE + c] = K.phi * ((((g[1] + g[2]) + g[3]) + g[4]) + g[5]);
+            gs[1 * SB_CUBE + c] = K.phi * ((((g[0] + g[2]) + g[3]) + g[4]) + g[5]);
+            gs[2 * SB_CUBE + c] = K.phi * ((((g[0] + g[1]) + g[3]) + g[4]) + g[5]);
+            gs[3 * SB_CUBE + c] = K.phi * ((((g[0] + g[1]) + g[2]) + g[4]) + g[5]);
+            gs[4 * SB_CUBE + c] = K.phi * ((((g[0] + g[1]) + g[2]) + g[3]) + g[5]);
+            gs[5 * SB_CUBE + c] = K.phi * ((((g[0] + g[1]) + g[2]) + g[3]) + g[4]);
+        }
+    }
+    __syncthreads();
+    // store phase: new_e = okz*pi_z(e) + phi*sum, back along the same runs
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+#pragma unroll
+        for (int w = 0; w < PER; ++w)
+            if (ok[e][w]) Z[za[e][w]] = K.okz * pz[e][w] + gs[e * SB_CUBE + li[e][w]];
 }
 
 // R_y <- (1-ky) pi_y, R_x <- (1-kx) pi_x (after the sweep has read them).
@@ -165,25 +205,32 @@ __global__ void k_scale_xy(double *__restrict__ Yc, const double *__restrict__ P
 }
 
 // ----------------------------------------------------------------- Z-LAP --
-// Groups of L lanes, G = blockDim/L groups per block; the block copies its G
-// consecutive tiles (contiguous in HBM) into LDS with one coalesced loop.
-// Writes xi (row duals) to U, psi (column duals) to V, adds Theta to R_y.
+// Groups of L lanes, G = blockDim/L groups per block.  LDS: the G tiles
+// (contiguous, filled by one coalesced copy of G consecutive tiles) followed
+// by G scratch areas of 2m doubles (potentials, matching, path links).  After
+// the solve each tile's slacks pi_z = (M - u_row) - v_col go back to HBM in
+// place, again as one coalesced pass, and Theta is added to R_y.
 template <int L, int C>
-__global__ __launch_bounds__(256) void k_zlap(const double *__restrict__ Z, double *__restrict__ U,
-                                              double *__restrict__ V, double *__restrict__ Yc, int m,
-                                              long long T, DevScalars *__restrict__ S)
+__global__ __launch_bounds__(256) void k_zlap(double *__restrict__ Z, double *__restrict__ Yc, int m,
+                                              long long T, DevScalars *__restrict__ S,
+                                              unsigned long long *__restrict__ bins)
 {
     if (S->stopped) return;
     extern __shared__ double lds[];
     __shared__ unsigned long long bsteps;
     const int G = blockDim.x / L;
     const int g = threadIdx.x / L, l = threadIdx.x % L;
+    const int gbase = (threadIdx.x & 63) - l;
     const long long t0 = (long long)blockIdx.x * G;
     const int mm = m * m;
     const long long left = T - t0;
     const int nt = (int)(left < G ? left : G);
-    const double *src = Z + t0 * mm;
+    double *src = Z + t0 * mm;
     for (int e = threadIdx.x; e < nt * mm; e += blockDim.x) lds[e] = src[e];
+    double *scr = lds + (size_t)G * mm + (size_t)g * 2 * m;
+    double *lu = scr;
+    int *lp = (int *)(scr + m);
+    int *lw = lp + m;
     if (threadIdx.x == 0) bsteps = 0ull;
     __syncthreads();
     const long long t = t0 + g;
@@ -191,14 +238,13 @@ __global__ __launch_bounds__(256) void k_zlap(const double *__restrict__ Z, doub
     if (g < nt) {
         double u[C], v[C], th;
         int pc[C];
-        lap_solve<L, C>(lds + g * mm, m, m, l, u, v, pc, th, st);
+        lap_solve<L, C>(lds + (size_t)g * mm, m, l, gbase, lu, lp, lw, u, v, pc, th, st);
+        __builtin_amdgcn_wave_barrier();
+        double *vs = scr + m;  // column potentials over the matching/links area
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int j = l + L * c;
-            if (j < m) {
-                U[t * m + j] = u[c];
-                V[t * m + j] = v[c];
-            }
+            if (j < m) vs[j] = v[c];
         }
         if (l == 0) {
             Yc[t] = Yc[t] + th;
@@ -206,7 +252,105 @@ __global__ __launch_bounds__(256) void k_zlap(const double *__restrict__ Z, doub
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(&S->steps, bsteps);
+    for (int e = threadIdx.x; e < nt * mm; e += blockDim.x) {
+        const int gg = e / mm, w = e - gg * mm;
+        const double *us = lds + (size_t)G * mm + (size_t)gg * 2 * m;
+        src[e] = (lds[e] - us[w / m]) - us[m + w % m];
+    }
+    if (threadIdx.x == 0) atomicAdd(&bins[blockIdx.x & (kStepBins - 1)], bsteps);
+}
+
+// Z-LAPs with the scalar-controlled solver: one wavefront per block holding
+// H tiles (H = 2: two 32-lane LAPs, m <= 32; H = 1: one 64-lane LAP).
+template <int H>
+__global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *__restrict__ Yc, int m,
+                                               long long T, DevScalars *__restrict__ S,
+                                               unsigned long long *__restrict__ bins)
+{
+    if (S->stopped) return;
+    extern __shared__ double lds[];
+    constexpr int W = 64 / H;
+    const int lane = threadIdx.x;
+    const int h = (H == 1) ? 0 : (lane >> 5);
+    const int l = lane & (W - 1);
+    const long long t0 = (long long)blockIdx.x * H;
+    const int mm = m * m;
+    const long long left = T - t0;
+    const int nt = (int)(left < H ? left : H);
+    double *src = Z + t0 * mm;
+    for (int e = lane; e < nt * mm; e += 64) lds[e] = src[e];
+    double *scr = lds + (size_t)H * mm;
+    const double *tiles[H];
+    double *lus[H];
+    int *lps[H];
+    int *lws[H];
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+        const int qq = q < nt ? q : 0;
+        tiles[q] = lds + (size_t)qq * mm;
+        lus[q] = scr + (size_t)qq * 2 * m;
+        lps[q] = (int *)(lus[q] + m);
+        lws[q] = lps[q] + m;
+    }
+    __syncthreads();
+    double u, v, th;
+    int p, st;
+    lap_solve_scalar<H>(tiles, lus, lps, lws, m, nt, u, v, p, th, st);
+    __builtin_amdgcn_wave_barrier();
+    if (l < m && h < nt) ((double *)lps[h])[l] = v;
+    __syncthreads();
+    for (int e = lane; e < nt * mm; e += 64) {
+        const int gg = e / mm, w = e - gg * mm;
+        const double *us = scr + (size_t)gg * 2 * m;
+        src[e] = (lds[e] - us[w / m]) - us[m + w % m];
+    }
+    if (l == 0 && h < nt) Yc[t0 + h] = Yc[t0 + h] + th;
+    int stt = st;
+    if (H == 2) stt = __builtin_amdgcn_readlane(st, 0) + (nt > 1 ? __builtin_amdgcn_readlane(st, 32) : 0);
+    if (lane == 0) atomicAdd(&bins[blockIdx.x & (kStepBins - 1)], (unsigned long long)stt);
+}
+
+// LAP batch with the scalar-controlled solver (validation entry point).
+template <int H>
+__global__ __launch_bounds__(64) void k_lap_batch_s(const double *__restrict__ cost, int count, int m,
+                                                    double *__restrict__ uo, double *__restrict__ vo,
+                                                    double *__restrict__ tho, int *__restrict__ rco)
+{
+    extern __shared__ double lds[];
+    constexpr int W = 64 / H;
+    const int lane = threadIdx.x;
+    const int h = (H == 1) ? 0 : (lane >> 5);
+    const int l = lane & (W - 1);
+    const long long t0 = (long long)blockIdx.x * H;
+    const int mm = m * m;
+    const long long left = count - t0;
+    const int nt = (int)(left < H ? left : H);
+    const double *src = cost + t0 * mm;
+    for (int e = lane; e < nt * mm; e += 64) lds[e] = src[e];
+    double *scr = lds + (size_t)H * mm;
+    const double *tiles[H];
+    double *lus[H];
+    int *lps[H];
+    int *lws[H];
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+        const int qq = q < nt ? q : 0;
+        tiles[q] = lds + (size_t)qq * mm;
+        lus[q] = scr + (size_t)qq * 2 * m;
+        lps[q] = (int *)(lus[q] + m);
+        lws[q] = lps[q] + m;
+    }
+    __syncthreads();
+    double u, v, th;
+    int p, st;
+    lap_solve_scalar<H>(tiles, lus, lps, lws, m, nt, u, v, p, th, st);
+    if (l < m && h < nt) {
+        const long long t = t0 + h;
+        uo[t * m + l] = u;
+        vo[t * m + l] = v;
+        rco[t * m + l] = p;
+        if (l == 0) tho[t] = th;
+    }
 }
 
 // ----------------------------------------------------------------- Y-LAP --
@@ -217,7 +361,8 @@ __global__ __launch_bounds__(256) void k_zlap(const double *__restrict__ Z, doub
 template <int L, int C>
 __global__ __launch_bounds__(256) void k_ylap(const double *__restrict__ Yc, double *__restrict__ Py,
                                               double *__restrict__ Xc, int n, int equalize,
-                                              double ophy, double phy, DevScalars *__restrict__ S)
+                                              double ophy, double phy, DevScalars *__restrict__ S,
+                                              unsigned long long *__restrict__ bins)
 {
     if (S->stopped) return;
     extern __shared__ double lds[];
@@ -225,11 +370,12 @@ __global__ __launch_bounds__(256) void k_ylap(const double *__restrict__ Yc, dou
     const int m = n - 1, mm = m * m;
     const int G = blockDim.x / L;
     const int g = threadIdx.x / L, l = threadIdx.x % L;
+    const int gbase = (threadIdx.x & 63) - l;
     const int ip = blockIdx.x * G + g;
-    // per group: matrix (mm) + u (m) + v (m)
     double *M = lds + (size_t)g * (mm + 2 * m);
-    double *us = M + mm;
-    double *vs = us + m;
+    double *lu = M + mm;
+    int *lp = (int *)(lu + m);
+    int *lw = lp + m;
     if (threadIdx.x == 0) bsteps = 0ull;
     const bool active = ip < n * n;
     if (active) {
@@ -250,27 +396,24 @@ __global__ __launch_bounds__(256) void k_ylap(const double *__restrict__ Yc, dou
     if (active) {
         double u[C], v[C], th;
         int pc[C], st = 0;
-        lap_solve<L, C>(M, m, m, l, u, v, pc, th, st);
+        lap_solve<L, C>(M, m, l, gbase, lu, lp, lw, u, v, pc, th, st);
+        __builtin_amdgcn_wave_barrier();
+        double *vs = lu + m;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int j = l + L * c;
-            if (j < m) {
-                us[j] = u[c];
-                vs[j] = v[c];
-            }
+            if (j < m) vs[j] = v[c];
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         const long long base = (long long)ip * mm;
-        for (int e = l; e < mm; e += L) Py[base + e] = (M[e] - us[e / m]) - vs[e % m];
+        for (int e = l; e < mm; e += L) Py[base + e] = (M[e] - lu[e / m]) - vs[e % m];
         if (l == 0) {
             Xc[ip] = Xc[ip] + th;
             atomicAdd(&bsteps, (unsigned long long)st);
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(&S->steps, bsteps);
+    if (threadIdx.x == 0) atomicAdd(&bins[blockIdx.x & (kStepBins - 1)], bsteps);
 }
 
 // ----------------------------------------------------------------- X-LAP --
@@ -286,7 +429,8 @@ __global__ __launch_bounds__(64) void k_xlap(const double *__restrict__ Xc, doub
 {
     if (S->stopped) return;
     __shared__ double M[64 * 64];
-    __shared__ double us[64], vs[64];
+    __shared__ double lu[64], vs[64];
+    __shared__ int lp[64], lw[64];
     __shared__ int sig[64];
     __shared__ int improved;
     const int l = threadIdx.x;
@@ -295,16 +439,15 @@ __global__ __launch_bounds__(64) void k_xlap(const double *__restrict__ Xc, doub
     __syncthreads();
     double u[1], v[1], th;
     int pc[1], st = 0;
-    lap_solve<64, 1>(M, n, n, l, u, v, pc, th, st);
+    lap_solve<64, 1>(M, n, l, 0, lu, lp, lw, u, v, pc, th, st);
     if (l < n) {
-        us[l] = u[0];
         vs[l] = v[0];
         alpha[l] = u[0];
         beta[l] = v[0];
         sig[pc[0]] = l;
     }
     __syncthreads();
-    for (int e = l; e < nn; e += 64) Px[e] = (M[e] - us[e / n]) - vs[e % n];
+    for (int e = l; e < nn; e += 64) Px[e] = (M[e] - lu[e / n]) - vs[e % n];
     // exact cost of the assignment
     double cd = 0.0;
     long long ci = 0;
@@ -335,7 +478,7 @@ __global__ __launch_bounds__(64) void k_xlap(const double *__restrict__ Xc, doub
             ub = cost;
             S->ub = ub;
         }
-        S->steps += (unsigned long long)st;
+        S->steps += (unsigned long long)st;  // X-LAP steps stay in the scalar block
         trace[S->t] = lb;
         S->t = S->t + 1;
         int proven = 0;
@@ -366,18 +509,21 @@ __global__ __launch_bounds__(256) void k_lap_batch(const double *__restrict__ co
     extern __shared__ double lds[];
     const int G = blockDim.x / L;
     const int g = threadIdx.x / L, l = threadIdx.x % L;
+    const int gbase = (threadIdx.x & 63) - l;
     const long long t0 = (long long)blockIdx.x * G;
     const int mm = m * m;
     const long long left = count - t0;
     const int nt = (int)(left < G ? left : G);
     const double *src = cost + t0 * mm;
     for (int e = threadIdx.x; e < nt * mm; e += blockDim.x) lds[e] = src[e];
+    double *scr = lds + (size_t)G * mm + (size_t)g * 2 * m;
     __syncthreads();
     if (g < nt) {
         const long long t = t0 + g;
         double u[C], v[C], th;
         int pc[C], st = 0;
-        lap_solve<L, C>(lds + g * mm, m, m, l, u, v, pc, th, st);
+        lap_solve<L, C>(lds + (size_t)g * mm, m, l, gbase, scr, (int *)(scr + m), (int *)(scr + m) + m, u, v,
+                        pc, th, st);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int j = l + L * c;

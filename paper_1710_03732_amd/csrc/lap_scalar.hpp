@@ -1,0 +1,192 @@
+// lap_scalar.hpp -- the Hungarian LAP solver of lap_wave.hpp with its control
+// held in scalar registers: a wavefront solves H independent LAPs at once
+// (H = 1: one LAP on 64 lanes, m <= 64; H = 2: two LAPs on 32 lanes each,
+// m <= 32).  Lane l of part h owns row l and column l of LAP h.
+//
+// Same algorithm, same arithmetic, same tie-break as lap_wave.hpp (shortest
+// augmenting paths, Section 2.3 "LAP Solution"; see there for the fixed
+// choice of optimal duals), so results are bitwise identical.  What differs is
+// the mapping: the current row, the chosen column, the matched row, the path
+// and the tree/used sets of each part are wave-uniform values (SGPRs, lane
+// masks), so the scalar unit runs the control flow and a Dijkstra step costs
+// about forty vector instructions for all H LAPs of the wave.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lap_wave.hpp"
+
+namespace qap {
+
+__device__ __forceinline__ double vmin_f64(double a, double b)
+{
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+template <int CTRL>
+__device__ __forceinline__ double mov_dpp_d(double x)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+// min over each 32-lane half (H = 2) or the whole wave (H = 1); every lane
+// receives the minimum of its part.  Inputs are never NaN.
+template <int H>
+__device__ __forceinline__ double part_min(double x)
+{
+    x = vmin_f64(x, mov_dpp_d<0x128>(x));  // row_ror:8
+    x = vmin_f64(x, mov_dpp_d<0x124>(x));  // row_ror:4
+    x = vmin_f64(x, mov_dpp_d<0x122>(x));  // row_ror:2
+    x = vmin_f64(x, mov_dpp_d<0x121>(x));  // row_ror:1
+    {
+        const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(x), false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(x), false, false);
+        x = vmin_f64(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
+    }
+    if constexpr (H == 1) {
+        const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(x), false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(x), false, false);
+        x = vmin_f64(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
+    }
+    return x;
+}
+
+__device__ __forceinline__ int sgpr(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Solve H LAPs.  tile[h] = matrix of part h (row stride m, LDS); lu/lp/lw[h]
+// = per-part LDS scratch (m doubles, m ints, m ints).  nparts <= H parts are
+// live (the others are skipped).  Outputs for lane l of part h: u (row l),
+// v (column l), p (row matched to column l, -1 past m); theta and steps of
+// the lane's part.  On return lu[h] holds that part's row potentials.
+template <int H>
+__device__ void lap_solve_scalar(const double *const *tile, double *const *lu, int *const *lp,
+                                 int *const *lw, int m, int nparts, double &u, double &v, int &p,
+                                 double &theta, int &steps)
+{
+    constexpr int W = 64 / H;  // lanes per part
+    const int lane = (int)(threadIdx.x & 63);
+    const int h = (H == 1) ? 0 : (lane >> 5);
+    const int l = lane & (W - 1);
+    const bool valid = l < m && h < nparts;
+    const double *M = tile[h];
+    double *mlu = lu[h];
+    int *mlp = lp[h];
+    int *mlw = lw[h];
+
+    u = 0.0;
+    v = 0.0;
+    p = -1;
+    if (valid) {
+        mlu[l] = 0.0;
+        mlp[l] = -1;
+    }
+    __builtin_amdgcn_wave_barrier();
+    double minv = kInf;
+    int way = -1;
+    bool used = false;
+    bool intree = valid && l == 0;
+    double th = 0.0;
+    int st = 0;
+    // per-part scalar state
+    int i0[H], r[H], last[H];
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+        i0[q] = (q < nparts) ? 0 : m;
+        r[q] = 0;
+        last[q] = -1;
+    }
+    for (;;) {
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < H; ++q) any = any || (i0[q] < m);
+        if (!any) break;
+        const int my_i0 = (H == 1 || h == 0) ? i0[0] : i0[H - 1];
+        const bool part_live = my_i0 < m;
+        const int my_r = (H == 1 || h == 0) ? r[0] : r[H - 1];
+        const int my_last = (H == 1 || h == 0) ? last[0] : last[H - 1];
+        if (part_live) ++st;
+        const bool act = valid && part_live && !used;
+        const double ur = mlu[my_r];
+        const double mv = M[my_r * m + (l < m ? l : 0)];
+        const double s = (mv - ur) - v;
+        if (act && s < minv) {
+            minv = s;
+            way = my_last;
+        }
+        const double mn = part_min<H>(act ? minv : kInf);
+        const bool cand = act && minv == mn;
+        const unsigned long long bc = __builtin_amdgcn_ballot_w64(cand);
+        const unsigned long long bf = __builtin_amdgcn_ballot_w64(cand && p < 0);
+        int js[H];
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            const unsigned long long cq = (H == 1) ? bc : ((bc >> (32 * q)) & 0xffffffffull);
+            const unsigned long long fq = (H == 1) ? bf : ((bf >> (32 * q)) & 0xffffffffull);
+            js[q] = (int)__builtin_ctzll(fq != 0ull ? fq : (cq | (1ull << 63)));
+        }
+        if (part_live) {
+            if (intree) u = u + mn;
+            if (valid) {
+                if (used)
+                    v = v - mn;
+                else
+                    minv = minv - mn;
+            }
+            th = th + mn;
+        }
+        const int my_js = (H == 1 || h == 0) ? js[0] : js[H - 1];
+        const int pjv = mlp[my_js < m ? my_js : 0];
+        int pj[H];
+#pragma unroll
+        for (int q = 0; q < H; ++q) pj[q] = __builtin_amdgcn_readlane(pjv, q * W);
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            if (i0[q] >= m) continue;
+            const bool mine = (H == 1) || (h == q);
+            if (pj[q] >= 0) {
+                if (mine && l == js[q]) used = true;
+                if (mine && valid && l == pj[q]) intree = true;
+                r[q] = pj[q];
+                last[q] = js[q];
+                continue;
+            }
+            // flip the alternating path of part q back to its root row
+            if (mine && valid) {
+                mlw[l] = way;
+                if (intree) mlu[l] = u;
+            }
+            __builtin_amdgcn_wave_barrier();
+            unsigned long long onpath = 0ull;
+            int j = js[q];
+            while (j >= 0) {
+                onpath |= 1ull << j;
+                j = sgpr(lw[q][j]);
+            }
+            int np = -1;
+            const bool flip = mine && valid && ((onpath >> l) & 1ull);
+            if (flip) np = (way < 0) ? i0[q] : mlp[way];
+            __builtin_amdgcn_wave_barrier();
+            if (flip) {
+                p = np;
+                mlp[l] = np;
+            }
+            __builtin_amdgcn_wave_barrier();
+            i0[q] = i0[q] + 1;
+            r[q] = i0[q];
+            last[q] = -1;
+            if (mine) {
+                minv = kInf;
+                way = -1;
+                used = false;
+                intree = valid && l == i0[q];
+            }
+        }
+    }
+    theta = th;
+    steps = st;
+}
+
+}  // namespace qap

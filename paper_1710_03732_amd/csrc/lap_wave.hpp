@@ -17,12 +17,19 @@
 //     non-tree columns minv -= delta; the LAP value is the running sum of the
 //     deltas;
 //   * reaching an unmatched column flips the alternating path to the root.
-// Every per-column operation is one IEEE add, subtract or compare, and the
-// argmin is an exact min reduction, so the result does not depend on L or C.
+// Every per-column operation is one IEEE add, subtract or compare and the
+// argmin is an exact min, so the result does not depend on L or C.
 //
-// Per step the group does one LDS row read per slot, two subtracts, a
-// butterfly min over the group (double) and one over an int code that
-// encodes the tie-break, plus two broadcasts (row potential, matched row).
+// Cross-lane work per Dijkstra step, all without LDS round trips:
+//   * min over the group: DPP row rotations inside 16-lane rows (half-row
+//     mirror and quad permutes for 8-lane groups), v_permlane16_swap across
+//     the two rows of a 32-lane group, v_permlane32_swap across wave halves;
+//   * the chosen column: wave ballots of the tied columns (unmatched ones
+//     first), masked to the group, lowest set bit;
+//   * the potential of the next row and the row matched to the chosen column
+//     are read from a per-group LDS mirror (u is written back there when a
+//     row's search ends, the matching when a path flips), at a group-uniform
+//     address.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -30,58 +37,92 @@ namespace qap {
 
 constexpr double kInf = __builtin_huge_val();
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double dmin(double a, double b) { return __builtin_fmin(a, b); }
+
+// min over each 16-lane DPP row (every lane gets the row minimum)
+__device__ __forceinline__ double row16_min(double x)
+{
+    x = dmin(x, dpp_d<0x128>(x));  // row_ror:8
+    x = dmin(x, dpp_d<0x124>(x));  // row_ror:4
+    x = dmin(x, dpp_d<0x122>(x));  // row_ror:2
+    x = dmin(x, dpp_d<0x121>(x));  // row_ror:1
+    return x;
+}
+
+// min over each 8-lane half row
+__device__ __forceinline__ double half8_min(double x)
+{
+    x = dmin(x, dpp_d<0x141>(x));  // row_half_mirror
+    x = dmin(x, dpp_d<0x4E>(x));   // quad_perm [2,3,0,1]
+    x = dmin(x, dpp_d<0xB1>(x));   // quad_perm [1,0,3,2]
+    return x;
+}
+
+__device__ __forceinline__ double swap16_min(double x)
+{
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(x), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(x), false, false);
+    return dmin(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
+}
+
+__device__ __forceinline__ double swap32_min(double x)
+{
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(x), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(x), false, false);
+    return dmin(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
+}
+
 template <int L>
 __device__ __forceinline__ double group_min(double x)
 {
-#pragma unroll
-    for (int off = L / 2; off >= 1; off >>= 1) {
-        const double y = __shfl_xor(x, off, L);
-        x = (y < x) ? y : x;
+    if constexpr (L == 8) {
+        return half8_min(x);
+    } else {
+        x = row16_min(x);
+        if constexpr (L >= 32) x = swap16_min(x);
+        if constexpr (L == 64) x = swap32_min(x);
+        return x;
     }
-    return x;
 }
 
-template <int L>
-__device__ __forceinline__ int group_min(int x)
-{
-#pragma unroll
-    for (int off = L / 2; off >= 1; off >>= 1) {
-        const int y = __shfl_xor(x, off, L);
-        x = (y < x) ? y : x;
-    }
-    return x;
-}
-
-template <int C, typename T>
-__device__ __forceinline__ T slot(const T (&a)[C], int s)
-{
-    T r = a[0];
-#pragma unroll
-    for (int c = 1; c < C; ++c)
-        if (s == c) r = a[c];
-    return r;
-}
-
-// Solve the m x m LAP whose matrix row r starts at M + r*ld (LDS or global).
-// Outputs per slot c (index j = l + L*c): u[c] = potential of row j, v[c] =
-// potential of column j, p[c] = row assigned to column j (-1 if j >= m).
-// theta = LAP value, steps = Dijkstra steps.  All lanes of the group must be
-// active; other groups of the wave may be doing their own solve.
+// Per-group LDS scratch of lap_solve: lu (m doubles), lp and lw (m ints each).
+// Solve the m x m LAP whose row r starts at M + r*m (LDS).  gbase = lane of
+// the group's first lane within the wavefront.  Outputs per slot c (column /
+// row j = l + L*c): u[c] row potential, v[c] column potential, p[c] row
+// assigned to column j (-1 for j >= m); theta = LAP value; steps = Dijkstra
+// steps.  On return lu holds u.  All lanes of the group must be active.
 template <int L, int C>
-__device__ void lap_solve(const double *__restrict__ M, int ld, int m, int l, double (&u)[C],
-                          double (&v)[C], int (&p)[C], double &theta, int &steps)
+__device__ void lap_solve(const double *__restrict__ M, int m, int l, int gbase, double *lu, int *lp,
+                          int *lw, double (&u)[C], double (&v)[C], int (&p)[C], double &theta,
+                          int &steps)
 {
+    static_assert(L == 8 || L == 16 || L == 32 || L == 64, "group size");
+    const unsigned long long gmask = (L == 64) ? ~0ull : (((1ull << L) - 1ull) << gbase);
     double minv[C];
     int way[C];
     unsigned used = 0u, intree = 0u;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
+        const int j = l + L * c;
         u[c] = 0.0;
         v[c] = 0.0;
         p[c] = -1;
         minv[c] = kInf;
         way[c] = -1;
+        if (j < m) {
+            lu[j] = 0.0;
+            lp[j] = -1;
+        }
     }
+    __builtin_amdgcn_wave_barrier();
     double th = 0.0;
     int st = 0;
     int i0 = 0, r = 0, last = -1;
@@ -100,8 +141,8 @@ __device__ void lap_solve(const double *__restrict__ M, int ld, int m, int l, do
             fresh = false;
         }
         ++st;
-        const double ur = __shfl(slot<C>(u, r / L), r % L, L);
-        const double *row = M + (size_t)r * ld;
+        const double ur = lu[r];
+        const double *row = M + (size_t)r * m;
         double best = kInf;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -112,21 +153,22 @@ __device__ void lap_solve(const double *__restrict__ M, int ld, int m, int l, do
                     minv[c] = s;
                     way[c] = last;
                 }
-                best = (minv[c] < best) ? minv[c] : best;
+                best = dmin(best, minv[c]);
             }
         }
         const double mn = group_min<L>(best);
-        int code = 1 << 20;
+        // chosen column: tied non-tree columns, unmatched first, lowest index
+        int js = -1;
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int j = l + L * c;
-            if (j < m && !((used >> c) & 1u) && minv[c] == mn) {
-                const int cc = (p[c] < 0) ? j : (j + 256);
-                code = (cc < code) ? cc : code;
+        for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int j = l + L * c;
+                const bool cand = j < m && !((used >> c) & 1u) && minv[c] == mn && (pass == 1 || p[c] < 0);
+                const unsigned long long b = __builtin_amdgcn_ballot_w64(cand) & gmask;
+                if (js < 0 && b != 0ull) js = (__builtin_ctzll(b) - gbase) + L * c;
             }
         }
-        code = group_min<L>(code);
-        const int js = code & 255;
         const double delta = mn;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -140,33 +182,39 @@ __device__ void lap_solve(const double *__restrict__ M, int ld, int m, int l, do
             }
         }
         th = th + delta;
-        const int pj = __shfl(slot<C>(p, js / L), js % L, L);
+        const int pj = lp[js];
         if (pj < 0) {
             // Flip the alternating path js <- way[js] <- ... <- root: every
             // column on it takes the old row of its predecessor (the root row
-            // i0 for the first column).
+            // i0 for the first column).  Tree rows publish their potentials.
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int j = l + L * c;
+                if (j < m) lw[j] = way[c];
+                if ((intree >> c) & 1u) lu[j] = u[c];
+            }
+            __builtin_amdgcn_wave_barrier();
             unsigned onpath = 0u;
             int j = js;
             while (j >= 0) {
                 if ((j % L) == l) onpath |= 1u << (j / L);
-                j = __shfl(slot<C>(way, j / L), j % L, L);
+                j = lw[j];
             }
             int np[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const int w = way[c];
-                const int ws = (w < 0) ? 0 : w;
-                int got = 0;
-#pragma unroll
-                for (int cc = 0; cc < C; ++cc) {
-                    const int val = __shfl(p[cc], ws % L, L);
-                    if ((ws / L) == cc) got = val;
-                }
-                np[c] = (w < 0) ? i0 : got;
+                np[c] = (w < 0) ? i0 : lp[w < 0 ? 0 : w];
             }
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
-            for (int c = 0; c < C; ++c)
-                if ((onpath >> c) & 1u) p[c] = np[c];
+            for (int c = 0; c < C; ++c) {
+                if ((onpath >> c) & 1u) {
+                    p[c] = np[c];
+                    lp[l + L * c] = np[c];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
             ++i0;
             fresh = true;
         } else {

@@ -18,7 +18,9 @@ from paper_1710_03732_amd import instances as I
 
 pytestmark = pytest.mark.gpu
 
-MAPPINGS = [(8, 1), (16, 1), (32, 1), (64, 1), (8, 2), (16, 2), (32, 2)]
+# (lanes, columns per lane); lanes -2 / -1: scalar-controlled whole-wave
+# solvers with two 32-lane LAPs / one 64-lane LAP per wavefront
+MAPPINGS = [(-2, 1), (-1, 1), (8, 1), (16, 1), (32, 1), (64, 1), (8, 2), (16, 2), (32, 2), (8, 4), (16, 4)]
 
 
 def _torch():
@@ -53,7 +55,7 @@ def test_lap_batch_bitwise(m):
         ref = [O.lap(cost[b]) for b in range(count)]
         dev = torch.from_numpy(cost).cuda()
         for (L, Cc) in MAPPINGS:
-            if L * Cc < m:
+            if {-2: 32, -1: 64}.get(L, L * Cc) < m:
                 continue
             th, u, v, rc = B.lap_batch(dev, lanes=L, cols=Cc)
             torch.cuda.synchronize()
@@ -168,7 +170,7 @@ def test_zlap_mapping_does_not_change_results():
     inst = I.grid_n15()
     F, D, Bm = inst.arrays()
     ref = None
-    for (L, Cc) in [(16, 1), (32, 1), (64, 1), (8, 2), (16, 2), (32, 2)]:
+    for (L, Cc) in [(-2, 1), (-1, 1), (16, 1), (32, 1), (64, 1), (8, 2), (16, 2), (32, 2), (8, 4), (16, 4)]:
         gpu = B.DualAscent(F, D, Bm, zlap_lanes=L, zlap_cols=Cc)
         gpu.run(8)
         tr = gpu.trace()
