@@ -64,16 +64,19 @@ int orc_max_threads(void)
  * and the dual slacks pi = (M - u) - v of every LAP variable (complementary
  * slackness, Eq. compslack).  Which optimal duals are returned is not fixed
  * by the paper; this routine fixes it:
- *   - cold start u = v = 0, rows inserted in order 0..m-1;
+ *   - start (textbook column reduction): v[j] = min_i M[i][j], u = 0; every
+ *     column proposes the lowest row attaining its minimum and each row
+ *     proposed to is matched to the lowest proposing column; the running LAP
+ *     value starts at the left fold of v[0..m-1];
+ *   - the unmatched rows are then inserted in ascending order;
  *   - a Dijkstra step scans the newest tree row r: for every column j not yet
  *     in the tree, s = (M[r][j] - u[r]) - v[j], and minv[j] takes s when s is
  *     strictly smaller (remembering the column through which it was reached);
  *   - the next column j* is the non-tree column of least minv; ties prefer a
  *     column that is still unmatched, then the lowest index;
  *   - delta = minv[j*]; every tree row gets u += delta, every tree column
- *     v -= delta, every non-tree column minv -= delta;
- *   - the LAP value is theta = the running sum of the deltas (the change of
- *     the dual objective sum(u) + sum(v) at each step is exactly delta);
+ *     v -= delta, every non-tree column minv -= delta; the LAP value gets
+ *     += delta (the change of the dual objective sum(u) + sum(v));
  *   - on reaching an unmatched column the path is flipped back to the root.
  * Outputs: u[m], v[m], row_of_col[m], *theta; *steps counts Dijkstra steps.
  * ---------------------------------------------------------------------- */
@@ -81,13 +84,25 @@ int orc_lap(int m, const double *M, double *u, double *v, int *row_of_col,
             double *theta, long long *steps)
 {
     double minv[ORC_MAXM];
-    int used[ORC_MAXM], way[ORC_MAXM];
+    int used[ORC_MAXM], way[ORC_MAXM], prop[ORC_MAXM], owner[ORC_MAXM];
     if (m < 1 || m > ORC_MAXM) return -1;
-    for (int j = 0; j < m; ++j) { v[j] = 0.0; row_of_col[j] = -1; }
-    for (int i = 0; i < m; ++i) u[i] = 0.0;
-    double th = 0.0;
+    for (int i = 0; i < m; ++i) { u[i] = 0.0; owner[i] = -1; }
+    for (int j = 0; j < m; ++j) {
+        int arg = 0;
+        double best = M[j];
+        for (int i = 1; i < m; ++i)
+            if (M[(size_t)i * m + j] < best) { best = M[(size_t)i * m + j]; arg = i; }
+        v[j] = best;
+        prop[j] = arg;
+        row_of_col[j] = -1;
+    }
+    for (int j = 0; j < m; ++j)
+        if (owner[prop[j]] < 0) { owner[prop[j]] = j; row_of_col[j] = prop[j]; }
+    double th = v[0];
+    for (int j = 1; j < m; ++j) th = th + v[j];
     long long st = 0;
     for (int i0 = 0; i0 < m; ++i0) {
+        if (owner[i0] >= 0) continue;  /* matched by the column reduction */
         for (int j = 0; j < m; ++j) { minv[j] = HUGE_VAL; used[j] = 0; way[j] = ORC_ROOT; }
         int r = i0, last = ORC_ROOT;
         for (;;) {

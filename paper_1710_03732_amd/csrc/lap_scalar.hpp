@@ -3,9 +3,10 @@
 // (H = 1: one LAP on 64 lanes, m <= 64; H = 2: two LAPs on 32 lanes each,
 // m <= 32).  Lane l of part h owns row l and column l of LAP h.
 //
-// Same algorithm, same arithmetic, same tie-break as lap_wave.hpp (shortest
-// augmenting paths, Section 2.3 "LAP Solution"; see there for the fixed
-// choice of optimal duals), so results are bitwise identical.  What differs is
+// Same algorithm, same arithmetic, same tie-break as lap_wave.hpp (column
+// reduction start, then shortest augmenting paths, Section 2.3 "LAP
+// Solution"; see there for the fixed choice of optimal duals), so results are
+// bitwise identical.  What differs is
 // the mapping: the current row, the chosen column, the matched row, the path
 // and the tree/used sets of each part are wave-uniform values (SGPRs, lane
 // masks), so the scalar unit runs the control flow and a Dijkstra step costs
@@ -76,28 +77,60 @@ __device__ void lap_solve_scalar(const double *const *tile, double *const *lu, i
     int *mlp = lp[h];
     int *mlw = lw[h];
 
+    // column reduction: lane l scans column l of its part
+    constexpr int kNone = 0x7fffffff;
     u = 0.0;
     v = 0.0;
     p = -1;
+    int prop = 0;
     if (valid) {
-        mlu[l] = 0.0;
-        mlp[l] = -1;
+        double best = M[l];
+        for (int i = 1; i < m; ++i) {
+            const double x = M[i * m + l];
+            if (x < best) {
+                best = x;
+                prop = i;
+            }
+        }
+        v = best;
+        mlw[l] = kNone;
     }
+    __builtin_amdgcn_wave_barrier();
+    if (valid) atomicMin(&mlw[prop], l);
+    __builtin_amdgcn_wave_barrier();
+    if (valid) {
+        p = (mlw[prop] == l) ? prop : -1;
+        mlp[l] = p;
+        mlu[l] = 0.0;
+    }
+    const unsigned long long unm_all = __builtin_amdgcn_ballot_w64(valid && mlw[l] == kNone);
     __builtin_amdgcn_wave_barrier();
     double minv = kInf;
     int way = -1;
     bool used = false;
-    bool intree = valid && l == 0;
+    bool intree = false;
     double th = 0.0;
     int st = 0;
-    // per-part scalar state
+    // per-part scalar state: rows still to insert, current row, last column;
+    // the LAP value starts at the left fold of the part's column minima
+    unsigned long long unm[H];
     int i0[H], r[H], last[H];
 #pragma unroll
     for (int q = 0; q < H; ++q) {
-        i0[q] = (q < nparts) ? 0 : m;
-        r[q] = 0;
+        unm[q] = (H == 1) ? unm_all : ((unm_all >> (32 * q)) & 0xffffffffull);
+        i0[q] = (q < nparts && unm[q]) ? (int)__builtin_ctzll(unm[q]) : m;
+        r[q] = i0[q];
         last[q] = -1;
+        if (q < nparts) {
+            double f = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), q * W),
+                                        __builtin_amdgcn_readlane(__double2loint(v), q * W));
+            for (int j = 1; j < m; ++j)
+                f = f + __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), q * W + j),
+                                         __builtin_amdgcn_readlane(__double2loint(v), q * W + j));
+            if (H == 1 || h == q) th = f;
+        }
     }
+    intree = valid && i0[(H == 1) ? 0 : h] == l;
     for (;;) {
         bool any = false;
 #pragma unroll
@@ -174,7 +207,8 @@ __device__ void lap_solve_scalar(const double *const *tile, double *const *lu, i
                 mlp[l] = np;
             }
             __builtin_amdgcn_wave_barrier();
-            i0[q] = i0[q] + 1;
+            unm[q] &= unm[q] - 1ull;
+            i0[q] = unm[q] ? (int)__builtin_ctzll(unm[q]) : m;
             r[q] = i0[q];
             last[q] = -1;
             if (mine) {

@@ -7,15 +7,18 @@
 // three-stage decomposition of DLRLT2 (Section 2.3, "LAP Solution").  The
 // paper does not say which optimal duals a solver must return; this solver
 // makes the fixed choice the whole library is built on:
-//   * cold start, rows inserted in order 0..m-1;
+//   * start by column reduction: v[j] = min_i M[i][j], u = 0; every column
+//     proposes the lowest row attaining its minimum and each proposed row is
+//     matched to the lowest proposing column; the LAP value starts at the
+//     left fold of v[0..m-1]; the unmatched rows are then inserted in
+//     ascending order;
 //   * a Dijkstra step scans the newest tree row r: every non-tree column j
 //     computes s = (M[r][j] - u[r]) - v[j] and keeps it in minv[j] when
 //     strictly smaller, remembering the column through which it was reached;
 //   * the next column is the non-tree column of least minv; ties prefer an
 //     unmatched column, then the lowest index;
 //   * delta = that least minv; tree rows u += delta, tree columns v -= delta,
-//     non-tree columns minv -= delta; the LAP value is the running sum of the
-//     deltas;
+//     non-tree columns minv -= delta; the LAP value gets += delta;
 //   * reaching an unmatched column flips the alternating path to the root.
 // Every per-column operation is one IEEE add, subtract or compare and the
 // argmin is an exact min, so the result does not depend on L or C.
@@ -106,9 +109,11 @@ __device__ void lap_solve(const double *__restrict__ M, int m, int l, int gbase,
 {
     static_assert(L == 8 || L == 16 || L == 32 || L == 64, "group size");
     const unsigned long long gmask = (L == 64) ? ~0ull : (((1ull << L) - 1ull) << gbase);
+    constexpr int kNone = 0x7fffffff;
     double minv[C];
-    int way[C];
+    int way[C], prop[C];
     unsigned used = 0u, intree = 0u;
+    // column reduction: each lane scans its own columns (conflict-free LDS reads)
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int j = l + L * c;
@@ -117,15 +122,50 @@ __device__ void lap_solve(const double *__restrict__ M, int m, int l, int gbase,
         p[c] = -1;
         minv[c] = kInf;
         way[c] = -1;
+        prop[c] = 0;
         if (j < m) {
-            lu[j] = 0.0;
-            lp[j] = -1;
+            double best = M[j];
+            int arg = 0;
+            for (int i = 1; i < m; ++i) {
+                const double x = M[(size_t)i * m + j];
+                if (x < best) {
+                    best = x;
+                    arg = i;
+                }
+            }
+            v[c] = best;
+            prop[c] = arg;
+            lw[j] = kNone;
+            lu[j] = best;
         }
     }
     __builtin_amdgcn_wave_barrier();
-    double th = 0.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        if (l + L * c < m) atomicMin(&lw[prop[c]], l + L * c);
+    __builtin_amdgcn_wave_barrier();
+    double th = lu[0];
+    for (int j = 1; j < m; ++j) th = th + lu[j];
+    unsigned long long unm = 0ull;  // rows left unmatched, group-uniform
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int j = l + L * c;
+        if (j < m) p[c] = (lw[prop[c]] == j) ? prop[c] : -1;
+        const unsigned long long b = __builtin_amdgcn_ballot_w64(j < m && lw[j] == kNone) & gmask;
+        unm |= (b >> gbase) << (L * c);
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int j = l + L * c;
+        if (j < m) {
+            lp[j] = p[c];
+            lu[j] = 0.0;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
     int st = 0;
-    int i0 = 0, r = 0, last = -1;
+    int i0 = unm ? __builtin_ctzll(unm) : m, r = 0, last = -1;
     bool fresh = true;
     while (i0 < m) {
         if (fresh) {
@@ -215,7 +255,8 @@ __device__ void lap_solve(const double *__restrict__ M, int m, int l, int gbase,
                 }
             }
             __builtin_amdgcn_wave_barrier();
-            ++i0;
+            unm &= unm - 1ull;
+            i0 = unm ? __builtin_ctzll(unm) : m;
             fresh = true;
         } else {
             if ((js % L) == l) used |= 1u << (js / L);

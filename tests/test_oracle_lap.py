@@ -80,46 +80,45 @@ def test_lap_rank_one_closed_form():
         assert th == closed
 
 
-def test_lap_zero_matrix_one_step_per_row():
-    """All-zero matrix: every row's search ends at once on the lowest unmatched
-    column (ties prefer unmatched columns), so m rows take m steps, the
-    assignment is the identity and all duals stay zero."""
+def test_lap_zero_matrix():
+    """All-zero matrix: the column reduction matches column 0 to row 0 (every
+    column proposes row 0, the lowest column wins); each other row's search
+    ends at once on the lowest unmatched column (ties prefer unmatched
+    columns): m - 1 steps, identity assignment, all duals zero."""
     for m in (1, 4, 28):
         th, u, v, rc, pi, steps = O.lap(np.zeros((m, m)))
-        assert th == 0.0 and steps == m
+        assert th == 0.0 and steps == m - 1
         assert rc.tolist() == list(range(m))
         assert not u.any() and not v.any()
 
 
 def test_lap_hand_worked_2x2():
     """M = [[1,2],[3,4]], worked by hand through the specified steps.
-    Row 0: minv = (1, 2) -> j* = 0, delta = 1, u0 = 1, col 0 <- row 0.
-    Row 1: minv = (3, 4) -> j* = 0 (matched), delta = 3, u1 = 3; scan row 0:
-    s_1 = (2 - 1) - 0 = 1 is not strictly below minv_1 = 1, so column 1 keeps
-    its link to the root; j* = 1, delta = 1: u1 = 4, u0 = 2, v0 = -1.
-    Column 1 is free: the path is just column 1, so row 1 takes column 1 and
-    row 0 keeps column 0.  theta = 1 + 3 + 1 = 5."""
+    Column reduction: v = (1, 2), both columns propose row 0, column 0 wins;
+    value starts at 1 + 2 = 3.  Row 1: s = (3-0-1, 4-0-2) = (2, 2), the tie
+    goes to the unmatched column 1, delta = 2: u1 = 2, value 5; column 1 is
+    free, so row 1 takes it."""
     th, u, v, rc, pi, steps = O.lap(np.array([[1.0, 2.0], [3.0, 4.0]]))
     assert th == 5.0
-    assert u.tolist() == [2.0, 4.0]
-    assert v.tolist() == [-1.0, 0.0]
+    assert u.tolist() == [0.0, 2.0]
+    assert v.tolist() == [1.0, 2.0]
     assert rc.tolist() == [0, 1]
-    assert steps == 3
+    assert steps == 1
     assert not pi.any()
 
 
 def test_lap_hand_worked_3x3_augmenting_path():
     """M = [[0,1,5],[0,4,5],[5,5,0]] by hand.
-    Row 0: minv = (0,1,5), j* = 0 free: col0 <- row0, delta 0.
-    Row 1: minv = (0,4,5): j* = 0 (matched, delta 0); scan row 0: s = (1,5)
-    for cols 1,2 improves col 1 to 1 (via col 0); j* = 1 free, delta = 1:
-    u1 = 1, u0 = 1, v0 = -1.  Path: col1 <- row0, col0 <- row1.
-    Row 2: minv = (6, 5, 0) -> j* = 2 free, delta 0.
-    Result: row0->col1, row1->col0, row2->col2, theta = 1."""
+    Column reduction: v = (0, 1, 0); columns 0 and 1 propose row 0 (column 0
+    wins), column 2 proposes row 2; value starts at 1.  Row 1: s = (0, 3, 5),
+    j* = 0 (matched to row 0), delta 0; scanning row 0 gives column 1
+    s = (1-0)-1 = 0 < 3 (via column 0); j* = 1 is free, delta 0.  Path:
+    column 1 <- row 0, column 0 <- row 1.  Result row0->col1, row1->col0,
+    row2->col2, theta = 1, u = 0, v = (0, 1, 0)."""
     M = np.array([[0.0, 1.0, 5.0], [0.0, 4.0, 5.0], [5.0, 5.0, 0.0]])
     th, u, v, rc, pi, steps = O.lap(M)
     assert th == 1.0
     assert rc.tolist() == [1, 0, 2]
-    assert u.tolist() == [1.0, 1.0, 0.0]
-    assert v.tolist() == [-1.0, 0.0, 0.0]
-    assert steps == 4
+    assert u.tolist() == [0.0, 0.0, 0.0]
+    assert v.tolist() == [0.0, 1.0, 0.0]
+    assert steps == 2
