@@ -117,6 +117,29 @@ typedef struct qap_bnb_stats {
     double seconds;
 } qap_bnb_stats;
 
+/* Node rules of qap_batch_dual_ascent (branch-and-bound control, Section 4
+ * and the early termination of Section 5.4).  Each handle runs at most
+ * `iters` more iterations and stops on its own when (a) its bound certifies
+ * its incumbent or its min_gap is reached, (b) it is fathomed against ub_cut
+ * (ceil(LB - tol) >= min(ub_cut, own UB) for integer data, tol =
+ * 1e-9*max(1,|UB|)), or (c) window > 0, min_improve > 0 and its bound rose
+ * by less than min_improve*max(1,|UB|) over the last `window` iterations. */
+typedef struct qap_batch_params {
+    int iters;
+    int window;
+    double min_improve;
+    double ub_cut;         /* +inf for none */
+} qap_batch_params;
+
+typedef struct qap_batch_stats {
+    long long iterations;  /* iterations of all handles so far (sum of t) */
+    int stopped;           /* handles stopped */
+    int fathomed;          /* ... by rule (a) or (b) */
+    int window_stops;      /* ... by rule (c) */
+    int pad;
+    double seconds;
+} qap_batch_stats;
+
 /* State header of qap_export_state / qap_import_state. */
 typedef struct qap_state_header {
     int n;
@@ -184,13 +207,42 @@ int qap_import_state(qap_handle h, const qap_state_header *hdr, const double *x,
 /* Use the given HIP stream (hipStream_t passed as void*) for all work. */
 int qap_set_stream(qap_handle h, void *hip_stream);
 
-/* Solve the QAP held by h to optimality by depth-first branch-and-bound
- * (Section 4): polytomic branching in Rule-3 facility order, children warm
- * started from the parent's reduced costs, node dual ascents batched on the
- * device.  perm_out (host, n): optimal permutation; *obj_out its exact cost.
- * p NULL selects the defaults. */
+/* Solve the QAP held by h to optimality by branch-and-bound (Section 4):
+ * polytomic branching in Rule-3 facility order, children warm started from
+ * the parent's reduced costs (qap_fold_child), up to p->batch open nodes of
+ * uneven size per batched dual ascent (qap_batch_dual_ascent), taken
+ * depth-first from a stack; nodes with at most enum_below free facilities
+ * are enumerated.  h's own state is not changed (the root restarts from the
+ * initial costs).  perm_out (host, n): optimal permutation; *obj_out its
+ * exact cost.  p NULL selects the defaults.  Errors: QAP_EUNSUPPORTED
+ * (n > 24), QAP_ESTATE (no permutation below ub0), QAP_EINVAL. */
 int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, double *obj_out,
                   qap_bnb_stats *st);
+
+/* Warm-start a child node from h's current reduced costs (the children of a
+ * branch-and-bound node start from their parent's multipliers, Section 4):
+ * fix facility l to location s (indices of h's own problem, 0-based).  The
+ * child is a handle of size n-1 whose QAP is h's restricted to the other
+ * facilities and locations, with the fixed pair's cross terms folded into its
+ * fixed costs and its constant cost added to an internal offset, so its
+ * incumbents are full-problem costs.  Its bound starts at h's bound plus
+ * pi_x[l][s]; every reduced-cost entry that holds (l,s) moves one level down
+ * and the rest is restricted; it runs from t = 0.  h must have run at least
+ * one iteration.  The child shares h's stream.  Errors: QAP_ESTATE (no
+ * iteration yet), QAP_EUNSUPPORTED (n < 4), QAP_EINVAL, QAP_ENOMEM. */
+int qap_fold_child(qap_handle h, int l, int s, qap_handle *child);
+
+/* Advance `count` independent handles (sizes may differ, one device) by one
+ * set of batched kernels per phase and iteration, replayed from one HIP
+ * graph, with the node rules above.  Each handle's trajectory is exactly the
+ * one qap_dual_ascent would produce until it stops.  hs: host array of
+ * handles; st nullable. */
+int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_stats *st);
+
+/* Scalars of a handle: iterations run, bound, incumbent, stop flag and the
+ * batch rule that stopped it (0 none, 1 certificate/fathomed, 2 window,
+ * 3 min_gap).  Pointers nullable. */
+int qap_node_status(qap_handle h, int *t, double *lb, double *ub, int *stopped, int *reason);
 
 /* Batched LAP solver (the Hungarian method used for every Z-, Y- and X-LAP,
  * Section 2.3 "LAP Solution"), exposed for validation.  cost: device,

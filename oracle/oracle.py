@@ -56,8 +56,10 @@ def lib():
         L.orc_da_identity.restype = C.c_double
         L.orc_da_min_entries.argtypes = [C.c_void_p, _dp]
         L.orc_rule3_order.argtypes = [C.c_int, _dp, _ip]
-        L.orc_da_fold.argtypes = [C.c_void_p, C.c_int, C.c_int, _dp, _dp, _dp]
+        L.orc_da_fold.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.orc_da_fold.restype = C.c_void_p
+        L.orc_da_offset.argtypes = [C.c_void_p]
+        L.orc_da_offset.restype = C.c_double
         L.orc_bnb.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_int, C.c_int, C.c_double,
                               C.c_double, _ip, _dp, C.POINTER(C.c_longlong)]
         L.orc_glb_bnb.argtypes = [C.c_int, _dp, _dp, _dp, C.c_double, _ip, _dp,
@@ -66,6 +68,10 @@ def lib():
         L.orc_da_create_xy.restype = C.c_void_p
         L.orc_da_iter0_xy.argtypes = [C.c_void_p]
         L.orc_iter1_tile.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
+        L.orc_da_track.argtypes = [C.c_void_p]
+        L.orc_da_multipliers.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_da_from_multipliers.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_da_from_multipliers.restype = C.c_void_p
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_max_threads.restype = C.c_int
         _lib = L
@@ -237,16 +243,48 @@ class DualAscent:
         return float(lib().orc_da_identity(self.h, _i(perm)))
 
     def fold(self, l: int, s: int):
-        """Child state after fixing local facility l to local location s."""
-        F, D, _ = self._keep
+        """Child state after fixing local facility l to local location s (a
+        self-contained QAP on the free indices plus a constant offset)."""
+        F, D, B = self._keep
         keep_f = [a for a in range(self.n) if a != l]
         keep_l = [a for a in range(self.n) if a != s]
         Fc = _f64(F[np.ix_(keep_f, keep_f)])
         Dc = _f64(D[np.ix_(keep_l, keep_l)])
-        h = lib().orc_da_fold(self.h, int(l), int(s), _d(Fc), _d(Dc), _d(self._params))
+        Bc = _f64((B[np.ix_(keep_f, keep_l)] + np.outer(F[keep_f, l], D[keep_l, s]))
+                  + np.outer(F[l, keep_f], D[s, keep_l]))
+        h = lib().orc_da_fold(self.h, int(l), int(s))
         if not h:
             raise ValueError("fold: bad arguments")
-        return DualAscent(Fc, Dc, None, tuple(self._params), _handle=h)
+        return DualAscent(Fc, Dc, Bc, tuple(self._params), _handle=h)
+
+    def track(self):
+        if lib().orc_da_track(self.h) != 0:
+            raise MemoryError("tracking arrays")
+
+    def multipliers(self):
+        n = self.n
+        V = np.zeros((n,) * 6)
+        U = np.zeros((n,) * 4)
+        lib().orc_da_multipliers(self.h, _d(V), _d(U))
+        return V, U
+
+    @classmethod
+    def from_multipliers(cls, F, D, B, params, V, U):
+        F, D = _f64(F), _f64(D)
+        B = np.zeros_like(F) if B is None else _f64(B)
+        P = _f64(params)
+        Vp = None if V is None else _d(_f64(V))
+        Up = None if U is None else _d(_f64(U))
+        keepV = None if V is None else _f64(V)
+        keepU = None if U is None else _f64(U)
+        h = lib().orc_da_from_multipliers(F.shape[0], _d(F), _d(D), _d(B), _d(P),
+                                          None if keepV is None else _d(keepV),
+                                          None if keepU is None else _d(keepU))
+        return cls(F, D, B, params, _handle=h)
+
+    @property
+    def offset(self) -> float:
+        return float(lib().orc_da_offset(self.h))
 
     def min_entries(self):
         out = np.zeros(3)

@@ -298,6 +298,7 @@ typedef struct orc_da {
     double kz, ky, kx, phi, phiy;
     double okz, oky, okx, ky2, kx3, ophiy;
     double *F, *D, *B;      /* original data, n^2 each (for exact UB) */
+    double offset;          /* constant added to every permutation cost (fixed pairs of a B&B node) */
     int integer_data;
     double *X, *Y, *Z;
     double LB, UB;
@@ -307,6 +308,7 @@ typedef struct orc_da {
     long long lap_steps;
     double *trace;          /* LB after each iteration */
     int trace_len, trace_cap;
+    double *Vt, *Ut;        /* tracked S-form multipliers v (n^6), u (n^4), or NULL */
 } orc_da;
 
 static void orc_da_derive(orc_da *s)
@@ -328,6 +330,7 @@ void orc_da_free(orc_da *s)
     free(s->F); free(s->D); free(s->B);
     free(s->X); free(s->Y); free(s->Z);
     free(s->xperm); free(s->best_perm); free(s->trace);
+    free(s->Vt); free(s->Ut);
     free(s);
 }
 
@@ -383,6 +386,7 @@ orc_da *orc_da_create(int n, const double *F, const double *D, const double *B,
     s->LB = 0.0;
     s->UB = HUGE_VAL;
     s->t = 0;
+    s->offset = 0.0;
     return s;
 }
 
@@ -450,6 +454,7 @@ void orc_da_sweep(orc_da *s)
                                     else acc = acc + g[f];
                                 }
                                 Z[zi[e]] = s->okz * pz[e] + s->phi * acc;
+                                if (s->Vt) s->Vt[zi[e]] = s->Vt[zi[e]] + (g[e] - s->phi * acc);
                             }
                         }
                     }
@@ -514,6 +519,10 @@ void orc_da_yequal(orc_da *s)
                     double ya = Y[a], yb = Y[b];
                     Y[a] = s->ophiy * ya + s->phiy * yb;
                     Y[b] = s->ophiy * yb + s->phiy * ya;
+                    if (s->Ut) {
+                        s->Ut[a] = s->Ut[a] + s->phiy * (ya - yb);
+                        s->Ut[b] = s->Ut[b] + s->phiy * (yb - ya);
+                    }
                 }
 }
 
@@ -567,7 +576,7 @@ void orc_da_xphase(orc_da *s)
             s->X[IX2(n, a, b)] = (M[IX2(n, a, b)] - u[a]) - v[b];
     s->LB = s->LB + th;
     for (int j = 0; j < n; ++j) s->xperm[rc[j]] = j;
-    orc_record_ub(s, s->xperm, orc_qap_cost(n, s->F, s->D, s->B, s->xperm));
+    orc_record_ub(s, s->xperm, orc_qap_cost(n, s->F, s->D, s->B, s->xperm) + s->offset);
     free(M);
 }
 
@@ -642,6 +651,43 @@ void orc_da_export(const orc_da *s, double *X, double *Y, double *Z)
     if (X) memcpy(X, s->X, sizeof(double) * n2);
     if (Y) memcpy(Y, s->Y, sizeof(double) * n4);
     if (Z) memcpy(Z, s->Z, sizeof(double) * n4 * n2);
+}
+
+/* Multiplier tracking.  The F1 transfers are Lagrange multiplier updates in
+ * the sense of the ascent rules: per sweep, entry e's multiplier moves by
+ * g_e - phi * sum_{f != e} g_f (Eq. ch4:proof:2: its own kappa-shares minus
+ * Omega_e), per y-pair rule u_ijpq moves by phy * (a - b) (Eq. da:yrule1).
+ * Both are zero-sum over an orbit / a pair.  Tracking starts at zero. */
+int orc_da_track(orc_da *s)
+{
+    size_t n2 = (size_t)s->n * s->n, n4 = n2 * n2;
+    if (!s->Vt) s->Vt = calloc(n4 * n2, sizeof(double));
+    if (!s->Ut) s->Ut = calloc(n4, sizeof(double));
+    return (s->Vt && s->Ut) ? 0 : -1;
+}
+
+void orc_da_multipliers(const orc_da *s, double *V, double *U)
+{
+    size_t n2 = (size_t)s->n * s->n, n4 = n2 * n2;
+    if (V && s->Vt) memcpy(V, s->Vt, sizeof(double) * n4 * n2);
+    if (U && s->Ut) memcpy(U, s->Ut, sizeof(double) * n4);
+}
+
+/* Lagrangian relaxation LRLT2(u, v) in its initial form (Algorithm 1 step 1
+ * with given multipliers): x costs b + f_ii d_pp, y costs C - u, z costs
+ * D - v = -v, LB = 0; any zero-sum u, v keep every bound valid (Eq.
+ * lgduality). */
+orc_da *orc_da_from_multipliers(int n, const double *F, const double *D, const double *B,
+                                const double *params, const double *V, const double *U)
+{
+    orc_da *s = orc_da_create(n, F, D, B, params);
+    if (!s) return NULL;
+    size_t n2 = (size_t)n * n, n4 = n2 * n2;
+    if (U)
+        for (size_t a = 0; a < n4; ++a) s->Y[a] = s->Y[a] - U[a];
+    if (V)
+        for (size_t a = 0; a < n4 * n2; ++a) s->Z[a] = 0.0 - V[a];
+    return s;
 }
 
 /* O3. Reformulation identity: LB plus the reduced costs picked by perm. */
@@ -889,10 +935,12 @@ void orc_rule3_order(int n, const double *F, int *order)
 }
 
 /* Child state for fixing facility l to location sidx (local indices of the
- * parent), per the fold described above.  Fc, Dc are the child's own
- * (restricted) flow and distance matrices, (n-1) x (n-1). */
-orc_da *orc_da_fold(const orc_da *s, int l, int sidx, const double *Fc, const double *Dc,
-                    const double *params)
+ * parent), per the fold described above.  The child is itself a QAP on the
+ * free facilities and locations: F and D restricted, the fixed pair's cross
+ * terms folded into the fixed costs, b'_ip = (b_ip + f_il d_ps) + f_li d_sp,
+ * and its own constant b_ls + f_ll d_ss added to the parent's offset, so
+ * that every child permutation's cost (plus offset) is the full QAP cost. */
+orc_da *orc_da_fold(const orc_da *s, int l, int sidx)
 {
     int n = s->n, n1 = n - 1;
     if (n1 < 3 || l < 0 || l >= n || sidx < 0 || sidx >= n) return NULL;
@@ -901,9 +949,19 @@ orc_da *orc_da_fold(const orc_da *s, int l, int sidx, const double *Fc, const do
     a = 0;
     for (int t = 0; t < n; ++t) if (t != sidx) li[a++] = t;
     size_t m2 = (size_t)n1 * n1, m4 = m2 * m2, m6 = m4 * m2;
+    double *Fc = malloc(sizeof(double) * m2), *Dc = malloc(sizeof(double) * m2);
+    double *Bc = malloc(sizeof(double) * m2);
     double *Xc = malloc(sizeof(double) * m2);
     double *Yc = calloc(m4, sizeof(double));
     double *Zc = calloc(m6, sizeof(double));
+    for (int a1 = 0; a1 < n1; ++a1)
+        for (int a2 = 0; a2 < n1; ++a2) {
+            Fc[IX2(n1, a1, a2)] = s->F[IX2(n, fi[a1], fi[a2])];
+            Dc[IX2(n1, a1, a2)] = s->D[IX2(n, li[a1], li[a2])];
+            int i = fi[a1], p = li[a2];
+            Bc[IX2(n1, a1, a2)] = (s->B[IX2(n, i, p)] + s->F[IX2(n, i, l)] * s->D[IX2(n, p, sidx)]) +
+                                  s->F[IX2(n, l, i)] * s->D[IX2(n, sidx, p)];
+        }
     for (int a1 = 0; a1 < n1; ++a1)
         for (int b1 = 0; b1 < n1; ++b1) {
             int i = fi[a1], p = li[b1];
@@ -929,11 +987,15 @@ orc_da *orc_da_fold(const orc_da *s, int l, int sidx, const double *Fc, const do
                     }
                 }
         }
+    double params[5] = {s->kz, s->ky, s->kx, s->phi, s->phiy};
     double lbc = s->LB + s->X[IX2(n, l, sidx)];
-    orc_da *cs = orc_da_from_arrays(n1, Fc, Dc, NULL, params, lbc, Xc, Yc, Zc);
-    free(Xc); free(Yc); free(Zc);
+    orc_da *cs = orc_da_from_arrays(n1, Fc, Dc, Bc, params, lbc, Xc, Yc, Zc);
+    if (cs) cs->offset = s->offset + (s->B[IX2(n, l, sidx)] + s->F[IX2(n, l, l)] * s->D[IX2(n, sidx, sidx)]);
+    free(Fc); free(Dc); free(Bc); free(Xc); free(Yc); free(Zc);
     return cs;
 }
+
+double orc_da_offset(const orc_da *s) { return s->offset; }
 
 static int fathomed(double LB, double UB, int integer_data)
 {
@@ -1002,14 +1064,7 @@ static void bnb_node(orc_bnb_ctx *c, int depth, int *perm, const int *fac, const
             enumerate_completions(c, perm, cfac, cloc, n1);
             continue;
         }
-        double *Fc = malloc(sizeof(double) * (size_t)n1 * n1), *Dc = malloc(sizeof(double) * (size_t)n1 * n1);
-        for (int a1 = 0; a1 < n1; ++a1)
-            for (int a2 = 0; a2 < n1; ++a2) {
-                Fc[IX2(n1, a1, a2)] = c->F[IX2(c->n, cfac[a1], cfac[a2])];
-                Dc[IX2(n1, a1, a2)] = c->D[IX2(c->n, cloc[a1], cloc[a2])];
-            }
-        orc_da *cs = orc_da_fold(s, l, sidx, Fc, Dc, c->params);
-        free(Fc); free(Dc);
+        orc_da *cs = orc_da_fold(s, l, sidx);
         bnb_node(c, depth + 1, perm, cfac, cloc, n1, cs);
         orc_da_free(cs);
     }

@@ -50,6 +50,16 @@ class QapBnbStats(C.Structure):
                 ("enumerated", C.c_longlong), ("seconds", C.c_double)]
 
 
+class QapBatchParams(C.Structure):
+    _fields_ = [("iters", C.c_int), ("window", C.c_int), ("min_improve", C.c_double),
+                ("ub_cut", C.c_double)]
+
+
+class QapBatchStats(C.Structure):
+    _fields_ = [("iterations", C.c_longlong), ("stopped", C.c_int), ("fathomed", C.c_int),
+                ("window_stops", C.c_int), ("pad", C.c_int), ("seconds", C.c_double)]
+
+
 class QapStateHeader(C.Structure):
     _fields_ = [("n", C.c_int), ("t", C.c_int), ("lb", C.c_double), ("ub", C.c_double),
                 ("checksum", C.c_uint64)]
@@ -62,7 +72,8 @@ _lib = None
 EXPORTED = ("qap_version", "qap_default_params", "qap_workspace_bytes", "qap_rlt2_init",
             "qap_destroy", "qap_dual_ascent", "qap_get_trace", "qap_get_assignment",
             "qap_export_state", "qap_export_z_tiles", "qap_import_state", "qap_set_stream", "qap_bnb_solve",
-            "qap_lap_batch", "qap_last_error")
+            "qap_lap_batch", "qap_last_error", "qap_fold_child", "qap_batch_dual_ascent",
+            "qap_node_status")
 
 
 def lib():
@@ -89,6 +100,12 @@ def lib():
                                     C.POINTER(QapBnbStats)]
         L.qap_lap_batch.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+        L.qap_fold_child.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_void_p)]
+        L.qap_batch_dual_ascent.argtypes = [C.POINTER(C.c_void_p), C.c_int,
+                                            C.POINTER(QapBatchParams), C.POINTER(QapBatchStats)]
+        L.qap_node_status.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double), C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int)]
         L.qap_last_error.argtypes = [C.c_void_p]
         L.qap_last_error.restype = C.c_char_p
         _lib = L
@@ -138,7 +155,16 @@ def tile_count(n: int) -> int:
 class DualAscent:
     """Handle of one RLT2 dual-ascent state on the GPU."""
 
-    def __init__(self, F, D, B=None, params: QapParams | None = None, **kw):
+    def __init__(self, F, D, B=None, params: QapParams | None = None, _handle=None, _n=None,
+                 _parent=None, **kw):
+        if _handle is not None:
+            self.h = _handle
+            self.n = _n
+            self.T = tile_count(_n)
+            self.m = _n - 2
+            self.params = _parent.params
+            self._parent = _parent  # children share the parent's stream
+            return
         F, D = _f64(F), _f64(D)
         n = F.shape[0]
         self.n = n
@@ -212,6 +238,24 @@ class DualAscent:
         x, y, z = _f64(x), _f64(y), _f64(z)
         _check(lib().qap_import_state(self.h, C.byref(hdr), _dptr(x), _dptr(y), _dptr(z)), self.h)
 
+    def fold(self, l: int, s: int) -> "DualAscent":
+        """Child node fixing facility l to location s (0-based, this
+        handle's own indices), warm-started from the current reduced costs."""
+        h = C.c_void_p()
+        _check(lib().qap_fold_child(self.h, int(l), int(s), C.byref(h)), self.h)
+        return DualAscent(None, None, _handle=h, _n=self.n - 1, _parent=self)
+
+    def status(self):
+        t = C.c_int(0)
+        lb = C.c_double(0.0)
+        ub = C.c_double(0.0)
+        stopped = C.c_int(0)
+        reason = C.c_int(0)
+        _check(lib().qap_node_status(self.h, C.byref(t), C.byref(lb), C.byref(ub),
+                                     C.byref(stopped), C.byref(reason)), self.h)
+        return {"t": t.value, "lb": lb.value, "ub": ub.value, "stopped": bool(stopped.value),
+                "reason": reason.value}
+
     def set_stream(self, stream_handle: int):
         _check(lib().qap_set_stream(self.h, C.c_void_p(stream_handle)), self.h)
 
@@ -226,6 +270,18 @@ class DualAscent:
         return obj.value, perm, {"nodes": st.nodes, "da_iters": st.da_iters,
                                  "batches": st.batches, "enumerated": st.enumerated,
                                  "seconds": st.seconds}
+
+
+def batch_run(handles, iters: int, window: int = 0, min_improve: float = 0.0,
+              ub_cut: float = float("inf")):
+    """Advance several DualAscent handles (any sizes) with the batched kernels."""
+    arr = (C.c_void_p * len(handles))(*[hd.h.value for hd in handles])
+    bp = QapBatchParams(int(iters), int(window), float(min_improve), float(ub_cut))
+    st = QapBatchStats()
+    code = lib().qap_batch_dual_ascent(arr, len(handles), C.byref(bp), C.byref(st))
+    _check(code, handles[0].h if handles else None)
+    return {"iterations": st.iterations, "stopped": st.stopped, "fathomed": st.fathomed,
+            "window_stops": st.window_stops, "seconds": st.seconds}
 
 
 def lap_batch(cost, lanes: int = 0, cols: int = 0, stream: int | None = None):

@@ -1,0 +1,429 @@
+// batch.hpp -- many independent dual ascents of uneven size n advanced in
+// lockstep by one set of kernels per phase (the branch-and-bound nodes of
+// Section 4 on one GPU), plus the child fold that warm-starts a node from its
+// parent's reduced costs.
+//
+// A batch is a table of node descriptors.  Each per-phase kernel flattens the
+// work of all nodes (tiles, Y-LAPs, orbit cubes, entries) into one grid; a
+// block or lane group finds its node by binary search in a prefix table.
+// Every node keeps its own iteration counter and stop flag in its DevScalars,
+// so the same kernel sequence serves every iteration and is replayed from one
+// HIP graph; stopped nodes cost one flag read per job.
+//
+// The arithmetic of every node is exactly that of the single-instance kernels
+// in kernels.hpp (same expressions, same order), so a node's trajectory does
+// not depend on what else is in its batch.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace qap {
+
+struct BNode {
+    double *Z, *Yc, *Py, *Xc, *Px, *alpha, *beta, *trace;
+    const double *F, *D, *B;
+    int *xperm, *bestperm;
+    DevScalars *S;
+    unsigned long long *bins;
+    const int *triples;
+    long long T;
+    int n, m, ntri, nb;
+    int integer_data;
+    int trace_cap;
+    double offset, min_gap;
+    double kz, okz, ky2, kx3, phi, oky, okx, phy, ophy;
+};
+
+// Node-level stop rules of a batch (branch-and-bound control, Section 4/5.4):
+// besides the per-node min_gap and optimality certificate, a node stops when
+// its bound fathoms against ub_cut, or when over `window` iterations its
+// bound rose by less than min_improve * max(1, |UB|) (reason 2 = branch).
+struct BatchCtl {
+    double ub_cut;       // incumbent at batch start (+inf if none)
+    double min_improve;  // 0 disables the window rule
+    int window;
+    int nnodes;
+};
+
+struct BatchPrefix {
+    const long long *zl;  // tiles
+    const long long *yl;  // Y-LAPs (n^2)
+    const long long *sw;  // sweep blocks (triples * nb^3)
+    const long long *sc;  // scale elements (T + n^2)
+};
+
+__device__ __forceinline__ int find_node(const long long *pre, int nnodes, long long j)
+{
+    int lo = 0, hi = nnodes - 1;  // largest b with pre[b] <= j
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= j)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// ----------------------------------------------------------------- sweep --
+__global__ __launch_bounds__(256) void k_bsweep(const BNode *__restrict__ nodes, BatchPrefix pf, int nnodes)
+{
+    __shared__ double gs[6 * SB_CUBE];
+    const long long jb = blockIdx.x;
+    if (jb >= pf.sw[nnodes]) return;
+    const int b = find_node(pf.sw, nnodes, jb);
+    const BNode &N = nodes[b];
+    if (N.S->stopped || N.S->t < 1) return;
+    const int nb = N.nb, n = N.n;
+    const int local = (int)(jb - pf.sw[b]);
+    const int nb3 = nb * nb * nb;
+    const int tri = local / nb3, sub = local % nb3;
+    const int base[3] = {(sub / (nb * nb)) * SB, ((sub / nb) % nb) * SB, (sub % nb) * SB};
+    const int packed = N.triples[tri];
+    const int fi = packed & 0xff, fj = (packed >> 8) & 0xff, fk = (packed >> 16) & 0xff;
+    const int m = N.m;
+    const long long mm = (long long)m * m;
+    double *Z = N.Z;
+    const int F1[6] = {fi, fi, fj, fj, fk, fk};
+    const int F2[6] = {fj, fk, fi, fk, fi, fj};
+    const int F3[6] = {fk, fj, fk, fi, fj, fi};
+    const int X1[6] = {0, 0, 1, 1, 2, 2};
+    const int X2[6] = {1, 2, 0, 2, 0, 1};
+    const int X3[6] = {2, 1, 2, 0, 1, 0};
+    constexpr int PER = (SB * SB * SB) / 256;
+    long long za[6][PER];
+    int li[6][PER];
+    bool ok[6][PER];
+    double pz[6][PER];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+#pragma unroll
+        for (int w = 0; w < PER; ++w) {
+            const int u = threadIdx.x + 256 * w;
+            const int a3 = u % SB, a2 = (u / SB) % SB, a1 = u / (SB * SB);
+            int loc[3];
+            loc[X1[e]] = base[X1[e]] + a1;
+            loc[X2[e]] = base[X2[e]] + a2;
+            loc[X3[e]] = base[X3[e]] + a3;
+            const int l1 = loc[X1[e]], l2 = loc[X2[e]], l3 = loc[X3[e]];
+            const bool v = l1 < n && l2 < n && l3 < n && l1 != l2 && l1 != l3 && l2 != l3;
+            const int f1 = F1[e], f2 = F2[e], f3 = F3[e];
+            const long long t = v ? tile_of(n, f1, l1, f2, l2) : 0;
+            const int row = f3 - (f3 > f1) - (f3 > f2);
+            const int col = v ? (l3 - (l3 > l1) - (l3 > l2)) : 0;
+            ok[e][w] = v;
+            za[e][w] = t * mm + (long long)row * m + col;
+            li[e][w] = cube_idx(loc[0] - base[0], loc[1] - base[1], loc[2] - base[2]);
+            pz[e][w] = v ? Z[za[e][w]] : 0.0;
+            if (v) gs[e * SB_CUBE + li[e][w]] = (N.kz * pz[e][w] + N.ky2 * N.Py[t]) + N.kx3 * N.Px[f1 * n + l1];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < PER; ++w) {
+        const int u = threadIdx.x + 256 * w;
+        const int rl = u % SB, ql = (u / SB) % SB, pl = u / (SB * SB);
+        const int p = base[0] + pl, q = base[1] + ql, r = base[2] + rl;
+        if (p < n && q < n && r < n && p != q && p != r && q != r) {
+            const int c = cube_idx(pl, ql, rl);
+            double g[6];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) g[e] = gs[e * SB_CUBE + c];
+            gs[0 * SB_CUBE + c] = N.phi * ((((g[1] + g[2]) + g[3]) + g[4]) + g[5]);
+            gs[1 * SB_CUBE + c] = N.phi * ((((g[0] + g[2]) + g[3]) + g[4]) + g[5]);
+            gs[2 * SB_CUBE + c] = N.phi * ((((g[0] + g[1]) + g[3]) + g[4]) + g[5]);
+            gs[3 * SB_CUBE + c] = N.phi * ((((g[0] + g[1]) + g[2]) + g[4]) + g[5]);
+            gs[4 * SB_CUBE + c] = N.phi * ((((g[0] + g[1]) + g[2]) + g[3]) + g[5]);
+            gs[5 * SB_CUBE + c] = N.phi * ((((g[0] + g[1]) + g[2]) + g[3]) + g[4]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+#pragma unroll
+        for (int w = 0; w < PER; ++w)
+            if (ok[e][w]) Z[za[e][w]] = N.okz * pz[e][w] + gs[e * SB_CUBE + li[e][w]];
+}
+
+// The x/y scaling after the sweep has read pi_x, pi_y.
+__global__ void k_bscale(const BNode *__restrict__ nodes, BatchPrefix pf, int nnodes)
+{
+    const long long total = pf.sc[nnodes];
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int b = find_node(pf.sc, nnodes, e);
+        const BNode &N = nodes[b];
+        if (N.S->stopped || N.S->t < 1) continue;
+        const long long a = e - pf.sc[b];
+        if (a < N.T)
+            N.Yc[a] = N.oky * N.Py[a];
+        else
+            N.Xc[a - N.T] = N.okx * N.Px[a - N.T];
+    }
+}
+
+// ----------------------------------------------------------------- Z-LAP --
+// One group of L lanes per tile; LDS per group sized for the batch's largest m.
+template <int L>
+__global__ __launch_bounds__(256) void k_bzlap(const BNode *__restrict__ nodes, BatchPrefix pf, int nnodes,
+                                               int mmax)
+{
+    extern __shared__ double lds[];
+    const int G = blockDim.x / L;
+    const int g = threadIdx.x / L, l = threadIdx.x % L;
+    const int gbase = (threadIdx.x & 63) - l;
+    const long long jg = (long long)blockIdx.x * G + g;
+    const int per = mmax * mmax + 2 * mmax;
+    double *M = lds + (size_t)g * per;
+    bool live = jg < pf.zl[nnodes];
+    int b = 0;
+    if (live) {
+        b = find_node(pf.zl, nnodes, jg);
+        live = !nodes[b].S->stopped;
+    }
+    if (!live) return;  // whole groups leave together; no block barrier below
+    const BNode &N = nodes[b];
+    const int m = N.m, mm = m * m;
+    const long long t = jg - pf.zl[b];
+    double *src = N.Z + t * mm;
+    for (int e = l; e < mm; e += L) M[e] = src[e];
+    double *lu = M + mm;
+    int *lp = (int *)(lu + m);
+    int *lw = lp + m;
+    __builtin_amdgcn_wave_barrier();
+    double u[1], v[1], th;
+    int pc[1], st = 0;
+    lap_solve<L, 1>(M, m, l, gbase, lu, lp, lw, u, v, pc, th, st);
+    __builtin_amdgcn_wave_barrier();
+    double *vs = lu + m;
+    if (l < m) vs[l] = v[0];
+    __builtin_amdgcn_wave_barrier();
+    for (int e = l; e < mm; e += L) src[e] = (M[e] - lu[e / m]) - vs[e % m];
+    if (l == 0) {
+        N.Yc[t] = N.Yc[t] + th;
+        atomicAdd(&N.bins[jg & (kStepBins - 1)], (unsigned long long)st);
+    }
+}
+
+// ----------------------------------------------------------------- Y-LAP --
+template <int L>
+__global__ __launch_bounds__(256) void k_bylap(const BNode *__restrict__ nodes, BatchPrefix pf, int nnodes,
+                                               int mmax)
+{
+    extern __shared__ double lds[];
+    const int G = blockDim.x / L;
+    const int g = threadIdx.x / L, l = threadIdx.x % L;
+    const int gbase = (threadIdx.x & 63) - l;
+    const long long jg = (long long)blockIdx.x * G + g;
+    const int per = mmax * mmax + 2 * mmax;
+    double *M = lds + (size_t)g * per;
+    bool live = jg < pf.yl[nnodes];
+    int b = 0;
+    if (live) {
+        b = find_node(pf.yl, nnodes, jg);
+        live = !nodes[b].S->stopped;
+    }
+    if (!live) return;
+    const BNode &N = nodes[b];
+    const int n = N.n, m = n - 1, mm = m * m;
+    const int ip = (int)(jg - pf.yl[b]);
+    const int i = ip / n, p = ip % n;
+    const bool equalize = N.S->t >= 1;
+    const long long base = (long long)ip * mm;
+    for (int e = l; e < mm; e += L) {
+        double a = N.Yc[base + e];
+        if (equalize) {
+            const int jp = e / m, qp = e % m;
+            const int j = jp + (jp >= i), q = qp + (qp >= p);
+            const long long tb = ((long long)(j * n + q) * m + (i - (i > j))) * m + (p - (p > q));
+            a = N.ophy * a + N.phy * N.Yc[tb];
+        }
+        M[e] = a;
+    }
+    double *lu = M + mm;
+    int *lp = (int *)(lu + m);
+    int *lw = lp + m;
+    __builtin_amdgcn_wave_barrier();
+    double u[1], v[1], th;
+    int pc[1], st = 0;
+    lap_solve<L, 1>(M, m, l, gbase, lu, lp, lw, u, v, pc, th, st);
+    __builtin_amdgcn_wave_barrier();
+    double *vs = lu + m;
+    if (l < m) vs[l] = v[0];
+    __builtin_amdgcn_wave_barrier();
+    for (int e = l; e < mm; e += L) N.Py[base + e] = (M[e] - lu[e / m]) - vs[e % m];
+    if (l == 0) {
+        N.Xc[ip] = N.Xc[ip] + th;
+        atomicAdd(&N.bins[jg & (kStepBins - 1)], (unsigned long long)st);
+    }
+}
+
+// ----------------------------------------------------------------- X-LAP --
+// One wavefront per node: the single-instance X-LAP step (bound, incumbent
+// with the node's constant offset, certificate, min_gap) plus the batch's
+// fathoming and window rules.  S->reason: 1 = optimality certificate or
+// fathomed, 2 = window rule, 3 = min_gap.
+__global__ __launch_bounds__(64) void k_bxlap(const BNode *__restrict__ nodes, BatchCtl ctl)
+{
+    const BNode &N = nodes[blockIdx.x];
+    DevScalars *S = N.S;
+    if (S->stopped) return;
+    __shared__ double M[64 * 64];
+    __shared__ double lu[64], vs[64];
+    __shared__ int lp[64], lw[64];
+    __shared__ int sig[64];
+    __shared__ int improved;
+    const int l = threadIdx.x;
+    const int n = N.n, nn = n * n;
+    for (int e = l; e < nn; e += 64) M[e] = N.Xc[e];
+    __syncthreads();
+    double u[1], v[1], th;
+    int pc[1], st = 0;
+    lap_solve<64, 1>(M, n, l, 0, lu, lp, lw, u, v, pc, th, st);
+    if (l < n) {
+        vs[l] = v[0];
+        N.alpha[l] = u[0];
+        N.beta[l] = v[0];
+        sig[pc[0]] = l;
+    }
+    __syncthreads();
+    for (int e = l; e < nn; e += 64) N.Px[e] = (M[e] - lu[e / n]) - vs[e % n];
+    double cd = 0.0;
+    long long ci = 0;
+    if (l < n) {
+        const int si = sig[l];
+        if (N.integer_data) {
+            ci = (long long)N.B[l * n + si];
+            for (int jj = 0; jj < n; ++jj) ci += (long long)N.F[l * n + jj] * (long long)N.D[si * n + sig[jj]];
+        } else {
+            cd = N.B[l * n + si];
+            for (int jj = 0; jj < n; ++jj) cd = cd + N.F[l * n + jj] * N.D[si * n + sig[jj]];
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        ci += __shfl_xor(ci, off, 64);
+        cd += __shfl_xor(cd, off, 64);
+    }
+    if (l == 0) {
+        const double cost = (N.integer_data ? (double)ci : cd) + N.offset;
+        const double lb = S->lb + th;
+        S->lb = lb;
+        double ub = S->ub;
+        const bool better = cost < ub;
+        if (better) {
+            ub = cost;
+            S->ub = ub;
+        }
+        S->steps += (unsigned long long)st;
+        const int t = S->t;
+        if (t < N.trace_cap) N.trace[t] = lb;
+        S->t = t + 1;
+        int proven = 0;
+        if (ub < kInf) {
+            const double tol = 1e-9 * fmax(1.0, fabs(ub));
+            proven = N.integer_data ? (ceil(lb - tol) >= ub) : (ub - lb <= tol);
+        }
+        S->proven = proven;
+        int stop = proven, reason = proven ? 1 : 0;
+        if (!stop && N.min_gap > 0.0 && ub < kInf && ub != 0.0 && (ub - lb) / fabs(ub) < N.min_gap) {
+            stop = 1;
+            reason = 3;
+        }
+        const double cut = ub < ctl.ub_cut ? ub : ctl.ub_cut;
+        if (!stop && cut < kInf) {
+            const double tol = 1e-9 * fmax(1.0, fabs(cut));
+            const bool fath = N.integer_data ? (ceil(lb - tol) >= cut) : (lb >= cut - tol);
+            if (fath) {
+                stop = 1;
+                reason = 1;
+            }
+        }
+        if (!stop && ctl.min_improve > 0.0 && t + 1 > ctl.window && t + 1 - ctl.window - 1 >= 0 &&
+            t + 1 - ctl.window - 1 < N.trace_cap) {
+            const double ref = (cut < kInf) ? fabs(cut) : fabs(lb);
+            if (lb - N.trace[t - ctl.window] < ctl.min_improve * fmax(1.0, ref)) {
+                stop = 1;
+                reason = 2;
+            }
+        }
+        S->stopped = stop;
+        S->reason = reason;
+        improved = better ? 1 : 0;
+    }
+    __syncthreads();
+    if (l < n) {
+        N.xperm[l] = sig[l];
+        if (improved) N.bestperm[l] = sig[l];
+    }
+}
+
+// ----------------------------------------------------------------- fold ---
+// Child of a parent in F-form (after >= 1 iteration: Px = pi_x, Py = pi_y,
+// Z = pi_z) for fixing local facility l to local location s: entries holding
+// (l,s) drop one level, the rest is restricted (see the oracle's fold).
+__global__ void k_fold_xy(const double *__restrict__ pPx, const double *__restrict__ pPy,
+                          const double *__restrict__ pZ, int n, int l, int s, double *__restrict__ cXc,
+                          double *__restrict__ cYc)
+{
+    const int n1 = n - 1, m = n - 2;
+    const long long mm = (long long)m * m;
+    const long long T1 = (long long)n1 * n1 * (n1 - 1) * (n1 - 1);
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < T1 + (long long)n1 * n1;
+         e += (long long)gridDim.x * blockDim.x) {
+        if (e < T1) {
+            const int m1 = n1 - 1;
+            const int qp = (int)(e % m1), jp = (int)((e / m1) % m1);
+            const int ipc = (int)(e / ((long long)m1 * m1));
+            const int a1 = ipc / n1, b1 = ipc % n1;
+            const int a2 = jp + (jp >= a1), b2 = qp + (qp >= b1);
+            const int i = a1 + (a1 >= l), p = b1 + (b1 >= s), j = a2 + (a2 >= l), q = b2 + (b2 >= s);
+            const long long t1 = tile_of(n, l, s, i, p);   // z(l,i,j,s,p,q): row j, col q
+            const long long t2 = tile_of(n, i, p, l, s);   // z(i,l,j,p,s,q): row j, col q
+            const long long t3 = tile_of(n, i, p, j, q);   // z(i,j,l,p,q,s): row l, col s
+            const double z1 = pZ[t1 * mm + (long long)(j - (j > l) - (j > i)) * m + (q - (q > s) - (q > p))];
+            const double z2 = pZ[t2 * mm + (long long)(j - (j > i) - (j > l)) * m + (q - (q > p) - (q > s))];
+            const double z3 = pZ[t3 * mm + (long long)(l - (l > i) - (l > j)) * m + (s - (s > p) - (s > q))];
+            cYc[e] = ((pPy[t3] + z1) + z2) + z3;
+        } else {
+            const long long x = e - T1;
+            const int a1 = (int)(x / n1), b1 = (int)(x % n1);
+            const int i = a1 + (a1 >= l), p = b1 + (b1 >= s);
+            cXc[x] = (pPx[i * n + p] + pPy[tile_of(n, l, s, i, p)]) + pPy[tile_of(n, i, p, l, s)];
+        }
+    }
+}
+
+__global__ void k_fold_z(const double *__restrict__ pZ, int n, int l, int s, double *__restrict__ cZ)
+{
+    const int n1 = n - 1, m = n - 2, m1 = n1 - 2;
+    const long long mm = (long long)m * m, mm1 = (long long)m1 * m1;
+    const long long V1 = (long long)n1 * n1 * (n1 - 1) * (n1 - 1) * mm1;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < V1;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long tc = e / mm1;
+        const int w = (int)(e % mm1);
+        const int rr = w / m1, cc = w % m1;
+        const int q1 = n1 - 1;
+        const int qp = (int)(tc % q1), jp = (int)((tc / q1) % q1);
+        const int ipc = (int)(tc / ((long long)q1 * q1));
+        const int a1 = ipc / n1, b1 = ipc % n1;
+        const int a2 = jp + (jp >= a1), b2 = qp + (qp >= b1);
+        // child row rr -> child facility a3 (skipping a1, a2), column cc -> b3
+        const int flo = a1 < a2 ? a1 : a2, fhi = a1 < a2 ? a2 : a1;
+        int a3 = rr;
+        a3 += (a3 >= flo);
+        a3 += (a3 >= fhi);
+        const int llo = b1 < b2 ? b1 : b2, lhi = b1 < b2 ? b2 : b1;
+        int b3 = cc;
+        b3 += (b3 >= llo);
+        b3 += (b3 >= lhi);
+        const int i = a1 + (a1 >= l), j = a2 + (a2 >= l), k = a3 + (a3 >= l);
+        const int p = b1 + (b1 >= s), q = b2 + (b2 >= s), r = b3 + (b3 >= s);
+        const long long tp = tile_of(n, i, p, j, q);
+        cZ[e] = pZ[tp * mm + (long long)(k - (k > i) - (k > j)) * m + (r - (r > p) - (r > q))];
+    }
+}
+
+}  // namespace qap

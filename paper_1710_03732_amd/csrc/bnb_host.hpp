@@ -1,0 +1,491 @@
+// bnb_host.hpp -- host side of the child fold, the batched dual ascent and
+// the branch-and-bound of Section 4 (included at the end of capi.hip: one
+// translation unit with the context helpers).
+#pragma once
+#include <algorithm>
+#include <memory>
+
+#include "batch.hpp"
+
+namespace {
+
+bool fathomed_host(double lb, double ub, bool integer_data)
+{
+    if (!(ub < HUGE_VAL)) return false;
+    const double tol = 1e-9 * std::fmax(1.0, std::fabs(ub));
+    if (integer_data) return std::ceil(lb - tol) >= ub;
+    return lb >= ub - tol;
+}
+
+// Exact QAP cost of a full permutation (int64 when every input is integer).
+double full_cost(const qap_ctx *root, const std::vector<int> &perm)
+{
+    const int n = root->n;
+    const double *F = root->hF.data(), *D = root->hD.data(), *B = root->hB.data();
+    if (root->integer_data) {
+        long long c = 0;
+        for (int i = 0; i < n; ++i) {
+            c += (long long)B[i * n + perm[i]];
+            for (int j = 0; j < n; ++j) c += (long long)F[i * n + j] * (long long)D[perm[i] * n + perm[j]];
+        }
+        return (double)c;
+    }
+    long double c = 0.0L;
+    for (int i = 0; i < n; ++i) {
+        c += B[i * n + perm[i]];
+        for (int j = 0; j < n; ++j) c += (long double)F[i * n + j] * D[perm[i] * n + perm[j]];
+    }
+    return (double)c;
+}
+
+// Rule 3 (Section 4): lowest total interaction first, then the lowest summed
+// interaction with the facilities already placed; ties to the lowest index.
+std::vector<int> rule3_order(int n, const double *F)
+{
+    std::vector<int> order, placed(n, 0);
+    for (int t = 0; t < n; ++t) {
+        int best = -1;
+        double bv = HUGE_VAL;
+        for (int i = 0; i < n; ++i) {
+            if (placed[i]) continue;
+            double s = 0.0;
+            for (int j = 0; j < n; ++j) {
+                if (t == 0) {
+                    if (j != i) s += F[i * n + j] + F[j * n + i];
+                } else if (placed[j]) {
+                    s += F[i * n + j] + F[j * n + i];
+                }
+            }
+            if (s < bv) {
+                bv = s;
+                best = i;
+            }
+        }
+        order.push_back(best);
+        placed[best] = 1;
+    }
+    return order;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qap_fold_child(qap_handle h, int l, int s, qap_handle *child)
+{
+    if (!h || !child) return QAP_EINVAL;
+    const int n = h->n, n1 = n - 1;
+    if (n1 < 3) return fail(h, QAP_EUNSUPPORTED, "a child needs n >= 4");
+    if (l < 0 || l >= n || s < 0 || s >= n) return fail(h, QAP_EINVAL, "facility/location out of range");
+    DevScalars ps{};
+    HIPCHK(h, hipMemcpyAsync(&ps, h->S, sizeof(ps), hipMemcpyDeviceToHost, h->stream));
+    double px = 0.0;
+    HIPCHK(h, hipMemcpyAsync(&px, h->Px + (size_t)l * n + s, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (ps.t < 1) return fail(h, QAP_ESTATE, "the parent has run no iteration yet");
+    // the child's own QAP: F, D restricted, fixed pair folded into B, constant
+    const double *F = h->hF.data(), *D = h->hD.data(), *B = h->hB.data();
+    std::vector<double> Fc((size_t)n1 * n1), Dc((size_t)n1 * n1), Bc((size_t)n1 * n1);
+    for (int a1 = 0; a1 < n1; ++a1)
+        for (int a2 = 0; a2 < n1; ++a2) {
+            const int i = a1 + (a1 >= l), j = a2 + (a2 >= l);
+            const int p = a1 + (a1 >= s), q = a2 + (a2 >= s);
+            Fc[(size_t)a1 * n1 + a2] = F[i * n + j];
+            Dc[(size_t)a1 * n1 + a2] = D[p * n + q];
+            Bc[(size_t)a1 * n1 + a2] = (B[i * n + q] + F[i * n + l] * D[q * n + s]) + F[l * n + i] * D[s * n + q];
+        }
+    const double off = h->offset + (B[l * n + s] + F[l * n + l] * D[s * n + s]);
+    qap_ctx *c = nullptr;
+    int rc = create_ctx(n1, Fc.data(), Dc.data(), Bc.data(), h->prm, off, h->stream, false, &c);
+    if (rc != QAP_OK) {
+        h->err = g_init_error;
+        return rc;
+    }
+    const long long T1 = c->T;
+    const unsigned gxy = (unsigned)std::min<long long>((T1 + (long long)n1 * n1 + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_fold_xy, dim3(gxy), dim3(256), 0, h->stream, h->Px, h->Py, h->Z, n, l, s, c->Xc, c->Yc);
+    const unsigned gz = (unsigned)std::min<long long>(((long long)c->Vz + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_fold_z, dim3(gz), dim3(256), 0, h->stream, h->Z, n, l, s, c->Z);
+    hipLaunchKernelGGL(k_fill, dim3(64), dim3(256), 0, h->stream, c->Py, (size_t)T1, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, h->stream, c->Px, (size_t)n1 * n1, 0.0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        qap_destroy(c);
+        return fail(h, QAP_EDEVICE, std::string("fold: ") + hipGetErrorString(e));
+    }
+    rc = upload_scalars(c, ps.lb + px);
+    if (rc != QAP_OK) {
+        h->err = c->err;
+        qap_destroy(c);
+        return rc;
+    }
+    *child = c;
+    return QAP_OK;
+}
+
+int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_stats *st)
+{
+    if (count < 0 || (count > 0 && (!hs || !bp))) return fail(nullptr, QAP_EINVAL, "bad batch arguments");
+    if (count == 0) return QAP_OK;
+    if (bp->iters < 0 || bp->window < 0 || bp->window > 1000) return fail(hs[0], QAP_EINVAL, "bad batch params");
+    qap_ctx *h0 = hs[0];
+    if (!h0) return QAP_EINVAL;
+    hipStream_t stream = h0->stream;
+    for (int b = 0; b < count; ++b) {
+        if (!hs[b] || hs[b]->prm.device != h0->prm.device) return fail(h0, QAP_EINVAL, "handles on one device");
+        if (hs[b]->n > 64) return fail(h0, QAP_EUNSUPPORTED, "n > 64 in a batch");
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    HIPCHK(h0, hipSetDevice(h0->prm.device));
+    for (int b = 0; b < count; ++b) HIPCHK(h0, hipStreamSynchronize(hs[b]->stream));
+    // node table and prefix tables
+    std::vector<BNode> nodes(count);
+    std::vector<long long> zl(count + 1, 0), yl(count + 1, 0), sw(count + 1, 0), sc(count + 1, 0);
+    int mz = 1, my = 1;
+    for (int b = 0; b < count; ++b) {
+        qap_ctx *h = hs[b];
+        DevScalars s{};
+        HIPCHK(h0, hipMemcpy(&s, h->S, sizeof(s), hipMemcpyDeviceToHost));
+        int rc = ensure_trace(h, s.t + bp->iters + 1);
+        if (rc != QAP_OK) return rc;
+        BNode &N = nodes[b];
+        N.Z = h->Z;
+        N.Yc = h->Yc;
+        N.Py = h->Py;
+        N.Xc = h->Xc;
+        N.Px = h->Px;
+        N.alpha = h->alpha;
+        N.beta = h->beta;
+        N.trace = h->trace;
+        N.F = h->F;
+        N.D = h->D;
+        N.B = h->B;
+        N.xperm = h->xperm;
+        N.bestperm = h->bestperm;
+        N.S = h->S;
+        N.bins = h->bins;
+        N.triples = h->triples;
+        N.T = h->T;
+        N.n = h->n;
+        N.m = h->m;
+        N.ntri = h->ntriples;
+        N.nb = (h->n + SB - 1) / SB;
+        N.integer_data = h->integer_data ? 1 : 0;
+        N.trace_cap = h->trace_cap;
+        N.offset = h->offset;
+        N.min_gap = h->prm.min_gap;
+        N.kz = h->kz;
+        N.okz = h->okz;
+        N.ky2 = h->ky2;
+        N.kx3 = h->kx3;
+        N.phi = h->phi;
+        N.oky = h->oky;
+        N.okx = h->okx;
+        N.phy = h->phy;
+        N.ophy = h->ophy;
+        zl[b + 1] = zl[b] + h->T;
+        yl[b + 1] = yl[b] + (long long)h->n * h->n;
+        sw[b + 1] = sw[b] + (long long)h->ntriples * N.nb * N.nb * N.nb;
+        sc[b + 1] = sc[b] + h->T + (long long)h->n * h->n;
+        mz = std::max(mz, h->m);
+        my = std::max(my, h->n - 1);
+    }
+    // device copies (one allocation)
+    const size_t nb_bytes = round_up(sizeof(BNode) * count), pf_bytes = round_up(sizeof(long long) * (count + 1));
+    void *dmem = nullptr;
+    HIPCHK(h0, hipMalloc(&dmem, nb_bytes + 4 * pf_bytes));
+    std::unique_ptr<void, void (*)(void *)> guard(dmem, [](void *p) { (void)hipFree(p); });
+    char *dp = (char *)dmem;
+    BNode *dnodes = (BNode *)dp;
+    long long *dzl = (long long *)(dp + nb_bytes), *dyl = (long long *)(dp + nb_bytes + pf_bytes);
+    long long *dsw = (long long *)(dp + nb_bytes + 2 * pf_bytes), *dsc = (long long *)(dp + nb_bytes + 3 * pf_bytes);
+    HIPCHK(h0, hipMemcpyAsync(dnodes, nodes.data(), sizeof(BNode) * count, hipMemcpyHostToDevice, stream));
+    HIPCHK(h0, hipMemcpyAsync(dzl, zl.data(), sizeof(long long) * (count + 1), hipMemcpyHostToDevice, stream));
+    HIPCHK(h0, hipMemcpyAsync(dyl, yl.data(), sizeof(long long) * (count + 1), hipMemcpyHostToDevice, stream));
+    HIPCHK(h0, hipMemcpyAsync(dsw, sw.data(), sizeof(long long) * (count + 1), hipMemcpyHostToDevice, stream));
+    HIPCHK(h0, hipMemcpyAsync(dsc, sc.data(), sizeof(long long) * (count + 1), hipMemcpyHostToDevice, stream));
+    BatchPrefix pf{dzl, dyl, dsw, dsc};
+    BatchCtl ctl{bp->ub_cut, bp->min_improve, bp->window, count};
+    const int Lz = mz <= 8 ? 8 : mz <= 16 ? 16 : mz <= 32 ? 32 : 64;
+    const int Ly = my <= 8 ? 8 : my <= 16 ? 16 : my <= 32 ? 32 : 64;
+    auto launch_all = [&]() -> hipError_t {
+        hipError_t e;
+        if (sw[count] > 0) {
+            hipLaunchKernelGGL(k_bsweep, dim3((unsigned)sw[count]), dim3(256), 0, stream, dnodes, pf, count);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        const unsigned sb = (unsigned)std::min<long long>((sc[count] + 255) / 256, 65535);
+        hipLaunchKernelGGL(k_bscale, dim3(sb), dim3(256), 0, stream, dnodes, pf, count);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        {
+            const size_t per = ((size_t)mz * mz + 2 * mz) * sizeof(double);
+            int G = 256 / Lz;
+            while (G > 1 && (size_t)G * per > 65536) --G;
+            const unsigned blocks = (unsigned)((zl[count] + G - 1) / G);
+#define QAP_BZ(LL)                                                                                              \
+    if (Lz == LL) hipLaunchKernelGGL((k_bzlap<LL>), dim3(blocks), dim3(G * LL), G * per, stream, dnodes, pf, count, mz);
+            QAP_BZ(8) QAP_BZ(16) QAP_BZ(32) QAP_BZ(64)
+#undef QAP_BZ
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        {
+            const size_t per = ((size_t)my * my + 2 * my) * sizeof(double);
+            int G = 256 / Ly;
+            while (G > 1 && (size_t)G * per > 65536) --G;
+            const unsigned blocks = (unsigned)((yl[count] + G - 1) / G);
+#define QAP_BY(LL)                                                                                              \
+    if (Ly == LL) hipLaunchKernelGGL((k_bylap<LL>), dim3(blocks), dim3(G * LL), G * per, stream, dnodes, pf, count, my);
+            QAP_BY(8) QAP_BY(16) QAP_BY(32) QAP_BY(64)
+#undef QAP_BY
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_bxlap, dim3(count), dim3(64), 0, stream, dnodes, ctl);
+        return hipGetLastError();
+    };
+    if (bp->iters > 0) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        HIPCHK(h0, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        hipError_t le = launch_all();
+        hipError_t ce = hipStreamEndCapture(stream, &g);
+        if (le != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch launch: ") + hipGetErrorString(le));
+        if (ce != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch capture: ") + hipGetErrorString(ce));
+        hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch graph: ") + hipGetErrorString(ie));
+        for (int it = 0; it < bp->iters; ++it) {
+            hipError_t e2 = hipGraphLaunch(ge, stream);
+            if (e2 != hipSuccess) {
+                (void)hipGraphExecDestroy(ge);
+                return fail(h0, QAP_EDEVICE, std::string("batch replay: ") + hipGetErrorString(e2));
+            }
+        }
+        (void)hipGraphExecDestroy(ge);
+    }
+    HIPCHK(h0, hipStreamSynchronize(stream));
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        for (int b = 0; b < count; ++b) {
+            DevScalars s{};
+            HIPCHK(h0, hipMemcpy(&s, hs[b]->S, sizeof(s), hipMemcpyDeviceToHost));
+            st->iterations += s.t;
+            st->stopped += s.stopped ? 1 : 0;
+            st->fathomed += s.reason == 1 ? 1 : 0;
+            st->window_stops += s.reason == 2 ? 1 : 0;
+        }
+        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    for (int b = 0; b < count; ++b) {
+        DevScalars s{};
+        HIPCHK(h0, hipMemcpy(&s, hs[b]->S, sizeof(s), hipMemcpyDeviceToHost));
+        hs[b]->t_host = s.t;
+    }
+    return QAP_OK;
+}
+
+int qap_node_status(qap_handle h, int *t, double *lb, double *ub, int *stopped, int *reason)
+{
+    if (!h) return QAP_EINVAL;
+    DevScalars s{};
+    HIPCHK(h, hipMemcpyAsync(&s, h->S, sizeof(s), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (t) *t = s.t;
+    if (lb) *lb = s.lb;
+    if (ub) *ub = s.ub;
+    if (stopped) *stopped = s.stopped;
+    if (reason) *reason = s.reason;
+    return QAP_OK;
+}
+
+int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, double *obj_out, qap_bnb_stats *st)
+{
+    if (!h || !perm_out || !obj_out) return QAP_EINVAL;
+    qap_bnb_params P{};
+    if (p) {
+        P = *p;
+    } else {
+        P.batch = 256;
+        P.node_iters = 100;
+        P.window = 25;
+        P.root_iters = 0;
+        P.min_improve = 2e-4;
+        P.ub0 = HUGE_VAL;
+        P.enum_below = 3;
+        P.rule = 3;
+    }
+    if (P.batch < 1 || P.node_iters < 1 || P.window < 0 || P.window > 1000 || P.enum_below < 3 ||
+        !(P.min_improve >= 0.0) || P.rule != 3)
+        return fail(h, QAP_EINVAL, "bad branch-and-bound parameters");
+    if (P.root_iters <= 0) P.root_iters = P.node_iters;
+    const int n = h->n;
+    if (n > 24) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound supports n <= 24");
+    auto t0 = std::chrono::steady_clock::now();
+    const std::vector<int> order = rule3_order(n, h->hF.data());
+    const bool integer_data = h->integer_data;
+    double UB = P.ub0;
+    std::vector<int> best(n, -1);
+    long long nodes_done = 0, da_iters = 0, batches = 0, enumerated = 0;
+
+    struct Node {
+        std::shared_ptr<qap_ctx> parent;  // materialised parent state (shared by siblings)
+        int l = -1, s = -1;               // fold of the parent, or -1 for the root
+        int depth = 0;
+        double lb_hint = -HUGE_VAL;       // parent bound + pi_x[l,s]
+        std::vector<int> fac, loc, fixed;
+    };
+    auto destroy = [](qap_ctx *c) { qap_destroy(c); };
+    auto update_ub = [&](double cost, const std::vector<int> &perm) {
+        if (cost < UB) {
+            UB = cost;
+            best = perm;
+        }
+    };
+    // exact completion of a node with at most enum_below free facilities
+    auto enumerate = [&](const Node &nd) {
+        const int k = (int)nd.fac.size();
+        std::vector<int> a(k);
+        for (int t = 0; t < k; ++t) a[t] = t;
+        std::vector<int> perm = nd.fixed;
+        do {
+            for (int t = 0; t < k; ++t) perm[nd.fac[t]] = nd.loc[a[t]];
+            update_ub(full_cost(h, perm), perm);
+            ++enumerated;
+        } while (std::next_permutation(a.begin(), a.end()));
+    };
+
+    std::vector<Node> stack;
+    {
+        Node root;
+        root.depth = 0;
+        for (int i = 0; i < n; ++i) {
+            root.fac.push_back(i);
+            root.loc.push_back(i);
+        }
+        root.fixed.assign(n, -1);
+        if (n <= P.enum_below) {
+            enumerate(root);
+            ++nodes_done;
+        } else {
+            stack.push_back(root);
+        }
+    }
+    int rc = QAP_OK;
+    while (!stack.empty() && rc == QAP_OK) {
+        // next batch: the top of the stack (deepest, lowest location first)
+        std::vector<Node> batch;
+        while (!stack.empty() && (int)batch.size() < P.batch) {
+            Node nd = std::move(stack.back());
+            stack.pop_back();
+            if (fathomed_host(nd.lb_hint, UB, integer_data)) {
+                ++nodes_done;
+                continue;
+            }
+            batch.push_back(std::move(nd));
+        }
+        if (batch.empty()) continue;
+        std::vector<std::shared_ptr<qap_ctx>> ctxs;
+        std::vector<qap_handle> hs;
+        for (auto &nd : batch) {
+            qap_ctx *c = nullptr;
+            if (nd.l < 0) {
+                rc = create_ctx(n, h->hF.data(), h->hD.data(), h->hB.data(), h->prm, 0.0, h->stream, true, &c);
+                if (rc != QAP_OK) h->err = g_init_error;
+            } else {
+                rc = qap_fold_child(nd.parent.get(), nd.l, nd.s, &c);
+                if (rc != QAP_OK) h->err = nd.parent->err;
+            }
+            if (rc != QAP_OK) break;
+            nd.parent.reset();  // release the parent once its last child is built
+            ctxs.emplace_back(c, destroy);
+            hs.push_back(c);
+        }
+        if (rc != QAP_OK) break;
+        const int iters = (batch.size() == 1 && batch[0].depth == 0) ? P.root_iters : P.node_iters;
+        qap_batch_params bp{iters, P.window, P.min_improve, UB};
+        rc = qap_batch_dual_ascent(hs.data(), (int)hs.size(), &bp, nullptr);
+        if (rc != QAP_OK) {
+            h->err = hs[0]->err;
+            break;
+        }
+        ++batches;
+        // incumbents first, then branching with the improved UB
+        std::vector<DevScalars> sv(hs.size());
+        for (size_t b = 0; b < hs.size(); ++b) {
+            qap_ctx *c = hs[b];
+            if (hipMemcpy(&sv[b], c->S, sizeof(DevScalars), hipMemcpyDeviceToHost) != hipSuccess) {
+                rc = fail(h, QAP_EDEVICE, "reading node state failed");
+                break;
+            }
+            da_iters += sv[b].t;
+            std::vector<int> lp(c->n);
+            if (hipMemcpy(lp.data(), c->bestperm, sizeof(int) * c->n, hipMemcpyDeviceToHost) != hipSuccess) {
+                rc = fail(h, QAP_EDEVICE, "reading node assignment failed");
+                break;
+            }
+            if (sv[b].ub < HUGE_VAL) {
+                std::vector<int> perm = batch[b].fixed;
+                for (int a = 0; a < c->n; ++a) perm[batch[b].fac[a]] = batch[b].loc[lp[a]];
+                update_ub(full_cost(h, perm), perm);
+            }
+        }
+        if (rc != QAP_OK) break;
+        std::vector<Node> pushes;
+        for (size_t b = 0; b < hs.size(); ++b) {
+            ++nodes_done;
+            Node &nd = batch[b];
+            if (fathomed_host(sv[b].lb, UB, integer_data)) continue;
+            const int nl = (int)nd.fac.size();
+            const int f = order[nd.depth];
+            int l = -1;
+            for (int t = 0; t < nl; ++t)
+                if (nd.fac[t] == f) l = t;
+            std::vector<double> pxr(nl);
+            if (hipMemcpy(pxr.data(), hs[b]->Px + (size_t)l * nl, sizeof(double) * nl, hipMemcpyDeviceToHost) !=
+                hipSuccess) {
+                rc = fail(h, QAP_EDEVICE, "reading pi_x failed");
+                break;
+            }
+            std::vector<Node> kids;
+            for (int s = 0; s < nl; ++s) {
+                const double lbc = sv[b].lb + pxr[s];
+                if (fathomed_host(lbc, UB, integer_data)) continue;
+                Node k;
+                k.depth = nd.depth + 1;
+                k.l = l;
+                k.s = s;
+                k.lb_hint = lbc;
+                for (int t = 0; t < nl; ++t)
+                    if (t != l) k.fac.push_back(nd.fac[t]);
+                for (int t = 0; t < nl; ++t)
+                    if (t != s) k.loc.push_back(nd.loc[t]);
+                k.fixed = nd.fixed;
+                k.fixed[f] = nd.loc[s];
+                if (nl - 1 <= P.enum_below) {
+                    enumerate(k);
+                    ++nodes_done;
+                    continue;
+                }
+                k.parent = ctxs[b];
+                kids.push_back(std::move(k));
+            }
+            for (auto &k : kids) pushes.push_back(std::move(k));
+        }
+        // pushes is in priority order (batch order, then ascending location):
+        // push it reversed so that its first entry ends on top
+        for (auto it = pushes.rbegin(); it != pushes.rend(); ++it) stack.push_back(std::move(*it));
+    }
+    if (rc != QAP_OK) return rc;
+    if (!(UB < HUGE_VAL)) return fail(h, QAP_ESTATE, "no incumbent below ub0");
+    for (int i = 0; i < n; ++i) perm_out[i] = best[i];
+    *obj_out = UB;
+    if (st) {
+        st->nodes = nodes_done;
+        st->da_iters = da_iters;
+        st->batches = batches;
+        st->enumerated = enumerated;
+        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return QAP_OK;
+}
+
+}  // extern "C"

@@ -52,6 +52,7 @@ struct qap_ctx {
     bool integer_data = false;
     int zl = 0, zc = 0;  // Z-LAP mapping
     int zlap_waves = 1;  // waves per Z-LAP block
+    double offset = 0.0; // constant added to every permutation cost (B&B nodes)
     std::vector<double> hF, hD, hB;
     std::string err;
     hipGraphExec_t graph = nullptr;  // one full iteration (t >= 1)
@@ -224,7 +225,7 @@ hipError_t launch_sweep(qap_ctx *h)
 hipError_t launch_xlap(qap_ctx *h)
 {
     hipLaunchKernelGGL(k_xlap, dim3(1), dim3(64), 0, h->stream, h->Xc, h->Px, h->alpha, h->beta, h->F,
-                       h->D, h->B, h->xperm, h->bestperm, h->trace, h->n, h->prm.min_gap, h->S);
+                       h->D, h->B, h->xperm, h->bestperm, h->trace, h->n, h->prm.min_gap, h->offset, h->S);
     return hipGetLastError();
 }
 
@@ -289,6 +290,8 @@ void derive_constants(qap_ctx *h)
     h->ophy = 1.0 - h->prm.phi_y;
 }
 
+int upload_scalars(qap_ctx *h, double lb);
+
 int upload_initial(qap_ctx *h)
 {
     const int n = h->n;
@@ -304,8 +307,21 @@ int upload_initial(qap_ctx *h)
     hipLaunchKernelGGL(k_init_xy, dim3(std::min<long long>((h->T + 255) / 256, 65535)), dim3(256), 0,
                        h->stream, h->F, h->D, h->B, h->Xc, h->Yc, n);
     HIPCHK(h, hipGetLastError());
+    return upload_scalars(h, 0.0);
+}
+
+// Reset the scalar block (bound lb, no incumbent, t = 0) and the matchings;
+// uploads F, D, B too.
+int upload_scalars(qap_ctx *h, double lb)
+{
+    const int n = h->n;
+    const int nn = n * n;
+    HIPCHK(h, hipMemcpyAsync(h->F, h->hF.data(), sizeof(double) * nn, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->D, h->hD.data(), sizeof(double) * nn, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->B, h->hB.data(), sizeof(double) * nn, hipMemcpyHostToDevice, h->stream));
+    hipLaunchKernelGGL(k_fill, dim3(16), dim3(256), 0, h->stream, (double *)h->bins, (size_t)kStepBins, 0.0);
     DevScalars s{};
-    s.lb = 0.0;
+    s.lb = lb;
     s.ub = HUGE_VAL;
     s.t = 0;
     s.proven = 0;
@@ -345,49 +361,15 @@ uint64_t fnv1a(uint64_t hsh, const void *data, size_t bytes)
     return hsh;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char *qap_version(void) { return "qap-rlt2-mi355x 0.1 (gfx950, F1 FULL)"; }
-
-int qap_default_params(qap_params *p)
+// Allocate and (optionally) initialise a context of size n.  stream: a
+// caller stream to share (not owned) or nullptr for a new one.  With init the
+// state is Algorithm 1's initial one; otherwise the caller fills Xc, Yc and Z
+// (the child fold) and only the scalars are reset.
+int create_ctx(int n, const double *F, const double *D, const double *B, const qap_params &prm, double offset,
+               hipStream_t stream, bool init, qap_ctx **out)
 {
-    if (!p) return QAP_EINVAL;
-    std::memset(p, 0, sizeof(*p));
-    p->kappa_z = 5.0 / 6.0;
-    p->kappa_y = 1.0;
-    p->kappa_x = 1.0;
-    p->phi_z = 1.0 / 5.0;
-    p->phi_y = 0.5;
-    p->min_gap = 0.0;
-    return QAP_OK;
-}
-
-size_t qap_workspace_bytes(int n, const qap_params *p)
-{
-    (void)p;
-    if (n < 3 || n > 64) return 0;
-    return sizes_for(n, 1024).total + round_up(sizeof(double) * 1024);
-}
-
-int qap_rlt2_init(const double *F, const double *D, const double *B, int n, const qap_params *p,
-                  qap_handle *out)
-{
-    if (!out) return fail(nullptr, QAP_EINVAL, "out is NULL");
-    if (n < 3 || n > 64) return fail(nullptr, QAP_EUNSUPPORTED, "n must be in 3..64");
-    if (!F || !D) return fail(nullptr, QAP_EINVAL, "F and D are required");
-    if (!finite_all(F, n) || !finite_all(D, n) || (B && !finite_all(B, n)))
-        return fail(nullptr, QAP_EINVAL, "non-finite input entry");
-    qap_params prm;
-    if (p)
-        prm = *p;
-    else
-        qap_default_params(&prm);
-    if (!params_ok(prm)) return fail(nullptr, QAP_EINVAL, "kappa/phi outside [0,1] or 5*phi_z != 1");
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
-        return fail(nullptr, QAP_EDEVICE, "no HIP device");
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, QAP_EDEVICE, "no HIP device");
     if (prm.device < 0 || prm.device >= ndev) return fail(nullptr, QAP_EINVAL, "bad device ordinal");
     if (hipSetDevice(prm.device) != hipSuccess) return fail(nullptr, QAP_EDEVICE, "hipSetDevice failed");
 
@@ -408,23 +390,32 @@ int qap_rlt2_init(const double *F, const double *D, const double *B, int n, cons
     h->T = (long long)n * n * (n - 1) * (n - 1);
     h->Vz = (size_t)h->T * h->m * h->m;
     h->prm = prm;
+    h->offset = offset;
     h->hF.assign(F, F + n * n);
     h->hD.assign(D, D + n * n);
     h->hB.assign(n * n, 0.0);
     if (B) h->hB.assign(B, B + n * n);
-    h->integer_data = integer_all(F, n) && integer_all(D, n) && integer_all(h->hB.data(), n);
+    h->integer_data = integer_all(F, n) && integer_all(D, n) && integer_all(h->hB.data(), n) &&
+                      std::fabs(offset) < 9.0e15 && offset == std::floor(offset);
     derive_constants(h);
     pick_zlap(h->m, prm.zlap_lanes, prm.zlap_cols, h->zl, h->zc);
 
     auto cleanup = [&](int code) {
+        const std::string e = h->err;
         qap_destroy(h);
+        if (!e.empty()) g_init_error = e;
         return code;
     };
-    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
-        delete h;
-        return fail(nullptr, QAP_EDEVICE, "stream creation failed");
+    if (stream) {
+        h->stream = stream;
+        h->own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete h;
+            return fail(nullptr, QAP_EDEVICE, "stream creation failed");
+        }
+        h->own_stream = true;
     }
-    h->own_stream = true;
     h->arena_bytes = sz.total;
     void *mem = nullptr;
     if (prm.alloc)
@@ -470,17 +461,59 @@ int qap_rlt2_init(const double *F, const double *D, const double *B, int n, cons
         for (int j = i + 1; j < n; ++j)
             for (int k = j + 1; k < n; ++k) tri.push_back(i | (j << 8) | (k << 16));
     h->ntriples = (int)tri.size();
-    if (hipMemcpy(h->triples, tri.data(), sizeof(int) * tri.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpyAsync(h->triples, tri.data(), sizeof(int) * tri.size(), hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
         g_init_error = "upload failed";
         return cleanup(QAP_EDEVICE);
     }
-    int rc = upload_initial(h);
-    if (rc != QAP_OK) {
-        g_init_error = h->err;
-        return cleanup(rc);
-    }
+    int rc = init ? upload_initial(h) : upload_scalars(h, 0.0);
+    if (rc != QAP_OK) return cleanup(rc);
     *out = h;
     return QAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *qap_version(void) { return "qap-rlt2-mi355x 0.1 (gfx950, F1 FULL)"; }
+
+int qap_default_params(qap_params *p)
+{
+    if (!p) return QAP_EINVAL;
+    std::memset(p, 0, sizeof(*p));
+    p->kappa_z = 5.0 / 6.0;
+    p->kappa_y = 1.0;
+    p->kappa_x = 1.0;
+    p->phi_z = 1.0 / 5.0;
+    p->phi_y = 0.5;
+    p->min_gap = 0.0;
+    return QAP_OK;
+}
+
+size_t qap_workspace_bytes(int n, const qap_params *p)
+{
+    (void)p;
+    if (n < 3 || n > 64) return 0;
+    return sizes_for(n, 1024).total + round_up(sizeof(double) * 1024);
+}
+
+int qap_rlt2_init(const double *F, const double *D, const double *B, int n, const qap_params *p,
+                  qap_handle *out)
+{
+    if (!out) return fail(nullptr, QAP_EINVAL, "out is NULL");
+    if (n < 3 || n > 64) return fail(nullptr, QAP_EUNSUPPORTED, "n must be in 3..64");
+    if (!F || !D) return fail(nullptr, QAP_EINVAL, "F and D are required");
+    if (!finite_all(F, n) || !finite_all(D, n) || (B && !finite_all(B, n)))
+        return fail(nullptr, QAP_EINVAL, "non-finite input entry");
+    qap_params prm;
+    if (p)
+        prm = *p;
+    else
+        qap_default_params(&prm);
+    if (!params_ok(prm)) return fail(nullptr, QAP_EINVAL, "kappa/phi outside [0,1] or 5*phi_z != 1");
+    return create_ctx(n, F, D, B, prm, 0.0, nullptr, true, out);
 }
 
 int qap_destroy(qap_handle h)
@@ -750,17 +783,6 @@ int qap_lap_batch(const double *cost, int count, int m, double *u, double *v, do
     return QAP_OK;
 }
 
-int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, double *obj_out,
-                  qap_bnb_stats *st)
-{
-    (void)p;
-    (void)perm_out;
-    (void)obj_out;
-    (void)st;
-    if (!h) return QAP_EINVAL;
-    return fail(h, QAP_ESTATE, "branch-and-bound not available in this build");
-}
-
 const char *qap_last_error(qap_handle h)
 {
     if (!h) return g_init_error.c_str();
@@ -768,3 +790,5 @@ const char *qap_last_error(qap_handle h)
 }
 
 }  // extern "C"
+
+#include "bnb_host.hpp"

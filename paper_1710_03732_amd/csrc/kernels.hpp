@@ -33,6 +33,8 @@ struct DevScalars {
     int proven;
     int integer_data;
     int stopped;       // set once the bound proves optimality or gap < min_gap
+    int reason;        // why a batched node stopped (1 fathomed, 2 window rule, 3 gap)
+    int pad;
     unsigned long long steps;
 };
 
@@ -425,7 +427,8 @@ __global__ __launch_bounds__(64) void k_xlap(const double *__restrict__ Xc, doub
                                              const double *__restrict__ F, const double *__restrict__ D,
                                              const double *__restrict__ B, int *__restrict__ xperm,
                                              int *__restrict__ bestperm, double *__restrict__ trace,
-                                             int n, double min_gap, DevScalars *__restrict__ S)
+                                             int n, double min_gap, double offset,
+                                             DevScalars *__restrict__ S)
 {
     if (S->stopped) return;
     __shared__ double M[64 * 64];
@@ -469,7 +472,7 @@ __global__ __launch_bounds__(64) void k_xlap(const double *__restrict__ Xc, doub
         cd += __shfl_xor(cd, off, 64);
     }
     if (l == 0) {
-        const double cost = integer_data ? (double)ci : cd;
+        const double cost = (integer_data ? (double)ci : cd) + offset;
         const double lb = S->lb + th;
         S->lb = lb;
         double ub = S->ub;

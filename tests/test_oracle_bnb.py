@@ -78,6 +78,9 @@ def test_child_fold_identity(l, s):
         val = child.identity(np.array(cperm, dtype=np.int32))
         cost = O.qap_cost(F, D, B, perm)
         assert abs(val - cost) <= 1e-9 * max(1.0, abs(cost))
+        # the child is a self-contained QAP: restricted F, D, folded B, offset
+        Fc, Dc, Bc = child._keep
+        assert O.qap_cost(Fc, Dc, Bc, np.array(cperm, dtype=np.int32)) + child.offset == cost
     assert child.LB == da.LB + da.export()[0][l, s]
     # the child's own ascent keeps the bound valid for the restricted problem
     child.run(5)

@@ -253,3 +253,32 @@ def test_sampled_iteration_paths_match_full_oracle(inst):
         ks = [k for k in range(n) if k not in (i, j)]
         rs = [r for r in range(n) if r not in (p, q)]
         assert np.array_equal(pi, np.array([[Z1[i, j, k, p, q, r] for r in rs] for k in ks]))
+
+
+@pytest.mark.parametrize("inst", [I.grid_instance(9, 3, 3, 0.4, 1, 10, 2), I.dense_instance(8, 3),
+                                  I.random_instance(7, 5)], ids=lambda x: x.name)
+def test_tracked_multipliers_reproduce_the_bound(inst):
+    """The F1 transfers are multiplier updates (Eq. ch4:proof:2 per sweep,
+    Eq. da:yrule1 per y-pair rule).  Tracked from zero they are zero-sum over
+    every orbit and pair, and the Lagrangian relaxation LRLT2(u, v) solved
+    from scratch on the costs (b, C - u, -v) gives at least the F1 bound
+    (Eq. ch4:proof:4, applied at every iteration)."""
+    F, D, Bm = inst.arrays()
+    n = inst.n
+    da = O.DualAscent(F, D, Bm)
+    da.track()
+    da.run(25)
+    V, U = da.multipliers()
+    scale = max(1.0, np.abs(V).max())
+    for (i, j, k) in itertools.combinations(range(n), 3):
+        for (p, q, r) in [(0, 1, 2), (n - 1, 0, 3), (2, n - 2, 1)]:
+            tot = sum(V[m] for m in _orbit_members(i, j, k, p, q, r))
+            assert abs(tot) <= 1e-9 * scale
+    for i in range(n):
+        for j in range(n):
+            if i != j:
+                assert np.all(np.abs(U[i, j] + U[j, i].T)[~np.eye(n, dtype=bool)] <= 1e-9 * scale)
+    s = O.DualAscent.from_multipliers(F, D, Bm, O.FULL, V, U)
+    s.run(1)
+    assert s.LB >= da.LB - 1e-9 * max(1.0, abs(da.LB))
+    assert s.LB <= O.bruteforce(F, D, Bm)[0] + 1e-9
