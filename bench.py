@@ -39,11 +39,11 @@ def algorithmic_bytes(n: int) -> dict:
     V = T * m * m
     nn = n * n
     return {
-        # reads the z array and Theta, writes xi/psi (2 T m) and Theta
-        "zlap": 8 * (V + 2 * T * m + 2 * T),
-        # reads and writes the z array, reads xi/psi, pi_y, pi_x; the x/y
+        # reads the z array, writes its slacks pi_z back in place; Theta RMW
+        "zlap": 8 * (2 * V + 2 * T),
+        # reads pi_z and writes the new z array, reads pi_y, pi_x; the x/y
         # scaling reads pi_y and writes R_y
-        "sweep": 8 * (2 * V + 2 * T * m + T + nn) + 8 * (2 * T + 2 * nn),
+        "sweep": 8 * (2 * V + T + nn) + 8 * (2 * T + 2 * nn),
         # reads R_y and its partner entries, writes pi_y, updates R_x
         "ylap": 8 * (3 * T + 2 * nn),
         "xlap": 8 * (5 * nn),
@@ -52,7 +52,7 @@ def algorithmic_bytes(n: int) -> dict:
 
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
-    for name in ("lap_wave.hpp", "kernels.hpp"):
+    for name in ("lap_scalar.hpp", "lap_wave.hpp", "kernels.hpp"):
         with open(os.path.join(ROOT, "paper_1710_03732_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
