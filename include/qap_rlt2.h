@@ -258,6 +258,136 @@ int qap_lap_batch(const double *cost, int count, int m, double *u, double *v, do
 /* Text of the last error on h (or of the last failed init when h is NULL). */
 const char *qap_last_error(qap_handle h);
 
+/* ---------------------------------------------------------------------------
+ * Lagrange multipliers and the learned warm start.
+ *
+ * The F1 transfers are multiplier updates of the Lagrangian dual LRLT2(u, v)
+ * (Section 3.1): per ascent sweep, z entry e's multiplier v_e moves by
+ * g_e - phi_z * sum_{f != e} g_f over its orbit (its own kappa-shares minus
+ * what its partners pass to it, Eq. ch4:proof:2); per y-pair rule, u moves by
+ * phi_y * (own - partner) (Eq. da:yrule1).  Both sum to zero over every orbit
+ * (the six z variables of one set {(i,p),(j,q),(k,r)}, tied by Eq.
+ * rlt2:con3) and every pair (ijpq, jiqp).  Any zero-sum (u, v) gives a valid
+ * bound (weak duality, Eq. lgduality), so a run may restart from the costs
+ * (b + f_ii d_pp, C - u, -v): the "S-form" start.
+ *
+ * Orbit ids: o = tri * n(n-1)(n-2) + (p*(n-1) + q')*(n-2) + r'', with tri
+ * the index of the facility triple i<j<k in lexicographic order,
+ * q' = q - [q>p], r'' = r - [r>p] - [r>q]; 0 <= o < qap_orbit_count(n).
+ * Members in the order (A,B,C),(A,C,B),(B,A,C),(B,C,A),(C,A,B),(C,B,A) of
+ * A=(i,p), B=(j,q), C=(k,r); member (P1,P2,P3) is the z entry
+ * (P1.fac, P2.fac, P3.fac, P1.loc, P2.loc, P3.loc).
+ * ------------------------------------------------------------------------- */
+
+/* Start (on != 0: allocate, zero) or stop (0: free) tracking the multipliers
+ * of the single-handle dual ascent.  Tracking costs T*m*m + T doubles of
+ * device memory and one more read and write of that array per sweep.
+ * Tracked handles are rejected by qap_batch_dual_ascent (QAP_ESTATE).
+ * Errors: QAP_ENOMEM, QAP_EDEVICE. */
+int qap_track(qap_handle h, int on);
+
+/* Host copies of the tracked multipliers since tracking (re)started:
+ * v (T*m*m doubles, z layout), u (T doubles, y layout); each nullable.
+ * Errors: QAP_ESTATE (tracking off). */
+int qap_get_multipliers(qap_handle h, double *v, double *u);
+
+/* Restart at t = 0 from the S-form costs (b + f_ii d_pp, C - u, -v) with
+ * LB = 0 (Algorithm 1 step 1 with given multipliers).  v: host, T*m*m
+ * doubles (z layout) or NULL (zero); u: host, T doubles (y layout) or NULL.
+ * Each orbit of v and each pair of u must sum to zero within 1e-9 of the
+ * largest magnitude.  Tracking, if on, restarts from zero.
+ * Errors: QAP_EINVAL (non-finite value, not zero-sum), QAP_EDEVICE. */
+int qap_set_multipliers(qap_handle h, const double *v, const double *u);
+
+/* Number of orbits of size n: C(n,3) * n(n-1)(n-2). */
+int qap_orbit_count(int n, int64_t *count);
+
+/* Scale of the warm start's outputs: max(1, max|F|) * max(1, max|D|) / (n-2). */
+int qap_multiplier_scale(qap_handle h, double *scale);
+
+/* Features of `count` orbits (ids: device int64; x: device, count*32
+ * float32, row per orbit).  With Fn = F/sF, Dn = D/sD (sF, sD the largest
+ * magnitudes, at least 1), sym(M)_ab = (M_ab + M_ba)/2, fa_a = sum_l
+ * (Fn_al + Fn_la)/2n, dl likewise for Dn, Xn = (b + f_ii d_pp)/(sF sD), fbar
+ * and dbar the off-diagonal means of Fn and Dn:
+ *   0-5 Fn_ij Dn_pq, Fn_ji Dn_qp, Fn_ik Dn_pr, Fn_ki Dn_rp, Fn_jk Dn_qr, Fn_kj Dn_rq;
+ *   6-8 sym(Fn) of ij, ik, jk;  9-11 sym(Dn) of pq, pr, qr;
+ *   12-14 fa_i, fa_j, fa_k;  15-17 dl_p, dl_q, dl_r;  18-20 Xn_ip, Xn_jq, Xn_kr;
+ *   21 1/(n-2);  22-24 sym(Fn) of ij, ik, jk times dbar;
+ *   25-27 sym(Dn) of pq, pr, qr times fbar;  28-31 zero.
+ * Ids outside [0, qap_orbit_count(n)) give rows of NaN.
+ * Runs on the handle's stream and waits for it.
+ * Errors: QAP_EINVAL, QAP_ENOMEM, QAP_EDEVICE. */
+int qap_orbit_features(qap_handle h, const int64_t *ids, int64_t count, float *x);
+
+/* Training targets: tracked v of each listed orbit's six members divided by
+ * `scale` (FP64) and rounded to float32 (t: device, count*6; NaN rows for
+ * ids out of range).  Runs on the handle's stream and waits for it.  Errors: QAP_ESTATE (tracking off),
+ * QAP_EINVAL.
+ * Device inputs of these calls must be complete when the call is made: the
+ * handle's stream does not wait for the caller's streams. */
+int qap_orbit_targets(qap_handle h, const int64_t *ids, int64_t count, double scale, float *t);
+
+/* S-form restart from per-orbit outputs y (device, qap_orbit_count(n)*6
+ * float32, orbit-id order): v_e = (y_e - mean) * scale in FP64, the mean a
+ * left-to-right sum of the six outputs divided by 6; z costs 0 - v_e, x and
+ * y costs of step 1, LB = 0, t = 0.  Errors: QAP_EINVAL, QAP_EDEVICE. */
+int qap_warm_start_outputs(qap_handle h, const float *y, double scale);
+
+/* The perceptron: 32 inputs, two hidden layers of 256 (ReLU), 6 outputs.
+ * Parameters (float32, 75782): W1 [256][32], b1 [256], W2 [256][256],
+ * b2 [256], W3 [6][256], b3 [6], back to back.  Forward:
+ *   h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = W3 h2 + b3,
+ * every matrix-product operand (inputs, weights, h1, h2) rounded to bf16,
+ * float32 accumulation.  Loss: mean over samples and outputs of
+ * (y - mean6(y) - t)^2.  Backward rounds its product operands to bf16 too
+ * (output error, and the hidden errors after the ReLU masks); bias gradients
+ * sum the unrounded errors.  Adam (Kingma and Ba) on float32 masters. */
+typedef struct qap_mlp *qap_mlp_handle;
+
+typedef struct qap_adam_params {
+    double lr, beta1, beta2, eps;
+} qap_adam_params;
+
+typedef struct qap_warm_stats {
+    long long orbits;
+    double scale;
+    double ms_mlp;     /* features + perceptron over all orbits (device time) */
+    double ms_write;   /* z writer and restart (device time) */
+    double seconds;    /* wall time of qap_warm_start */
+    double mlp_flops;  /* 2 * orbits * (32*256 + 256*256 + 256*6) */
+} qap_warm_stats;
+
+/* params: host, 75782 floats; max_batch: largest training/forward batch;
+ * stream: HIP stream for all of its work (NULL: the null stream).
+ * Errors: QAP_EINVAL, QAP_ENOMEM, QAP_EDEVICE. */
+int qap_mlp_create(const float *params, int max_batch, void *stream, qap_mlp_handle *out);
+int qap_mlp_destroy(qap_mlp_handle p);
+int qap_mlp_set_stream(qap_mlp_handle p, void *stream);
+/* Host copy of the float32 master parameters. */
+int qap_mlp_get_params(qap_mlp_handle p, float *params);
+/* Forward of `count` <= max_batch samples: x device [count][32], y device
+ * [count][6]; enqueued on the perceptron's stream. */
+int qap_mlp_forward(qap_mlp_handle p, const float *x, int count, float *y);
+/* Loss and gradients (host, 75782 floats, parameter order; nullable) of
+ * `count` samples with targets t (device [count][6]); waits for the stream. */
+int qap_mlp_gradients(qap_mlp_handle p, const float *x, const float *t, int count, float *grad,
+                      double *loss);
+/* One Adam step on `count` samples; *loss (nullable) gets the loss before the
+ * step.  Errors: QAP_EINVAL (count, hyper-parameters), QAP_EDEVICE. */
+int qap_mlp_train_step(qap_mlp_handle p, const float *x, const float *t, int count,
+                       const qap_adam_params *opt, double *loss);
+
+/* Features and perceptron over every orbit of the handle's instance (y:
+ * device, qap_orbit_count(n)*6 float32, orbit-id order).  Runs on the
+ * handle's stream after waiting for the perceptron's; waits for completion. */
+int qap_orbit_outputs(qap_handle h, qap_mlp_handle p, float *y);
+
+/* Learned warm start: qap_orbit_outputs into a temporary device buffer, then
+ * qap_warm_start_outputs with qap_multiplier_scale.  st nullable.
+ * Errors: QAP_ENOMEM (buffer of 24 bytes per orbit), QAP_EDEVICE. */
+int qap_warm_start(qap_handle h, qap_mlp_handle p, qap_warm_stats *st);
+
 #ifdef __cplusplus
 }
 #endif

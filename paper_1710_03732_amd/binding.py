@@ -65,6 +65,21 @@ class QapStateHeader(C.Structure):
                 ("checksum", C.c_uint64)]
 
 
+class QapAdamParams(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double)]
+
+
+class QapWarmStats(C.Structure):
+    _fields_ = [("orbits", C.c_longlong), ("scale", C.c_double), ("ms_mlp", C.c_double),
+                ("ms_write", C.c_double), ("seconds", C.c_double), ("mlp_flops", C.c_double)]
+
+
+MLP_PARAMS = 75782   # W1 [256][32], b1, W2 [256][256], b2, W3 [6][256], b3
+MLP_SHAPES = (("W1", (256, 32)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
+              ("W3", (6, 256)), ("b3", (6,)))
+
+
 _dp = C.POINTER(C.c_double)
 _i32p = C.POINTER(C.c_int32)
 _lib = None
@@ -73,7 +88,11 @@ EXPORTED = ("qap_version", "qap_default_params", "qap_workspace_bytes", "qap_rlt
             "qap_destroy", "qap_dual_ascent", "qap_get_trace", "qap_get_assignment",
             "qap_export_state", "qap_export_z_tiles", "qap_import_state", "qap_set_stream", "qap_bnb_solve",
             "qap_lap_batch", "qap_last_error", "qap_fold_child", "qap_batch_dual_ascent",
-            "qap_node_status")
+            "qap_node_status", "qap_track", "qap_get_multipliers", "qap_set_multipliers",
+            "qap_orbit_count", "qap_multiplier_scale", "qap_orbit_features", "qap_orbit_targets",
+            "qap_warm_start_outputs", "qap_mlp_create", "qap_mlp_destroy", "qap_mlp_set_stream",
+            "qap_mlp_get_params", "qap_mlp_forward", "qap_mlp_gradients", "qap_mlp_train_step",
+            "qap_orbit_outputs", "qap_warm_start")
 
 
 def lib():
@@ -108,6 +127,24 @@ def lib():
                                       C.POINTER(C.c_int)]
         L.qap_last_error.argtypes = [C.c_void_p]
         L.qap_last_error.restype = C.c_char_p
+        vp = C.c_void_p
+        L.qap_track.argtypes = [vp, C.c_int]
+        L.qap_get_multipliers.argtypes = [vp, _dp, _dp]
+        L.qap_set_multipliers.argtypes = [vp, _dp, _dp]
+        L.qap_orbit_count.argtypes = [C.c_int, C.POINTER(C.c_int64)]
+        L.qap_multiplier_scale.argtypes = [vp, _dp]
+        L.qap_orbit_features.argtypes = [vp, vp, C.c_int64, vp]
+        L.qap_orbit_targets.argtypes = [vp, vp, C.c_int64, C.c_double, vp]
+        L.qap_warm_start_outputs.argtypes = [vp, vp, C.c_double]
+        L.qap_mlp_create.argtypes = [C.POINTER(C.c_float), C.c_int, vp, C.POINTER(vp)]
+        L.qap_mlp_destroy.argtypes = [vp]
+        L.qap_mlp_set_stream.argtypes = [vp, vp]
+        L.qap_mlp_get_params.argtypes = [vp, C.POINTER(C.c_float)]
+        L.qap_mlp_forward.argtypes = [vp, vp, C.c_int, vp]
+        L.qap_mlp_gradients.argtypes = [vp, vp, vp, C.c_int, C.POINTER(C.c_float), _dp]
+        L.qap_mlp_train_step.argtypes = [vp, vp, vp, C.c_int, C.POINTER(QapAdamParams), _dp]
+        L.qap_orbit_outputs.argtypes = [vp, vp, vp]
+        L.qap_warm_start.argtypes = [vp, vp, C.POINTER(QapWarmStats)]
         _lib = L
     return _lib
 
@@ -270,6 +307,157 @@ class DualAscent:
         return obj.value, perm, {"nodes": st.nodes, "da_iters": st.da_iters,
                                  "batches": st.batches, "enumerated": st.enumerated,
                                  "seconds": st.seconds}
+
+
+    # ---- multipliers and the learned warm start ---------------------------
+    def track(self, on: bool = True):
+        _check(lib().qap_track(self.h, 1 if on else 0), self.h)
+
+    def multipliers(self):
+        """Tracked (v, u) in the z and y layouts (host float64)."""
+        v = np.zeros(self.T * self.m * self.m)
+        u = np.zeros(self.T)
+        _check(lib().qap_get_multipliers(self.h, _dptr(v), _dptr(u)), self.h)
+        return v, u
+
+    def set_multipliers(self, v=None, u=None):
+        vv = None if v is None else _f64(v).reshape(-1)
+        uu = None if u is None else _f64(u).reshape(-1)
+        _check(lib().qap_set_multipliers(self.h, None if vv is None else _dptr(vv),
+                                         None if uu is None else _dptr(uu)), self.h)
+
+    def multiplier_scale(self) -> float:
+        s = C.c_double(0.0)
+        _check(lib().qap_multiplier_scale(self.h, C.byref(s)), self.h)
+        return s.value
+
+    def orbit_features(self, ids):
+        """ids: int64 CUDA tensor; returns a float32 CUDA tensor (count, 32)."""
+        import torch
+
+        ids = ids.contiguous()
+        x = torch.empty((ids.numel(), 32), dtype=torch.float32, device=ids.device)
+        _check(lib().qap_orbit_features(self.h, C.c_void_p(ids.data_ptr()), ids.numel(),
+                                        C.c_void_p(x.data_ptr())), self.h)
+        return x
+
+    def orbit_targets(self, ids, scale: float, out=None):
+        import torch
+
+        ids = ids.contiguous()
+        t = out if out is not None else torch.empty((ids.numel(), 6), dtype=torch.float32,
+                                                    device=ids.device)
+        _check(lib().qap_orbit_targets(self.h, C.c_void_p(ids.data_ptr()), ids.numel(),
+                                       float(scale), C.c_void_p(t.data_ptr())), self.h)
+        return t
+
+    def orbit_outputs(self, mlp: "Mlp"):
+        import torch
+
+        y = torch.empty((orbit_count(self.n), 6), dtype=torch.float32, device="cuda")
+        _check(lib().qap_orbit_outputs(self.h, mlp.h, C.c_void_p(y.data_ptr())), self.h)
+        return y
+
+    def warm_start_outputs(self, y, scale: float):
+        y = y.contiguous()
+        _check(lib().qap_warm_start_outputs(self.h, C.c_void_p(y.data_ptr()), float(scale)), self.h)
+
+    def warm_start(self, mlp: "Mlp"):
+        st = QapWarmStats()
+        _check(lib().qap_warm_start(self.h, mlp.h, C.byref(st)), self.h)
+        return {"orbits": st.orbits, "scale": st.scale, "ms_mlp": st.ms_mlp,
+                "ms_write": st.ms_write, "seconds": st.seconds, "mlp_flops": st.mlp_flops}
+
+
+def orbit_count(n: int) -> int:
+    c = C.c_int64(0)
+    _check(lib().qap_orbit_count(int(n), C.byref(c)))
+    return c.value
+
+
+def pack_mlp_params(tensors: dict) -> np.ndarray:
+    """Concatenate W1, b1, W2, b2, W3, b3 (any float arrays) into the
+    library's float32 parameter block."""
+    parts = []
+    for name, shape in MLP_SHAPES:
+        a = np.asarray(tensors[name], dtype=np.float32)
+        if a.shape != shape:
+            raise ValueError(f"{name}: shape {a.shape}, expected {shape}")
+        parts.append(a.reshape(-1))
+    return np.ascontiguousarray(np.concatenate(parts))
+
+
+def unpack_mlp_params(flat) -> dict:
+    out, o = {}, 0
+    for name, shape in MLP_SHAPES:
+        k = int(np.prod(shape))
+        out[name] = np.asarray(flat[o:o + k]).reshape(shape)
+        o += k
+    return out
+
+
+class Mlp:
+    """The warm start's perceptron on the GPU (float32 masters, bf16 MFMA
+    kernels).  Device tensors are torch CUDA tensors."""
+
+    def __init__(self, params, max_batch: int = 8192, stream: int | None = None):
+        import torch
+
+        flat = params if isinstance(params, np.ndarray) and params.ndim == 1 else pack_mlp_params(params)
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        if flat.size != MLP_PARAMS:
+            raise ValueError("parameter block of 75782 floats expected")
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.max_batch = int(max_batch)
+        h = C.c_void_p()
+        _check(lib().qap_mlp_create(flat.ctypes.data_as(C.POINTER(C.c_float)), self.max_batch,
+                                    C.c_void_p(stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().qap_mlp_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream: int):
+        _check(lib().qap_mlp_set_stream(self.h, C.c_void_p(stream)))
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(lib().qap_mlp_get_params(self.h, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def forward(self, x):
+        import torch
+
+        x = x.contiguous()
+        y = torch.empty((x.shape[0], 6), dtype=torch.float32, device=x.device)
+        _check(lib().qap_mlp_forward(self.h, C.c_void_p(x.data_ptr()), x.shape[0],
+                                     C.c_void_p(y.data_ptr())))
+        return y
+
+    def gradients(self, x, t):
+        x, t = x.contiguous(), t.contiguous()
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        loss = C.c_double(0.0)
+        _check(lib().qap_mlp_gradients(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                       x.shape[0], g.ctypes.data_as(C.POINTER(C.c_float)),
+                                       C.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, x, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8) -> float:
+        opt = QapAdamParams(float(lr), float(beta1), float(beta2), float(eps))
+        loss = C.c_double(0.0)
+        _check(lib().qap_mlp_train_step(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                        x.shape[0], C.byref(opt), C.byref(loss)))
+        return loss.value
 
 
 def batch_run(handles, iters: int, window: int = 0, min_improve: float = 0.0,

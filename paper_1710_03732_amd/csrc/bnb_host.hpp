@@ -134,6 +134,7 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
     for (int b = 0; b < count; ++b) {
         if (!hs[b] || hs[b]->prm.device != h0->prm.device) return fail(h0, QAP_EINVAL, "handles on one device");
         if (hs[b]->n > 64) return fail(h0, QAP_EUNSUPPORTED, "n > 64 in a batch");
+        if (hs[b]->Vt) return fail(h0, QAP_ESTATE, "a batched handle tracks multipliers");
     }
     auto t0 = std::chrono::steady_clock::now();
     HIPCHK(h0, hipSetDevice(h0->prm.device));

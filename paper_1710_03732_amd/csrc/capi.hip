@@ -56,6 +56,8 @@ struct qap_ctx {
     std::vector<double> hF, hD, hB;
     std::string err;
     hipGraphExec_t graph = nullptr;  // one full iteration (t >= 1)
+    // multiplier tracking (Vz entries like Z, T entries like Yc), or null
+    double *Vt = nullptr, *Ut = nullptr;
 };
 
 namespace {
@@ -189,7 +191,7 @@ hipError_t launch_ylap_t(qap_ctx *h, int equalize)
     while (G > 1 && (size_t)G * per > 65536) --G;
     const int blocks = (n * n + G - 1) / G;
     hipLaunchKernelGGL((k_ylap<L, C>), dim3(blocks), dim3(G * L), G * per, h->stream, h->Yc, h->Py,
-                       h->Xc, n, equalize, h->ophy, h->phy, h->S, h->bins);
+                       h->Xc, n, equalize, h->ophy, h->phy, h->S, h->bins, h->Ut);
     return hipGetLastError();
 }
 
@@ -210,8 +212,12 @@ hipError_t launch_sweep(qap_ctx *h)
         const unsigned groups8 = (unsigned)((h->ntriples + 7) / 8);
         const int nb = (h->n + SB - 1) / SB;
         const unsigned blocks = groups8 * 8u * (unsigned)(nb * nb * nb);
-        hipLaunchKernelGGL(k_sweep, dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py, h->Px,
-                           h->triples, h->ntriples, h->n, nb, K, h->S);
+        if (h->Vt)
+            hipLaunchKernelGGL(k_sweep<true>, dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py, h->Px,
+                               h->triples, h->ntriples, h->n, nb, K, h->S, h->Vt);
+        else
+            hipLaunchKernelGGL(k_sweep<false>, dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py, h->Px,
+                               h->triples, h->ntriples, h->n, nb, K, h->S, (double *)nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const long long work = std::max<long long>(h->T, (long long)h->n * h->n);
         const unsigned sb = (unsigned)std::min<long long>((work + 255) / 256, 65535);
@@ -528,6 +534,13 @@ int qap_destroy(qap_handle h)
             (void)hipFree(h->arena);
     }
     if (h->trace) (void)hipFree(h->trace);
+    for (double *a : {h->Vt, h->Ut}) {
+        if (!a) continue;
+        if (h->prm.alloc && h->prm.free_fn)
+            h->prm.free_fn(a, h->prm.alloc_ctx);
+        else if (!h->prm.alloc)
+            (void)hipFree(a);
+    }
     if (h->stream && h->own_stream) (void)hipStreamDestroy(h->stream);
     delete h;
     return QAP_OK;
@@ -792,3 +805,4 @@ const char *qap_last_error(qap_handle h)
 }  // extern "C"
 
 #include "bnb_host.hpp"
+#include "learn_host.hpp"

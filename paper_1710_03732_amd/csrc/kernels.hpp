@@ -104,10 +104,16 @@ constexpr int SB_CUBE = SB * SB_P;          // doubles per staged member
 
 __device__ __forceinline__ int cube_idx(int pl, int ql, int rl) { return pl * SB_P + ql * SB_Q + rl; }
 
+//
+// With TRACK the sweep also accumulates each entry's Lagrange multiplier
+// change, g_e - phi * sum_{f != e} g_f (its own shares minus what it
+// receives from its partners, Eq. ch4:proof:2), into Vt (same layout as Z).
+template <bool TRACK>
 __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const double *__restrict__ Py,
                                                const double *__restrict__ Px,
                                                const int *__restrict__ triples, int ntriples, int n,
-                                               int nb, SweepConsts K, const DevScalars *__restrict__ S)
+                                               int nb, SweepConsts K, const DevScalars *__restrict__ S,
+                                               double *__restrict__ Vt)
 {
     if (S->stopped) return;
     // g_e staged per orbit position; the orbit phase overwrites it with phi*sum
@@ -191,7 +197,14 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
     for (int e = 0; e < 6; ++e)
 #pragma unroll
         for (int w = 0; w < PER; ++w)
-            if (ok[e][w]) Z[za[e][w]] = K.okz * pz[e][w] + gs[e * SB_CUBE + li[e][w]];
+            if (ok[e][w]) {
+                const double share = gs[e * SB_CUBE + li[e][w]];
+                Z[za[e][w]] = K.okz * pz[e][w] + share;
+                if (TRACK) {
+                    const double g = (K.kz * pz[e][w] + K.ky2 * py[e][w]) + K.kx3 * px[e][w];
+                    Vt[za[e][w]] = Vt[za[e][w]] + (g - share);
+                }
+            }
 }
 
 // R_y <- (1-ky) pi_y, R_x <- (1-kx) pi_x (after the sweep has read them).
@@ -359,12 +372,14 @@ __global__ __launch_bounds__(64) void k_lap_batch_s(const double *__restrict__ c
 // One group per (i,p); its (n-1)x(n-1) block of R_y is contiguous.  For
 // t >= 1 every entry is first replaced by ophy*R_y[ijpq] + phy*R_y[jiqp]
 // (the y-pair rule applied by both members of the pair).  Writes pi_y to Py
-// and adds Delta_ip to R_x.
+// and adds Delta_ip to R_x.  With Ut (same layout as Yc) each entry's
+// multiplier moves by phy * (own - partner) (Eq. da:yrule1).
 template <int L, int C>
 __global__ __launch_bounds__(256) void k_ylap(const double *__restrict__ Yc, double *__restrict__ Py,
                                               double *__restrict__ Xc, int n, int equalize,
                                               double ophy, double phy, DevScalars *__restrict__ S,
-                                              unsigned long long *__restrict__ bins)
+                                              unsigned long long *__restrict__ bins,
+                                              double *__restrict__ Ut)
 {
     if (S->stopped) return;
     extern __shared__ double lds[];
@@ -389,7 +404,9 @@ __global__ __launch_bounds__(256) void k_ylap(const double *__restrict__ Yc, dou
                 const int jp = e / m, qp = e % m;
                 const int j = jp + (jp >= i), q = qp + (qp >= p);
                 const long long tb = ((long long)(j * n + q) * m + (i - (i > j))) * m + (p - (p > q));
-                a = ophy * a + phy * Yc[tb];
+                const double b = Yc[tb];
+                if (Ut) Ut[base + e] = Ut[base + e] + phy * (a - b);
+                a = ophy * a + phy * b;
             }
             M[e] = a;
         }

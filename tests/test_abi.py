@@ -75,3 +75,35 @@ def test_lap_batch_rejects_bad_sizes():
     assert lib.qap_lap_batch(None, 1, 0, None, None, None, None, 0, 0, None) == -1
     assert lib.qap_lap_batch(None, 1, 65, None, None, None, None, 0, 0, None) == -1
     assert lib.qap_lap_batch(None, 0, 5, None, None, None, None, 0, 0, None) == 0
+
+
+def test_orbit_count_and_learned_entry_points_validate():
+    lib = B.lib()
+    c = ctypes.c_int64(0)
+    assert lib.qap_orbit_count(3, ctypes.byref(c)) == 0 and c.value == 6
+    assert lib.qap_orbit_count(30, ctypes.byref(c)) == 0 and c.value == 4060 * 24360
+    assert lib.qap_orbit_count(2, ctypes.byref(c)) == -1
+    assert lib.qap_orbit_count(65, ctypes.byref(c)) == -1
+    assert lib.qap_track(None, 1) == -1
+    assert lib.qap_get_multipliers(None, None, None) == -1
+    assert lib.qap_set_multipliers(None, None, None) == -1
+    assert lib.qap_warm_start_outputs(None, None, 1.0) == -1
+    assert lib.qap_warm_start(None, None, None) == -1
+    out = ctypes.c_void_p()
+    assert lib.qap_mlp_create(None, 16, None, ctypes.byref(out)) == -1
+    params = np.zeros(B.MLP_PARAMS, dtype=np.float32)
+    fp = params.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    assert lib.qap_mlp_create(fp, 0, None, ctypes.byref(out)) == -1
+    params[7] = np.nan
+    assert lib.qap_mlp_create(fp, 16, None, ctypes.byref(out)) == -1
+    assert lib.qap_mlp_destroy(None) == -1
+
+
+def test_mlp_parameter_packing_round_trip():
+    rng = np.random.default_rng(0)
+    p = {name: rng.standard_normal(shape) for name, shape in B.MLP_SHAPES}
+    flat = B.pack_mlp_params(p)
+    assert flat.dtype == np.float32 and flat.size == B.MLP_PARAMS
+    back = B.unpack_mlp_params(flat)
+    for name, _ in B.MLP_SHAPES:
+        np.testing.assert_array_equal(back[name], p[name].astype(np.float32))
