@@ -14,8 +14,11 @@ stream, each phase between HIP events recorded on that stream.
 
 Prints one JSON line.  `roofline` is for the kernel with the largest device
 time; its `achieved` is algorithmic bytes per launch / average launch time.
-`cpu_baseline` times the CPU oracle (all OpenMP threads) on one iteration of
-the same workload.
+`time_to_bound` compares 100 cold iterations with the learned warm start
+(trained weights from train_warm.py) reaching the same bound; its
+`mlp_roofline` gives the inference kernel's TFLOP/s against the bf16 MFMA
+peak.  `cpu_baseline` times the CPU oracle (all OpenMP threads) on one
+iteration of the same workload.
 """
 from __future__ import annotations
 
@@ -30,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 MFMA
 
 
 def algorithmic_bytes(n: int) -> dict:
@@ -93,6 +97,26 @@ def cpu_baseline(inst, threads: int | None):
             "seconds": el, "lb_after": cpu.LB}
 
 
+def warm_vs_cold(inst, cold_iters: int):
+    """Time-to-bound: wall time of `cold_iters` cold F1 iterations (W, bound
+    LB_cold) against the learned warm start (features, inference and z
+    writer included) plus the F1 iterations it needs to reach LB_cold."""
+    from paper_1710_03732_amd import binding, train_warm
+
+    if not os.path.exists(train_warm.WEIGHTS):
+        return {"skipped": "no trained weights (paper_1710_03732_amd/train_warm.py)"}
+    mlp = binding.Mlp(train_warm.load_weights(), max_batch=256)
+    res = train_warm.time_to_bound(inst, mlp, cold_iters)
+    ms = res["warm_start_ms_mlp"]
+    flops = 2.0 * binding.orbit_count(inst.n) * (32 * 256 + 256 * 256 + 256 * 6)
+    res["mlp_roofline"] = {"bound": "mfma", "kernel": "k_orbit_mlp", "achieved": flops / (ms * 1e-3) / 1e12,
+                           "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": flops / (ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, "flops": flops,
+                           "ms": ms}
+    mlp.close()
+    return res
+
+
 def calibrate_copy(nbytes: int = 1 << 31):
     """A plain device copy of known size, for scaling PMC byte counters."""
     import torch
@@ -117,6 +141,9 @@ def main(argv=None):
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--zlap-lanes", type=int, default=0)
     ap.add_argument("--zlap-cols", type=int, default=0)
+    ap.add_argument("--no-time-to-bound", action="store_true")
+    ap.add_argument("--cold-iters", type=int, default=100,
+                    help="cold iterations whose bound the learned warm start must reach")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 2 GiB device copy (PMC counter calibration)")
     args = ap.parse_args(argv)
@@ -213,6 +240,13 @@ def main(argv=None):
         "cpu_baseline": None,
     }
     da.close()
+    if not args.no_time_to_bound:
+        from paper_1710_03732_amd import instances as insts
+
+        ttb = {inst.name: warm_vs_cold(inst, args.cold_iters)}
+        if inst.name == "dense_n30":  # the headline's second instance
+            ttb["grid_n30"] = warm_vs_cold(insts.grid_n30(), args.cold_iters)
+        out["time_to_bound"] = ttb
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_threads or None)
