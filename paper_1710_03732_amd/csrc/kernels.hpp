@@ -314,10 +314,20 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
     __builtin_amdgcn_wave_barrier();
     if (l < m && h < nt) ((double *)lps[h])[l] = v;
     __syncthreads();
-    for (int e = lane; e < nt * mm; e += 64) {
-        const int gg = e / mm, w = e - gg * mm;
-        const double *us = scr + (size_t)gg * 2 * m;
-        src[e] = (lds[e] - us[w / m]) - us[m + w % m];
+    // slacks back in place, row by row (no index division): a lane owns one
+    // column; with one LAP of m <= 32 per wave the two half-waves take
+    // alternate rows
+    {
+        const bool two = (H == 1) && (m <= 32);
+        const int sub = two ? (lane >> 5) : 0;
+        const int col = (H == 1 && !two) ? lane : (lane & 31);
+        if (h < nt && col < m) {
+            const double *us = scr + (size_t)h * 2 * m;
+            const double vc = us[m + col];
+            const double *tl = lds + (size_t)h * mm;
+            double *dst = src + (size_t)h * mm;
+            for (int r = sub; r < m; r += (two ? 2 : 1)) dst[r * m + col] = (tl[r * m + col] - us[r]) - vc;
+        }
     }
     if (l == 0 && h < nt) Yc[t0 + h] = Yc[t0 + h] + th;
     int stt = st;
