@@ -117,6 +117,26 @@ def warm_vs_cold(inst, cold_iters: int):
     return res
 
 
+def bnb_leg():
+    """Branch-and-bound on the n = 14 dense instance: forced branching (4
+    iterations per node, batches of up to 256 nodes of mixed depth) and the
+    default settings (the root bound closes it)."""
+    from paper_1710_03732_amd import binding, instances as insts
+
+    inst = insts.dense_n14()
+    F, D, B = inst.arrays()
+    out = {"instance": inst.name}
+    for label, kw in (("branching", dict(batch=256, node_iters=4, window=25)), ("default", {})):
+        h = binding.DualAscent(F, D, B)
+        t0 = time.perf_counter()
+        obj, perm, st = h.bnb_solve(**kw)
+        el = time.perf_counter() - t0
+        h.close()
+        out[label] = {"optimum": obj, "seconds": el, "nodes": st["nodes"], "batches": st["batches"],
+                      "da_iterations": st["da_iters"], "nodes_per_s": st["nodes"] / el, **kw}
+    return out
+
+
 def calibrate_copy(nbytes: int = 1 << 31):
     """A plain device copy of known size, for scaling PMC byte counters."""
     import torch
@@ -142,6 +162,7 @@ def main(argv=None):
     ap.add_argument("--zlap-lanes", type=int, default=0)
     ap.add_argument("--zlap-cols", type=int, default=0)
     ap.add_argument("--no-time-to-bound", action="store_true")
+    ap.add_argument("--no-bnb", action="store_true", help="skip the n = 14 branch-and-bound leg")
     ap.add_argument("--cold-iters", type=int, default=100,
                     help="cold iterations whose bound the learned warm start must reach")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -236,10 +257,13 @@ def main(argv=None):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": ab[dom],
                      "avg_launch_ms": phase_ms[dom]},
+        "bnb": None,
         "time_to_bound": None,
         "cpu_baseline": None,
     }
     da.close()
+    if not args.no_bnb and inst.name == "dense_n30":
+        out["bnb"] = bnb_leg()
     if not args.no_time_to_bound:
         from paper_1710_03732_amd import instances as insts
 

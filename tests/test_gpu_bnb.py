@@ -126,3 +126,16 @@ def test_bnb_dense_n14_batched():
     assert st["nodes"] > 1 and st["batches"] >= 2
     obj2, perm2, st2 = h.bnb_solve()  # defaults: the root bound alone closes it
     assert obj2 == g["optimum"]
+
+
+@pytest.mark.parametrize("inst", [I.random_instance(3, 20), I.random_instance(4, 21, lo=-3, hi=7)],
+                         ids=lambda x: x.name)
+def test_bnb_smallest_sizes(inst):
+    F, D, Bm = inst.arrays()
+    opt, _ = O.bruteforce(F, D, Bm)
+    obj, perm, st = B.DualAscent(F, D, Bm).bnb_solve()
+    assert obj == opt and O.qap_cost(F, D, Bm, perm) == opt
+
+
+def test_batch_of_no_handles():
+    assert B.batch_run([], iters=5)["iterations"] == 0

@@ -287,3 +287,26 @@ def test_trained_warm_start_beats_cold_on_heldout(idx):
     assert np.all(warm.trace() <= ub + 1e-9 * ub)
     hit = np.nonzero(tr >= rc["lb"])[0]
     assert len(hit) and hit[0] + 1 <= 80, (hit[:1], rc["lb"], tr[-1])
+
+
+@pytest.mark.parametrize("n", [3, 4])
+def test_warm_start_smallest_sizes(n):
+    """One facility triple (n = 3, six orbits, 1x1 Z-LAPs): writer and
+    inference still agree with the oracle and the bound stays valid."""
+    inst = I.random_instance(n, 30 + n, lo=0, hi=9)
+    F, D, Bm = inst.arrays()
+    opt, _ = O.bruteforce(F, D, Bm)
+    y = (np.random.default_rng(n).standard_normal((L.orbit_count(n), 6))).astype(np.float32)
+    scale = L.scales(F, D)[2]
+    g = B.DualAscent(F, D, Bm)
+    g.warm_start_outputs(torch.tensor(y, device="cuda"), scale)
+    w = O.DualAscent.from_multipliers(F, D, Bm, O.FULL, L.multipliers_from_outputs(n, y, scale), None)
+    _state_equal(g, w)
+    g.run(4)
+    w.run(4)
+    assert np.array_equal(g.trace(), w.trace())
+    assert np.all(g.trace() <= opt + 1e-9 * abs(opt))
+    mlp = B.Mlp(_params(105), max_batch=64)
+    yo = g.orbit_outputs(mlp).cpu().numpy()
+    ref, _ = L.forward(_oracle_params(_params(105)), L.features(F, D, Bm, np.arange(L.orbit_count(n))), True)
+    assert _rel(yo, ref) <= 1e-3

@@ -259,3 +259,68 @@ def test_full_size_n30_sampled(inst):
     assert tr[-1] <= g["ub"]
     got = gpu.export_tiles(tiles)
     assert got.min() >= -1e-9 * F.max() * D.max()
+
+
+def test_full_size_n42_iteration0_and_sampled_tiles():
+    """The largest benchmark size, n = 42 (4.74 G z entries, 38 GB): iteration
+    0 in full against the oracle and the Gilmore-Lawler closed form, then
+    sampled iteration-1 tiles recomputed entry by entry."""
+    from scipy.optimize import linear_sum_assignment
+
+    inst = I.dense_n42()
+    F, D, Bm = inst.arrays()
+    n = 42
+    gpu = B.DualAscent(F, D, Bm)
+    gpu.run(1)
+    ref = O.Iter0XY(F, D, Bm)
+    X0, Y0 = ref.xy()
+    hdr, x, y, _ = gpu.export_state(with_z=False)
+    assert hdr.lb == ref.LB and hdr.ub == ref.UB
+    assert np.array_equal(x, X0.reshape(-1))
+    assert np.array_equal(y, dense_to_compact_y(n, Y0))
+    L = np.zeros((n, n))
+    for i in range(n):
+        fi = np.sort(np.delete(F[i], i))
+        for p in range(n):
+            L[i, p] = Bm[i, p] + F[i, i] * D[p, p] + float(fi @ np.sort(np.delete(D[p], p))[::-1])
+    r, c = linear_sum_assignment(L)
+    assert hdr.lb == float(L[r, c].sum())
+    gpu.run(1)
+    rng = np.random.default_rng(42)
+    picks = [(0, 1, 0, 1), (41, 40, 41, 40)]
+    for _ in range(10):
+        i, j = rng.choice(n, 2, replace=False)
+        p, q = rng.choice(n, 2, replace=False)
+        picks.append((int(i), int(j), int(p), int(q)))
+    got = gpu.export_tiles([tile_index(n, i, p, j, q) for (i, j, p, q) in picks])
+    for a, (i, j, p, q) in enumerate(picks):
+        _, pi, _ = ref.tile1(i, j, p, q)
+        assert np.array_equal(got[a], pi), (i, j, p, q)
+    gpu.close()
+
+
+def test_size_beyond_device_memory_is_rejected_before_allocation():
+    """n = 64 needs a 500 GB z array: init fails with QAP_ENOMEM, cleanly."""
+    F = np.ones((64, 64))
+    with pytest.raises(B.QapError) as e:
+        B.DualAscent(F, F)
+    assert e.value.code == -2
+    # the device is still usable afterwards
+    g = B.DualAscent(*I.random_instance(5, 11).arrays())
+    g.run(2)
+
+
+def test_zero_flows_reduce_to_a_lap_on_b():
+    """f = 0: iteration 0 is the LAP on b, optimal and certified."""
+    from scipy.optimize import linear_sum_assignment
+
+    rng = np.random.default_rng(12)
+    n = 9
+    Bm = rng.integers(-20, 50, (n, n)).astype(float)
+    F = np.zeros((n, n))
+    D = rng.integers(0, 30, (n, n)).astype(float)
+    g = B.DualAscent(F, D, Bm)
+    r = g.run(5)
+    rr, cc = linear_sum_assignment(Bm)
+    assert r["lb"] == Bm[rr, cc].sum() == r["ub"]
+    assert r["proven"] and r["iterations_done"] == 1
