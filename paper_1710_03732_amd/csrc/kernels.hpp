@@ -310,7 +310,10 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
     __syncthreads();
     double u, v, th;
     int p, st;
-    lap_solve_scalar<H>(tiles, lus, lps, lws, m, nt, u, v, p, th, st);
+    if (H == 1 && m <= 32)
+        lap_solve_scalar<1, 32>(tiles, lus, lps, lws, m, nt, u, v, p, th, st);
+    else
+        lap_solve_scalar<H>(tiles, lus, lps, lws, m, nt, u, v, p, th, st);
     __builtin_amdgcn_wave_barrier();
     if (l < m && h < nt) ((double *)lps[h])[l] = v;
     __syncthreads();

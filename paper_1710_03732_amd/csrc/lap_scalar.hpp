@@ -33,9 +33,9 @@ __device__ __forceinline__ double mov_dpp_d(double x)
     return __hiloint2double(hi, lo);
 }
 
-// min over each 32-lane half (H = 2) or the whole wave (H = 1); every lane
-// receives the minimum of its part.  Inputs are never NaN.
-template <int H>
+// min over each 32-lane half (RW = 32) or the whole wave (RW = 64); every
+// lane receives the minimum of its half / of the wave.  Inputs are never NaN.
+template <int RW>
 __device__ __forceinline__ double part_min(double x)
 {
     x = vmin_f64(x, mov_dpp_d<0x128>(x));  // row_ror:8
@@ -47,7 +47,7 @@ __device__ __forceinline__ double part_min(double x)
         const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(x), false, false);
         x = vmin_f64(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
     }
-    if constexpr (H == 1) {
+    if constexpr (RW == 64) {
         const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(x), false, false);
         const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(x), false, false);
         x = vmin_f64(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
@@ -62,7 +62,10 @@ __device__ __forceinline__ int sgpr(int x) { return __builtin_amdgcn_readfirstla
 // live (the others are skipped).  Outputs for lane l of part h: u (row l),
 // v (column l), p (row matched to column l, -1 past m); theta and steps of
 // the lane's part.  On return lu[h] holds that part's row potentials.
-template <int H>
+// RW: width of the step's min reduction, 32 when every live column sits in
+// the lower half-wave (H = 2, or H = 1 with m <= 32: the upper lanes never
+// take part, and what they receive is never used), else 64.
+template <int H, int RW = (H == 1 ? 64 : 32)>
 __device__ void lap_solve_scalar(const double *const *tile, double *const *lu, int *const *lp,
                                  int *const *lw, int m, int nparts, double &u, double &v, int &p,
                                  double &theta, int &steps)
@@ -149,7 +152,7 @@ __device__ void lap_solve_scalar(const double *const *tile, double *const *lu, i
             minv = s;
             way = my_last;
         }
-        const double mn = part_min<H>(act ? minv : kInf);
+        const double mn = part_min<RW>(act ? minv : kInf);
         const bool cand = act && minv == mn;
         const unsigned long long bc = __builtin_amdgcn_ballot_w64(cand);
         const unsigned long long bf = __builtin_amdgcn_ballot_w64(cand && p < 0);
