@@ -189,17 +189,15 @@ __device__ void lap_solve_scalar(const double *const *tile, double *const *lu, i
                 last[q] = js[q];
                 continue;
             }
-            // flip the alternating path of part q back to its root row
-            if (mine && valid) {
-                mlw[l] = way;
-                if (intree) mlu[l] = u;
-            }
+            // flip the alternating path of part q back to its root row; the
+            // path links are the lanes' own `way` registers
+            if (mine && valid && intree) mlu[l] = u;
             __builtin_amdgcn_wave_barrier();
             unsigned long long onpath = 0ull;
             int j = js[q];
             while (j >= 0) {
                 onpath |= 1ull << j;
-                j = sgpr(lw[q][j]);
+                j = __builtin_amdgcn_readlane(way, q * W + j);
             }
             int np = -1;
             const bool flip = mine && valid && ((onpath >> l) & 1ull);
