@@ -170,8 +170,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); the multi-GPU "
-              "design is described in DESIGN.md and not built", file=sys.stderr)
+        print("bench.py: runs on one GPU only (--gpus 1); sharding the dual ascent over "
+              "several GPUs is not implemented", file=sys.stderr)
         return 2
 
     import torch
