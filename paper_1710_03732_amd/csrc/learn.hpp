@@ -195,8 +195,17 @@ __global__ void k_orbit_targets(const long long *__restrict__ ids, long long cou
 
 // ------------------------------------------------------- fused inference --
 constexpr int kMlpThreads = 512;   // 8 waves, 2 per SIMD
-constexpr int kOrbitsPerWave = 32; // one MFMA column block
+constexpr int kMlpNB = 1;          // 32-orbit column blocks per wave pass (2 spills at 2 waves/SIMD)
+constexpr int kOrbitsPerWave = 32 * kMlpNB;
 
+// relu as one integer max on the bit pattern: a negative float (-0 included)
+// is a negative int32 and becomes +0, anything else is kept.  fmaxf would add
+// a NaN-quieting max first; inputs here are finite.  Plain C, not inline asm:
+// the compiler must see this read of MFMA results to insert its wait states.
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+// Each wave pass takes kMlpNB blocks of 32 orbits; every weight fragment read
+// from LDS feeds one MFMA per block.
 __global__ __launch_bounds__(kMlpThreads) void k_orbit_mlp(const bf16x8 *__restrict__ Wf,
                                                            const float *__restrict__ master,
                                                            const int *__restrict__ triples, FeatTables T,
@@ -222,76 +231,103 @@ __global__ __launch_bounds__(kMlpThreads) void k_orbit_mlp(const bf16x8 *__restr
     const long long stride = (long long)gridDim.x * (kMlpThreads / 64) * kOrbitsPerWave;
     for (long long base = ((long long)blockIdx.x * (kMlpThreads / 64) + wave) * kOrbitsPerWave; base < count;
          base += stride) {
-        const long long o = base + col;
-        const bool valid = o < count;
         // The weight fragments are loop-invariant; an opaque zero offset
         // keeps the compiler from hoisting all of them into registers.
         int z0;
         asm volatile("s_mov_b32 %0, 0" : "=s"(z0));
         const bf16x8 *wv = wl + z0;
-        float f[kFeat];
-        if (valid) {
-            int i, j, k, p, q, r;
-            decode_orbit(o, T.n, triples, i, j, k, p, q, r);
-            orbit_features(T, i, j, k, p, q, r, f);
-        } else {
+        // layer 1 B operands: chunk c of block nb holds inputs 16c + 8h + i
+        bf16x8 xb[kMlpNB][2];
 #pragma unroll
-            for (int c = 0; c < kFeat; ++c) f[c] = 0.f;
-        }
-        // layer 1: B operand of chunk c holds inputs 16c + 8h + i
-        bf16x8 xb[2];
+        for (int nb = 0; nb < kMlpNB; ++nb) {
+            const long long o = base + 32 * nb + col;
+            float f[kFeat];
+            if (o < count) {
+                int i, j, k, p, q, r;
+                decode_orbit(o, T.n, triples, i, j, k, p, q, r);
+                orbit_features(T, i, j, k, p, q, r, f);
+            } else {
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int i = 0; i < 8; ++i) xb[c][i] = (__bf16)(h ? f[16 * c + 8 + i] : f[16 * c + i]);
-        bf16x8 h1[16];
-#pragma unroll
-        for (int mb = 0; mb < 8; ++mb) {
-            f32x16 acc;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) acc[j] = bl[32 * mb + 8 * (j >> 2) + 4 * h + (j & 3)];
+                for (int c = 0; c < kFeat; ++c) f[c] = 0.f;
+            }
 #pragma unroll
             for (int c = 0; c < 2; ++c)
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wv[kFragW1 + (mb * 2 + c) * 64 + lane], xb[c], acc, 0,
-                                                              0, 0);
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+                for (int i = 0; i < 8; ++i) xb[nb][c][i] = (__bf16)(h ? f[16 * c + 8 + i] : f[16 * c + i]);
+        }
+        bf16x8 h1[kMlpNB][16];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) h1[2 * mb + a][i] = (__bf16)fmaxf(acc[8 * a + i], 0.f);
+        for (int mb = 0; mb < 8; ++mb) {
+            f32x16 acc[kMlpNB];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const float b = bl[32 * mb + 8 * (j >> 2) + 4 * h + (j & 3)];
+#pragma unroll
+                for (int nb = 0; nb < kMlpNB; ++nb) acc[nb][j] = b;
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const bf16x8 a = wv[kFragW1 + (mb * 2 + c) * 64 + lane];
+#pragma unroll
+                for (int nb = 0; nb < kMlpNB; ++nb)
+                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, xb[nb][c], acc[nb], 0, 0, 0);
+            }
+#pragma unroll
+            for (int nb = 0; nb < kMlpNB; ++nb)
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) h1[nb][2 * mb + a][i] = (__bf16)relu(acc[nb][8 * a + i]);
         }
         // layers 2 and 3: each pair of layer-2 output chunks feeds layer 3 at once
-        f32x16 acc3;
+        f32x16 acc3[kMlpNB];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int row = 8 * (j >> 2) + 4 * h + (j & 3);
-            acc3[j] = row < kOut ? bl[2 * kWidth + row] : 0.f;
+            const float b = row < kOut ? bl[2 * kWidth + row] : 0.f;
+#pragma unroll
+            for (int nb = 0; nb < kMlpNB; ++nb) acc3[nb][j] = b;
         }
 #pragma unroll
         for (int mb = 0; mb < 8; ++mb) {
-            f32x16 acc;
+            f32x16 acc[kMlpNB];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) acc[j] = bl[kWidth + 32 * mb + 8 * (j >> 2) + 4 * h + (j & 3)];
+            for (int j = 0; j < 16; ++j) {
+                const float b = bl[kWidth + 32 * mb + 8 * (j >> 2) + 4 * h + (j & 3)];
 #pragma unroll
-            for (int c = 0; c < 16; ++c)
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wv[kFragW2 + (mb * 16 + c) * 64 + lane], h1[c], acc, 0,
-                                                              0, 0);
+                for (int nb = 0; nb < kMlpNB; ++nb) acc[nb][j] = b;
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const bf16x8 a = wv[kFragW2 + (mb * 16 + c) * 64 + lane];
+#pragma unroll
+                for (int nb = 0; nb < kMlpNB; ++nb)
+                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, h1[nb][c], acc[nb], 0, 0, 0);
+            }
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
-                bf16x8 h2;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) h2[i] = (__bf16)fmaxf(acc[8 * a + i], 0.f);
                 bf16x8 w3 = wv[kFragW3 + ((2 * mb + a) * 2 + h) * kOut + w3row];
                 if (col >= kOut) w3 = bf16x8{};
-                acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w3, h2, acc3, 0, 0, 0);
+#pragma unroll
+                for (int nb = 0; nb < kMlpNB; ++nb) {
+                    bf16x8 h2;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) h2[i] = (__bf16)relu(acc[nb][8 * a + i]);
+                    acc3[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w3, h2, acc3[nb], 0, 0, 0);
+                }
             }
         }
-        if (valid) {
-            float2 *dst = (float2 *)(y + o * kOut);
-            if (h == 0) {
-                dst[0] = make_float2(acc3[0], acc3[1]);
-                dst[1] = make_float2(acc3[2], acc3[3]);
-            } else {
-                dst[2] = make_float2(acc3[0], acc3[1]);
+#pragma unroll
+        for (int nb = 0; nb < kMlpNB; ++nb) {
+            const long long o = base + 32 * nb + col;
+            if (o < count) {
+                float2 *dst = (float2 *)(y + o * kOut);
+                if (h == 0) {
+                    dst[0] = make_float2(acc3[nb][0], acc3[nb][1]);
+                    dst[1] = make_float2(acc3[nb][2], acc3[nb][3]);
+                } else {
+                    dst[2] = make_float2(acc3[nb][0], acc3[nb][1]);
+                }
             }
         }
     }
