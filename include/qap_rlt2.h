@@ -351,7 +351,8 @@ typedef struct qap_adam_params {
 
 typedef struct qap_warm_stats {
     long long orbits;
-    double scale;
+    double scale;      /* scale passed to the writer: qap_multiplier_scale * gain */
+    double gain;
     double ms_mlp;     /* features + perceptron over all orbits (device time) */
     double ms_write;   /* z writer and restart (device time) */
     double seconds;    /* wall time of qap_warm_start */
@@ -384,9 +385,13 @@ int qap_mlp_train_step(qap_mlp_handle p, const float *x, const float *t, int cou
 int qap_orbit_outputs(qap_handle h, qap_mlp_handle p, float *y);
 
 /* Learned warm start: qap_orbit_outputs into a temporary device buffer, then
- * qap_warm_start_outputs with qap_multiplier_scale.  st nullable.
- * Errors: QAP_ENOMEM (buffer of 24 bytes per orbit), QAP_EDEVICE. */
-int qap_warm_start(qap_handle h, qap_mlp_handle p, qap_warm_stats *st);
+ * qap_warm_start_outputs with scale = qap_multiplier_scale * gain.  The gain
+ * (> 0) multiplies the predicted multipliers; any value keeps the bound
+ * valid, and the trained weights come with one calibrated on the training
+ * instances.  st nullable.
+ * Errors: QAP_EINVAL (gain), QAP_ENOMEM (buffer of 24 bytes per orbit),
+ * QAP_EDEVICE. */
+int qap_warm_start(qap_handle h, qap_mlp_handle p, double gain, qap_warm_stats *st);
 
 #ifdef __cplusplus
 }

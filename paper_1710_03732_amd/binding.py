@@ -71,7 +71,7 @@ class QapAdamParams(C.Structure):
 
 
 class QapWarmStats(C.Structure):
-    _fields_ = [("orbits", C.c_longlong), ("scale", C.c_double), ("ms_mlp", C.c_double),
+    _fields_ = [("orbits", C.c_longlong), ("scale", C.c_double), ("gain", C.c_double), ("ms_mlp", C.c_double),
                 ("ms_write", C.c_double), ("seconds", C.c_double), ("mlp_flops", C.c_double)]
 
 
@@ -144,7 +144,7 @@ def lib():
         L.qap_mlp_gradients.argtypes = [vp, vp, vp, C.c_int, C.POINTER(C.c_float), _dp]
         L.qap_mlp_train_step.argtypes = [vp, vp, vp, C.c_int, C.POINTER(QapAdamParams), _dp]
         L.qap_orbit_outputs.argtypes = [vp, vp, vp]
-        L.qap_warm_start.argtypes = [vp, vp, C.POINTER(QapWarmStats)]
+        L.qap_warm_start.argtypes = [vp, vp, C.c_double, C.POINTER(QapWarmStats)]
         _lib = L
     return _lib
 
@@ -362,10 +362,12 @@ class DualAscent:
         y = y.contiguous()
         _check(lib().qap_warm_start_outputs(self.h, C.c_void_p(y.data_ptr()), float(scale)), self.h)
 
-    def warm_start(self, mlp: "Mlp"):
+    def warm_start(self, mlp: "Mlp", gain: float | None = None):
+        """Learned S-form start; gain defaults to the perceptron's own."""
         st = QapWarmStats()
-        _check(lib().qap_warm_start(self.h, mlp.h, C.byref(st)), self.h)
-        return {"orbits": st.orbits, "scale": st.scale, "ms_mlp": st.ms_mlp,
+        g = mlp.gain if gain is None else float(gain)
+        _check(lib().qap_warm_start(self.h, mlp.h, g, C.byref(st)), self.h)
+        return {"orbits": st.orbits, "scale": st.scale, "gain": st.gain, "ms_mlp": st.ms_mlp,
                 "ms_write": st.ms_write, "seconds": st.seconds, "mlp_flops": st.mlp_flops}
 
 
@@ -400,9 +402,12 @@ class Mlp:
     """The warm start's perceptron on the GPU (float32 masters, bf16 MFMA
     kernels).  Device tensors are torch CUDA tensors."""
 
-    def __init__(self, params, max_batch: int = 8192, stream: int | None = None):
+    def __init__(self, params, max_batch: int = 8192, stream: int | None = None, gain: float | None = None):
         import torch
 
+        if gain is None:
+            gain = float(params.get("gain", 1.0)) if isinstance(params, dict) else 1.0
+        self.gain = float(gain)  # multiplier gain used by DualAscent.warm_start
         flat = params if isinstance(params, np.ndarray) and params.ndim == 1 else pack_mlp_params(params)
         flat = np.ascontiguousarray(flat, dtype=np.float32)
         if flat.size != MLP_PARAMS:

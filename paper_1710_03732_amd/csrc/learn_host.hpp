@@ -599,9 +599,10 @@ int qap_orbit_outputs(qap_handle h, qap_mlp_handle p, float *y)
     return QAP_OK;
 }
 
-int qap_warm_start(qap_handle h, qap_mlp_handle p, qap_warm_stats *st)
+int qap_warm_start(qap_handle h, qap_mlp_handle p, double gain, qap_warm_stats *st)
 {
     if (!h || !p) return QAP_EINVAL;
+    if (!(gain > 0.0) || !std::isfinite(gain)) return fail(h, QAP_EINVAL, "gain must be positive and finite");
     auto t0 = std::chrono::steady_clock::now();
     const long long count = orbit_count_of(h->n);
     float *y = (float *)dev_alloc(h, sizeof(float) * kOut * (size_t)count);
@@ -615,7 +616,7 @@ int qap_warm_start(qap_handle h, qap_mlp_handle p, qap_warm_stats *st)
     (void)hipEventRecord(ev[0], h->stream);
     int rc = qap_orbit_outputs(h, p, y);
     (void)hipEventRecord(ev[1], h->stream);
-    double scale = host_tables(h).scale;
+    const double scale = host_tables(h).scale * gain;
     if (rc == QAP_OK) rc = qap_warm_start_outputs(h, y, scale);
     (void)hipEventRecord(ev[2], h->stream);
     (void)hipStreamSynchronize(h->stream);
@@ -628,6 +629,7 @@ int qap_warm_start(qap_handle h, qap_mlp_handle p, qap_warm_stats *st)
     if (st) {
         st->orbits = count;
         st->scale = scale;
+        st->gain = gain;
         st->ms_mlp = ms[0];
         st->ms_write = ms[1];
         st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

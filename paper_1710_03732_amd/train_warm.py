@@ -11,6 +11,10 @@ and gathers their features and their members' tracked z multipliers divided
 by max|F| max|D| / (n - 2).  The perceptron (bf16 MFMA kernels, float32
 Adam) fits the zero-sum projection of its outputs to those targets.
 
+After fitting, a gain on the predicted multipliers is chosen on the last
+`--calib` training instances (fewest iterations to the bound of
+`--cold-iters` cold iterations) and saved with the weights.
+
 Held-out measurement (time-to-bound): cold = `--cold-iters` F1 iterations
 from Algorithm 1's start, wall time W and bound LB_cold; warm = the learned
 S-form start (features + inference + z writer, all timed) followed by F1
@@ -55,13 +59,53 @@ def init_params(seed: int) -> dict:
 
 
 def load_weights(path: str = WEIGHTS) -> dict:
+    """W1..b3 and the calibrated multiplier gain (1.0 if the file has none)."""
     with np.load(path) as z:
-        return {k: z[k] for k in ("W1", "b1", "W2", "b2", "W3", "b3")}
+        out = {k: z[k] for k in ("W1", "b1", "W2", "b2", "W3", "b3")}
+        out["gain"] = float(z["gain"]) if "gain" in z.files else 1.0
+    return out
 
 
 def save_weights(mlp: "B.Mlp", path: str):
     os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
-    np.savez(path, **B.unpack_mlp_params(mlp.params()))
+    np.savez(path, gain=np.float64(mlp.gain), **B.unpack_mlp_params(mlp.params()))
+
+
+GAINS = (1.0, 1.5, 2.0, 2.5, 3.0, 3.5)
+
+
+def calibrate_gain(mlp, idx_list, cold_iters: int):
+    """Multiplier gain of the warm start, chosen on training instances: the
+    one whose warm run reaches the bound of `cold_iters` cold iterations in
+    the fewest iterations (geometric mean over the instances; a run that
+    never reaches it counts 2 * cold_iters).  Regression toward the mean
+    shrinks the predicted multipliers, and the ascent profits from a
+    stronger start than their least-squares scale."""
+    scores = {g: [] for g in GAINS}
+    for idx in idx_list:
+        inst = I.learned_family(idx)
+        F, D, Bm = inst.arrays()
+        c = B.DualAscent(F, D, Bm)
+        lbc = c.run(cold_iters)["lb"]
+        c.close()
+        h = B.DualAscent(F, D, Bm)
+        y = h.orbit_outputs(mlp)
+        scale = h.multiplier_scale()
+        row = []
+        for g in GAINS:
+            h.warm_start_outputs(y, scale * g)
+            h.run(cold_iters)
+            tr = np.maximum.accumulate(h.trace())
+            hit = np.nonzero(tr >= lbc)[0]
+            k = int(hit[0]) + 1 if len(hit) else 2 * cold_iters
+            scores[g].append(k)
+            row.append(k)
+        h.close()
+        log(f"gain calibration {inst.name}: iterations to the cold bound {dict(zip(GAINS, row))}")
+    gm = {g: float(np.exp(np.mean(np.log(v)))) for g, v in scores.items()}
+    best = min(GAINS, key=lambda g: gm[g])
+    log(f"gain {best} (geometric-mean iterations {gm})")
+    return best, gm
 
 
 def collect(idx_list, iters, per_instance, seed):
@@ -190,6 +234,9 @@ def main(argv=None):
     ap.add_argument("--report", default=None)
     ap.add_argument("--eval-only", action="store_true",
                     help="load --out instead of training; re-measure the held-out instances")
+    ap.add_argument("--recalibrate", action="store_true",
+                    help="with --eval-only: choose the gain again on the training instances and save it")
+    ap.add_argument("--calib", type=int, default=16, help="training instances (the last ones) for the gain")
     args = ap.parse_args(argv)
 
     import torch
@@ -198,18 +245,25 @@ def main(argv=None):
         print("train_warm.py: no GPU visible", file=sys.stderr)
         return 1
     t_all = time.perf_counter()
+    calib = list(range(max(0, args.train - args.calib), args.train))
+    gain_scores = None
     if args.eval_only:
         mlp = B.Mlp(load_weights(args.out), max_batch=args.batch)
         info, train_r2 = None, None
-        log(f"weights <- {args.out}")
+        log(f"weights <- {args.out} (gain {mlp.gain})")
+        if args.recalibrate:
+            mlp.gain, gain_scores = calibrate_gain(mlp, calib, args.cold_iters)
+            save_weights(mlp, args.out)
+            log(f"gain {mlp.gain} -> {args.out}")
     else:
         X, T, info = collect(range(args.train), args.iters, args.per_instance, args.seed)
         log(f"training set: {X.shape[0]} orbits from {len(info)} instances")
         mlp = fit(X, T, args.epochs, args.batch, args.lr, args.seed)
         train_r2 = r2(mlp, X, T, args.batch)
         del X, T
+        mlp.gain, gain_scores = calibrate_gain(mlp, calib, args.cold_iters)
         save_weights(mlp, args.out)
-        log(f"weights -> {args.out}; train R^2 {train_r2:.4f}")
+        log(f"weights -> {args.out}; train R^2 {train_r2:.4f}; gain {mlp.gain}")
     held = list(range(64, 64 + args.heldout))
     Xh, Th, _ = collect(held, args.iters, 1 << 16, args.seed + 7)
     held_r2 = r2(mlp, Xh, Th, args.batch)
@@ -224,7 +278,8 @@ def main(argv=None):
             f"warm LB0 {res['warm_lb_t0']:.1f} (cold LB0 {res['cold_lb_t0']:.1f}); "
             + (f"warm reaches it in {w['seconds']:.3f} s / {w['iterations']} its" if w else "warm does not reach it")
             + f"; warm LB after {args.cold_iters} its {res['warm_lb_after_cold_iterations']:.1f}")
-    report = {"train": info, "train_r2": train_r2, "heldout_r2": held_r2, "time_to_bound": ttb,
+    report = {"train": info, "train_r2": train_r2, "heldout_r2": held_r2, "gain": mlp.gain,
+              "gain_calibration": gain_scores, "time_to_bound": ttb,
               "args": vars(args), "seconds": time.perf_counter() - t_all}
     if args.report:
         with open(args.report, "w") as f:

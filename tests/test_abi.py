@@ -88,7 +88,7 @@ def test_orbit_count_and_learned_entry_points_validate():
     assert lib.qap_get_multipliers(None, None, None) == -1
     assert lib.qap_set_multipliers(None, None, None) == -1
     assert lib.qap_warm_start_outputs(None, None, 1.0) == -1
-    assert lib.qap_warm_start(None, None, None) == -1
+    assert lib.qap_warm_start(None, None, 1.0, None) == -1
     out = ctypes.c_void_p()
     assert lib.qap_mlp_create(None, 16, None, ctypes.byref(out)) == -1
     params = np.zeros(B.MLP_PARAMS, dtype=np.float32)

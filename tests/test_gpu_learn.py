@@ -310,3 +310,23 @@ def test_warm_start_smallest_sizes(n):
     yo = g.orbit_outputs(mlp).cpu().numpy()
     ref, _ = L.forward(_oracle_params(_params(105)), L.features(F, D, Bm, np.arange(L.orbit_count(n))), True)
     assert _rel(yo, ref) <= 1e-3
+
+
+def test_warm_start_gain_scales_the_multipliers():
+    """qap_warm_start with a gain equals the writer fed the same outputs at
+    scale * gain (bitwise), and any gain keeps the bound valid."""
+    inst = I.dense_instance(8, 106)
+    F, D, Bm = inst.arrays()
+    opt, _ = O.bruteforce(F, D, Bm)
+    mlp = B.Mlp(_params(107), max_batch=64)
+    a = B.DualAscent(F, D, Bm)
+    st = a.warm_start(mlp, gain=2.5)
+    assert st["gain"] == 2.5 and st["scale"] == a.multiplier_scale() * 2.5
+    b = B.DualAscent(F, D, Bm)
+    b.warm_start_outputs(b.orbit_outputs(mlp), b.multiplier_scale() * 2.5)
+    for h in (a, b):
+        h.run(6)
+    assert np.array_equal(a.trace(), b.trace())
+    assert np.all(a.trace() <= opt + 1e-9 * abs(opt))
+    with pytest.raises(B.QapError):
+        a.warm_start(mlp, gain=0.0)
