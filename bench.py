@@ -62,16 +62,17 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, launches_bytes: int):
-    """HBM traffic of the dominant kernel from the committed rocprofv3 PMC
-    summary (FETCH_SIZE / WRITE_SIZE scaled by the copy-kernel factor), or None
-    when the kernels changed since the counters were taken."""
+def load_traffic(kernel: str, workload: str):
+    """HBM traffic per launch of the dominant kernel from the committed
+    rocprofv3 PMC summary (FETCH_SIZE / WRITE_SIZE scaled by the copy-kernel
+    factor), or None when it was taken on another workload or the kernels
+    changed since."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_sha") != kernel_source_sha():
+    if t.get("kernel_source_sha") != kernel_source_sha() or t.get("workload") != workload:
         return None
     k = t.get("kernels", {}).get(kernel)
     if not k:
@@ -215,7 +216,7 @@ def main(argv=None):
     dom = max(("zlap", "sweep"), key=lambda k: phase_ms[k])
     dom_s = phase_ms[dom] / 1e3
     achieved = ab[dom] / dom_s / 1e9
-    traffic = load_traffic(dom, ab[dom])
+    traffic = load_traffic(dom, inst.name)
     iter_bytes = sum(ab.values())
     steps_per_zlap = r["dijkstra_steps"] / max(1, done * laps_per_iter)
 
