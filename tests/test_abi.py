@@ -107,3 +107,13 @@ def test_mlp_parameter_packing_round_trip():
     back = B.unpack_mlp_params(flat)
     for name, _ in B.MLP_SHAPES:
         np.testing.assert_array_equal(back[name], p[name].astype(np.float32))
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No CPU fallback: without the HIP library every entry point raises."""
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", "/nonexistent/libqaprlt2.so")
+    with pytest.raises(RuntimeError, match="HIP library missing"):
+        B.lib()
+    with pytest.raises(RuntimeError):
+        B.DualAscent(np.ones((5, 5)), np.ones((5, 5)))
