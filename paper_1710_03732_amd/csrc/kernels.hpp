@@ -295,27 +295,23 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
     double *src = Z + t0 * mm;
     for (int e = lane; e < nt * mm; e += 64) lds[e] = src[e];
     double *scr = lds + (size_t)H * mm;
-    const double *tiles[H];
-    double *lus[H];
-    int *lps[H];
-    int *lws[H];
+    int toff[H], soff[H];
 #pragma unroll
     for (int q = 0; q < H; ++q) {
         const int qq = q < nt ? q : 0;
-        tiles[q] = lds + (size_t)qq * mm;
-        lus[q] = scr + (size_t)qq * 2 * m;
-        lps[q] = (int *)(lus[q] + m);
-        lws[q] = lps[q] + m;
+        toff[q] = qq * mm;
+        soff[q] = H * mm + qq * 2 * m;
     }
     __syncthreads();
     double u, v, th;
     int p, st;
     if (H == 1 && m <= 32)
-        lap_solve_scalar<1, 32>(tiles, lus, lps, lws, m, nt, u, v, p, th, st);
+        lap_solve_scalar<1, 32>(lds, toff, soff, m, nt, u, v, p, th, st);
     else
-        lap_solve_scalar<H>(tiles, lus, lps, lws, m, nt, u, v, p, th, st);
+        lap_solve_scalar<H>(lds, toff, soff, m, nt, u, v, p, th, st);
     __builtin_amdgcn_wave_barrier();
-    if (l < m && h < nt) ((double *)lps[h])[l] = v;
+    // v to the scratch after the potentials (matching and links are done)
+    if (l < m && h < nt) scr[(size_t)h * 2 * m + m + l] = v;
     __syncthreads();
     // slacks back in place, row by row (no index division): a lane owns one
     // column; with one LAP of m <= 32 per wave the two half-waves take
@@ -355,23 +351,17 @@ __global__ __launch_bounds__(64) void k_lap_batch_s(const double *__restrict__ c
     const int nt = (int)(left < H ? left : H);
     const double *src = cost + t0 * mm;
     for (int e = lane; e < nt * mm; e += 64) lds[e] = src[e];
-    double *scr = lds + (size_t)H * mm;
-    const double *tiles[H];
-    double *lus[H];
-    int *lps[H];
-    int *lws[H];
+    int toff[H], soff[H];
 #pragma unroll
     for (int q = 0; q < H; ++q) {
         const int qq = q < nt ? q : 0;
-        tiles[q] = lds + (size_t)qq * mm;
-        lus[q] = scr + (size_t)qq * 2 * m;
-        lps[q] = (int *)(lus[q] + m);
-        lws[q] = lps[q] + m;
+        toff[q] = qq * mm;
+        soff[q] = H * mm + qq * 2 * m;
     }
     __syncthreads();
     double u, v, th;
     int p, st;
-    lap_solve_scalar<H>(tiles, lus, lps, lws, m, nt, u, v, p, th, st);
+    lap_solve_scalar<H>(lds, toff, soff, m, nt, u, v, p, th, st);
     if (l < m && h < nt) {
         const long long t = t0 + h;
         uo[t * m + l] = u;

@@ -57,28 +57,33 @@ __device__ __forceinline__ double part_min(double x)
 
 __device__ __forceinline__ int sgpr(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// Solve H LAPs.  tile[h] = matrix of part h (row stride m, LDS); lu/lp/lw[h]
-// = per-part LDS scratch (m doubles, m ints, m ints).  nparts <= H parts are
-// live (the others are skipped).  Outputs for lane l of part h: u (row l),
-// v (column l), p (row matched to column l, -1 past m); theta and steps of
-// the lane's part.  On return lu[h] holds that part's row potentials.
+// Solve H LAPs.  All data lives in the block's LDS array `lds`: part h's
+// matrix (row stride m) at lds + tile_off[h], its scratch at lds +
+// scr_off[h] (m doubles: row potentials, then m ints: matching, then m ints:
+// path links).  Offsets rather than pointers keep every access a known LDS
+// access (a per-lane choice between generic pointers compiles to flat
+// loads).  nparts <= H parts are live (the others are skipped).  Outputs for
+// lane l of part h: u (row l), v (column l), p (row matched to column l, -1
+// past m); theta and steps of the lane's part.  On return the scratch holds
+// that part's row potentials.
 // RW: width of the step's min reduction, 32 when every live column sits in
 // the lower half-wave (H = 2, or H = 1 with m <= 32: the upper lanes never
 // take part, and what they receive is never used), else 64.
 template <int H, int RW = (H == 1 ? 64 : 32)>
-__device__ void lap_solve_scalar(const double *const *tile, double *const *lu, int *const *lp,
-                                 int *const *lw, int m, int nparts, double &u, double &v, int &p,
-                                 double &theta, int &steps)
+__device__ void lap_solve_scalar(double *lds, const int *tile_off, const int *scr_off, int m, int nparts,
+                                 double &u, double &v, int &p, double &theta, int &steps)
 {
     constexpr int W = 64 / H;  // lanes per part
     const int lane = (int)(threadIdx.x & 63);
     const int h = (H == 1) ? 0 : (lane >> 5);
     const int l = lane & (W - 1);
     const bool valid = l < m && h < nparts;
-    const double *M = tile[h];
-    double *mlu = lu[h];
-    int *mlp = lp[h];
-    int *mlw = lw[h];
+    const int toff = (H == 1 || h == 0) ? tile_off[0] : tile_off[H - 1];
+    const int soff = (H == 1 || h == 0) ? scr_off[0] : scr_off[H - 1];
+    const double *M = lds + toff;
+    double *mlu = lds + soff;
+    int *mlp = (int *)(mlu + m);
+    int *mlw = mlp + m;
 
     // column reduction: lane l scans column l of its part
     constexpr int kNone = 0x7fffffff;
