@@ -107,6 +107,11 @@ typedef struct qap_bnb_params {
     int enum_below;        /* enumerate nodes with at most this many free
                               facilities (default 3) */
     int rule;              /* branching rule (3 = lowest interaction first) */
+    int depth_cap;         /* warm-start children from their parent's reduced
+                              costs down to this depth; deeper nodes start
+                              cold from their restricted QAP, so no parent
+                              state is kept for them (Section 4's depth limit
+                              d; 0 = no cap, the default) */
 } qap_bnb_params;
 
 typedef struct qap_bnb_stats {

@@ -42,7 +42,7 @@ class QapDaStats(C.Structure):
 class QapBnbParams(C.Structure):
     _fields_ = [("batch", C.c_int), ("node_iters", C.c_int), ("window", C.c_int),
                 ("root_iters", C.c_int), ("min_improve", C.c_double), ("ub0", C.c_double),
-                ("enum_below", C.c_int), ("rule", C.c_int)]
+                ("enum_below", C.c_int), ("rule", C.c_int), ("depth_cap", C.c_int)]
 
 
 class QapBnbStats(C.Structure):
@@ -297,8 +297,9 @@ class DualAscent:
         _check(lib().qap_set_stream(self.h, C.c_void_p(stream_handle)), self.h)
 
     def bnb_solve(self, batch=256, node_iters=100, window=25, root_iters=0, min_improve=2e-4,
-                  ub0=float("inf"), enum_below=3, rule=3):
-        p = QapBnbParams(batch, node_iters, window, root_iters, min_improve, ub0, enum_below, rule)
+                  ub0=float("inf"), enum_below=3, rule=3, depth_cap=0):
+        p = QapBnbParams(batch, node_iters, window, root_iters, min_improve, ub0, enum_below, rule,
+                         depth_cap)
         perm = np.zeros(self.n, dtype=np.int32)
         obj = C.c_double(0.0)
         st = QapBnbStats()

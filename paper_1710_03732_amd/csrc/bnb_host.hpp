@@ -298,6 +298,42 @@ int qap_node_status(qap_handle h, int *t, double *lb, double *ub, int *stopped, 
     return QAP_OK;
 }
 
+// The QAP left when the facilities with fixed[i] >= 0 sit at those
+// locations: F and D restricted to the free facilities `fac` and free
+// locations `loc`, b'_ac = b_{fac[a],loc[c]} + sum over fixed i of
+// (f_{fac[a],i} d_{loc[c],fixed[i]} + f_{i,fac[a]} d_{fixed[i],loc[c]}), and the
+// constant offset = sum over fixed i of b_{i,fixed[i]} + sum over fixed i, j of
+// f_ij d_{fixed[i],fixed[j]}.  Its cost plus the offset is the full cost of
+// every completion.
+void restricted_qap(const qap_ctx *h, const std::vector<int> &fac, const std::vector<int> &loc,
+                    const std::vector<int> &fixed, std::vector<double> &Fc, std::vector<double> &Dc,
+                    std::vector<double> &Bc, double &offset)
+{
+    const int n = h->n, k = (int)fac.size();
+    const double *F = h->hF.data(), *D = h->hD.data(), *B = h->hB.data();
+    Fc.assign((size_t)k * k, 0.0);
+    Dc.assign((size_t)k * k, 0.0);
+    Bc.assign((size_t)k * k, 0.0);
+    for (int a = 0; a < k; ++a)
+        for (int c = 0; c < k; ++c) {
+            Fc[a * k + c] = F[fac[a] * n + fac[c]];
+            Dc[a * k + c] = D[loc[a] * n + loc[c]];
+            double b = B[fac[a] * n + loc[c]];
+            for (int i = 0; i < n; ++i)
+                if (fixed[i] >= 0)
+                    b = (b + F[fac[a] * n + i] * D[loc[c] * n + fixed[i]]) + F[i * n + fac[a]] * D[fixed[i] * n + loc[c]];
+            Bc[a * k + c] = b;
+        }
+    double off = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (fixed[i] < 0) continue;
+        off += B[i * n + fixed[i]];
+        for (int j = 0; j < n; ++j)
+            if (fixed[j] >= 0) off += F[i * n + j] * D[fixed[i] * n + fixed[j]];
+    }
+    offset = off;
+}
+
 int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, double *obj_out, qap_bnb_stats *st)
 {
     if (!h || !perm_out || !obj_out) return QAP_EINVAL;
@@ -313,9 +349,10 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
         P.ub0 = HUGE_VAL;
         P.enum_below = 3;
         P.rule = 3;
+        P.depth_cap = 0;
     }
     if (P.batch < 1 || P.node_iters < 1 || P.window < 0 || P.window > 1000 || P.enum_below < 3 ||
-        !(P.min_improve >= 0.0) || P.rule != 3)
+        !(P.min_improve >= 0.0) || P.rule != 3 || P.depth_cap < 0)
         return fail(h, QAP_EINVAL, "bad branch-and-bound parameters");
     if (P.root_iters <= 0) P.root_iters = P.node_iters;
     const int n = h->n;
@@ -391,6 +428,17 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
             if (nd.l < 0) {
                 rc = create_ctx(n, h->hF.data(), h->hD.data(), h->hB.data(), h->prm, 0.0, h->stream, true, &c);
                 if (rc != QAP_OK) h->err = g_init_error;
+            } else if (!nd.parent) {
+                // past the depth cap: the restricted QAP of the node, from scratch
+                std::vector<double> Fc, Dc, Bc;
+                double off = 0.0;
+                restricted_qap(h, nd.fac, nd.loc, nd.fixed, Fc, Dc, Bc, off);
+                rc = create_ctx((int)nd.fac.size(), Fc.data(), Dc.data(), Bc.data(), h->prm, off, h->stream, true,
+                                &c);
+                if (rc != QAP_OK)
+                    h->err = g_init_error;
+                else if ((rc = upload_scalars(c, off)) != QAP_OK)  // the bound counts the fixed part too
+                    h->err = c->err;
             } else {
                 rc = qap_fold_child(nd.parent.get(), nd.l, nd.s, &c);
                 if (rc != QAP_OK) h->err = nd.parent->err;
@@ -466,7 +514,7 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
                     ++nodes_done;
                     continue;
                 }
-                k.parent = ctxs[b];
+                if (P.depth_cap == 0 || k.depth <= P.depth_cap) k.parent = ctxs[b];
                 kids.push_back(std::move(k));
             }
             for (auto &k : kids) pushes.push_back(std::move(k));

@@ -139,3 +139,17 @@ def test_bnb_smallest_sizes(inst):
 
 def test_batch_of_no_handles():
     assert B.batch_run([], iters=5)["iterations"] == 0
+
+
+@pytest.mark.parametrize("inst", [I.dense_instance(8, 4), I.random_instance(7, 7, lo=-4, hi=9),
+                                  I.grid_instance(9, 3, 3, 0.4, 1, 9, 25)], ids=lambda x: x.name)
+def test_bnb_depth_cap_keeps_the_optimum(inst):
+    """Nodes past the depth cap start cold from their restricted QAP (fixed
+    pairs folded into b and a constant offset) instead of the parent's
+    reduced costs; the optimum must not move, with negative data too."""
+    F, D, Bm = inst.arrays()
+    opt, _ = O.bruteforce(F, D, Bm)
+    for cap in (1, 2):
+        obj, perm, st = B.DualAscent(F, D, Bm).bnb_solve(node_iters=3, depth_cap=cap)
+        assert obj == opt and O.qap_cost(F, D, Bm, perm) == opt
+        assert st["nodes"] > 1
