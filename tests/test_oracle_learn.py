@@ -245,3 +245,23 @@ def test_tracked_targets_are_zero_sum():
     t = L.targets(V, np.arange(L.orbit_count(8)), scale).astype(np.float64)
     assert np.abs(t.sum(1)).max() <= 1e-5 * max(1.0, np.abs(t).max())
     assert np.abs(t).max() > 0
+
+
+def test_s_form_start_keeps_the_reformulation_identity():
+    """After a start from zero-sum multipliers (z costs -v) the reformulation
+    identity cost(perm) = LB + sum of reduced costs holds for every
+    permutation, at t = 0 (each orbit a permutation selects is selected whole,
+    so its -v sum vanishes) and after further iterations."""
+    inst = I.random_instance(6, 50, lo=-3, hi=8)
+    F, D, B = inst.arrays()
+    n = 6
+    _, _, scale = L.scales(F, D)
+    y = np.random.default_rng(51).standard_normal((L.orbit_count(n), 6)).astype(np.float32)
+    w = O.DualAscent.from_multipliers(F, D, B, O.FULL, L.multipliers_from_outputs(n, y, scale), None)
+    perms = [np.array(p, dtype=np.int32) for p in itertools.islice(itertools.permutations(range(n)), 0, 720, 37)]
+    for steps in (0, 1, 4):
+        if steps:
+            w.run(steps)
+        for p in perms:
+            cost = O.qap_cost(F, D, B, p)
+            assert abs(w.identity(p) - cost) <= 1e-9 * max(1.0, abs(cost)) * 100
