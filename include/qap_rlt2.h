@@ -291,6 +291,13 @@ const char *qap_last_error(qap_handle h);
  * Errors: QAP_ENOMEM, QAP_EDEVICE. */
 int qap_track(qap_handle h, int on);
 
+/* Device allocator for this handle's later allocations: tracking arrays
+ * and the temporary buffers of the learned calls (the arena keeps the
+ * allocator of qap_params it was created with).  alloc NULL selects
+ * hipMalloc/hipFree; a non-NULL alloc needs free_fn.
+ * Errors: QAP_EINVAL, QAP_ESTATE (tracking arrays live). */
+int qap_set_allocator(qap_handle h, qap_alloc_fn alloc, qap_free_fn free_fn, void *ctx);
+
 /* Host copies of the tracked multipliers since tracking (re)started:
  * v (T*m*m doubles, z layout), u (T doubles, y layout); each nullable.
  * Errors: QAP_ESTATE (tracking off). */

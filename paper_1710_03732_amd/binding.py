@@ -92,7 +92,7 @@ EXPORTED = ("qap_version", "qap_default_params", "qap_workspace_bytes", "qap_rlt
             "qap_orbit_count", "qap_multiplier_scale", "qap_orbit_features", "qap_orbit_targets",
             "qap_warm_start_outputs", "qap_mlp_create", "qap_mlp_destroy", "qap_mlp_set_stream",
             "qap_mlp_get_params", "qap_mlp_forward", "qap_mlp_gradients", "qap_mlp_train_step",
-            "qap_orbit_outputs", "qap_warm_start")
+            "qap_orbit_outputs", "qap_warm_start", "qap_set_allocator")
 
 
 def lib():
@@ -145,6 +145,7 @@ def lib():
         L.qap_mlp_train_step.argtypes = [vp, vp, vp, C.c_int, C.POINTER(QapAdamParams), _dp]
         L.qap_orbit_outputs.argtypes = [vp, vp, vp]
         L.qap_warm_start.argtypes = [vp, vp, C.c_double, C.POINTER(QapWarmStats)]
+        L.qap_set_allocator.argtypes = [vp, _alloc_fn, _free_fn, vp]
         _lib = L
     return _lib
 
@@ -326,6 +327,21 @@ class DualAscent:
         uu = None if u is None else _f64(u).reshape(-1)
         _check(lib().qap_set_multipliers(self.h, None if vv is None else _dptr(vv),
                                          None if uu is None else _dptr(uu)), self.h)
+
+    def set_allocator(self, alloc=None, free=None):
+        """Route later allocations (tracking arrays, learned-call buffers)
+        through Python callables alloc(nbytes) -> int and free(ptr), e.g.
+        torch's caching allocator; None restores hipMalloc."""
+        # the library may still call the current callbacks (it refuses the
+        # change while tracking arrays are live): drop them only on success
+        if alloc is None:
+            _check(lib().qap_set_allocator(self.h, _alloc_fn(), _free_fn(), None), self.h)
+            self._alloc_cbs = None
+            return
+        a = _alloc_fn(lambda nbytes, ctx: alloc(nbytes))
+        f = _free_fn(lambda ptr, ctx: free(ptr))
+        _check(lib().qap_set_allocator(self.h, a, f, None), self.h)
+        self._alloc_cbs = (a, f)  # keep the callbacks alive while the library holds them
 
     def multiplier_scale(self) -> float:
         s = C.c_double(0.0)

@@ -58,6 +58,10 @@ struct qap_ctx {
     hipGraphExec_t graph = nullptr;  // one full iteration (t >= 1)
     // multiplier tracking (Vz entries like Z, T entries like Yc), or null
     double *Vt = nullptr, *Ut = nullptr;
+    // allocator the arena came from (prm.alloc may change later)
+    qap_alloc_fn arena_alloc = nullptr;
+    qap_free_fn arena_free = nullptr;
+    void *arena_ctx = nullptr;
 };
 
 namespace {
@@ -433,6 +437,9 @@ int create_ctx(int n, const double *F, const double *D, const double *B, const q
         return cleanup(QAP_ENOMEM);
     }
     h->arena = mem;
+    h->arena_alloc = prm.alloc;
+    h->arena_free = prm.free_fn;
+    h->arena_ctx = prm.alloc_ctx;
     char *c = (char *)mem;
     auto take = [&](size_t bytes) {
         char *r = c;
@@ -528,9 +535,9 @@ int qap_destroy(qap_handle h)
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->arena) {
-        if (h->prm.alloc && h->prm.free_fn)
-            h->prm.free_fn(h->arena, h->prm.alloc_ctx);
-        else if (!h->prm.alloc)
+        if (h->arena_alloc && h->arena_free)
+            h->arena_free(h->arena, h->arena_ctx);
+        else if (!h->arena_alloc)
             (void)hipFree(h->arena);
     }
     if (h->trace) (void)hipFree(h->trace);

@@ -304,6 +304,17 @@ int qap_track(qap_handle h, int on)
     return QAP_OK;
 }
 
+int qap_set_allocator(qap_handle h, qap_alloc_fn alloc, qap_free_fn free_fn, void *ctx)
+{
+    if (!h) return QAP_EINVAL;
+    if (alloc && !free_fn) return fail(h, QAP_EINVAL, "an allocator needs a free function");
+    if (h->Vt) return fail(h, QAP_ESTATE, "tracking arrays are live (qap_track(h, 0) first)");
+    h->prm.alloc = alloc;
+    h->prm.free_fn = free_fn;
+    h->prm.alloc_ctx = ctx;
+    return QAP_OK;
+}
+
 int qap_get_multipliers(qap_handle h, double *v, double *u)
 {
     if (!h) return QAP_EINVAL;

@@ -330,3 +330,43 @@ def test_warm_start_gain_scales_the_multipliers():
     assert np.all(a.trace() <= opt + 1e-9 * abs(opt))
     with pytest.raises(B.QapError):
         a.warm_start(mlp, gain=0.0)
+
+
+def test_later_allocations_through_a_caller_allocator():
+    """qap_set_allocator: tracking arrays and the learned calls' buffers come
+    from torch's caching allocator; results equal the hipMalloc handle's."""
+    F, D, Bm = I.dense_instance(8, 108).arrays()
+    seen = []
+
+    def alloc(nbytes):
+        p = torch.cuda.caching_allocator_alloc(nbytes)
+        seen.append(nbytes)
+        return p
+
+    def free(ptr):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = B.DualAscent(F, D, Bm)
+    a.set_allocator(alloc, free)
+    a.track()
+    a.run(4)
+    b = B.DualAscent(F, D, Bm)
+    b.track()
+    b.run(4)
+    va, ua = a.multipliers()
+    vb, ub = b.multipliers()
+    assert np.array_equal(va, vb) and np.array_equal(ua, ub)
+    mlp = B.Mlp(_params(109), max_batch=64)
+    a.track(False)
+    a.warm_start(mlp)
+    b.track(False)
+    b.warm_start(mlp)
+    a.run(3)
+    b.run(3)
+    assert np.array_equal(a.trace(), b.trace())
+    assert len(seen) >= 3  # two tracking arrays, then the warm start's buffers
+    with pytest.raises(B.QapError):
+        a.track()
+        a.set_allocator(None)  # refused while tracking arrays are live
+    a.track(False)
+    a.set_allocator(None)

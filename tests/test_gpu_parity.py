@@ -324,3 +324,24 @@ def test_zero_flows_reduce_to_a_lap_on_b():
     rr, cc = linear_sum_assignment(Bm)
     assert r["lb"] == Bm[rr, cc].sum() == r["ub"]
     assert r["proven"] and r["iterations_done"] == 1
+
+
+def test_arena_from_a_caller_allocator():
+    """qap_params.alloc: the whole arena comes from torch's caching allocator;
+    the run is bitwise the default one, and destroy hands the arena back."""
+    import torch
+
+    F, D, Bm = I.grid_n8().arrays()
+    got, freed = [], []
+    afn = B._alloc_fn(lambda n, ctx: got.append(n) or torch.cuda.caching_allocator_alloc(n))
+    ffn = B._free_fn(lambda p, ctx: freed.append(p) or torch.cuda.caching_allocator_delete(p))
+    prm = B.default_params()
+    prm.alloc, prm.free_fn = afn, ffn
+    a = B.DualAscent(F, D, Bm, params=prm)
+    a.run(6)
+    b = B.DualAscent(F, D, Bm)
+    b.run(6)
+    assert np.array_equal(a.trace(), b.trace())
+    assert got and got[0] == B.workspace_bytes(8) - 8 * 1024
+    a.close()
+    assert len(freed) == 1
