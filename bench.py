@@ -17,8 +17,9 @@ time; its `achieved` is algorithmic bytes per launch / average launch time.
 `time_to_bound` compares 100 cold iterations with the learned warm start
 (trained weights from train_warm.py) reaching the same bound; its
 `mlp_roofline` gives the inference kernel's TFLOP/s against the bf16 MFMA
-peak.  `cpu_baseline` times the CPU oracle (all OpenMP threads) on one
-iteration of the same workload.
+peak.  `bnb` times branch-and-bound at n = 14 and 18.  `cpu_baseline` times
+the CPU oracle (all OpenMP threads) on a
+bounded sample (about 10 s of iterations) of the same workload.
 """
 from __future__ import annotations
 
@@ -80,7 +81,10 @@ def load_traffic(kernel: str, workload: str):
     return k.get("bytes_per_launch")
 
 
-def cpu_baseline(inst, threads: int | None):
+def cpu_baseline(inst, threads: int | None, budget_s: float = 10.0):
+    """The CPU oracle on the same workload: full F1 iterations (t >= 1: ascent
+    sweep and all Z/Y/X LAPs) after iteration 0, until `budget_s` seconds of
+    CPU work have been timed (at least two iterations)."""
     from oracle import oracle as O
 
     if threads:
@@ -89,13 +93,16 @@ def cpu_baseline(inst, threads: int | None):
     F, D, B = inst.arrays()
     cpu = O.DualAscent(F, D, B)
     cpu.run(1)  # iteration 0 (z level zero), untimed
-    t0 = time.perf_counter()
-    cpu.run(1)  # iteration 1: sweep + all Z/Y/X LAPs
-    el = time.perf_counter() - t0
-    return {"value": 1.0 / el, "unit": "iterations/s", "cores": used, "kind": "oracle",
-            "sample": f"one full F1 iteration (t=1: ascent sweep and all Z/Y/X LAPs) of the "
+    done, el = 0, 0.0
+    while done < 2 or el < budget_s:
+        t0 = time.perf_counter()
+        cpu.run(1)
+        el += time.perf_counter() - t0
+        done += 1
+    return {"value": done / el, "unit": "iterations/s", "cores": used, "kind": "oracle",
+            "sample": f"{done} full F1 iterations (t = 1..{done}: ascent sweep and all Z/Y/X LAPs) of the "
                       f"{inst.name} workload after iteration 0, {el:.2f} s on {used} threads",
-            "seconds": el, "lb_after": cpu.LB}
+            "seconds": el, "iterations": done, "lb_after": cpu.LB}
 
 
 def warm_vs_cold(inst, cold_iters: int):
@@ -119,22 +126,26 @@ def warm_vs_cold(inst, cold_iters: int):
 
 
 def bnb_leg():
-    """Branch-and-bound on the n = 14 dense instance: forced branching (4
-    iterations per node, batches of up to 256 nodes of mixed depth) and the
-    default settings (the root bound closes it)."""
+    """Branch-and-bound: the n = 14 dense instance with forced branching (4
+    iterations per node, batches of up to 256 nodes of mixed depth) and with
+    the default settings (the root bound closes it), and the n = 18 dense
+    instance (seed 0) with the default settings."""
     from paper_1710_03732_amd import binding, instances as insts
 
-    inst = insts.dense_n14()
-    F, D, B = inst.arrays()
-    out = {"instance": inst.name}
-    for label, kw in (("branching", dict(batch=256, node_iters=4, window=25)), ("default", {})):
+    out = {}
+    runs = (("dense_n14_branching", insts.dense_n14(), dict(batch=256, node_iters=4, window=25)),
+            ("dense_n14_default", insts.dense_n14(), {}),
+            ("dense_n18_default", insts.dense_instance(18, 0), {}))
+    for label, inst, kw in runs:
+        F, D, B = inst.arrays()
         h = binding.DualAscent(F, D, B)
         t0 = time.perf_counter()
         obj, perm, st = h.bnb_solve(**kw)
         el = time.perf_counter() - t0
         h.close()
         out[label] = {"optimum": obj, "seconds": el, "nodes": st["nodes"], "batches": st["batches"],
-                      "da_iterations": st["da_iters"], "nodes_per_s": st["nodes"] / el, **kw}
+                      "da_iterations": st["da_iters"], "nodes_per_s": st["nodes"] / el,
+                      "node_iterations_per_s": st["da_iters"] / el, **kw}
     return out
 
 
@@ -163,7 +174,7 @@ def main(argv=None):
     ap.add_argument("--zlap-lanes", type=int, default=0)
     ap.add_argument("--zlap-cols", type=int, default=0)
     ap.add_argument("--no-time-to-bound", action="store_true")
-    ap.add_argument("--no-bnb", action="store_true", help="skip the n = 14 branch-and-bound leg")
+    ap.add_argument("--no-bnb", action="store_true", help="skip the branch-and-bound leg (n = 14 and 18)")
     ap.add_argument("--cold-iters", type=int, default=100,
                     help="cold iterations whose bound the learned warm start must reach")
     ap.add_argument("--calibrate-copy", action="store_true",
