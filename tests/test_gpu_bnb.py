@@ -128,6 +128,21 @@ def test_bnb_dense_n14_batched():
     assert obj2 == g["optimum"]
 
 
+def test_bnb_dense_n16():
+    """n = 16 dense symmetric U{0..99}: the optimum both exact solvers of the
+    oracle agree on (golden file; the Gilmore-Lawler B&B needed about 1.5e7
+    nodes), reached with the default node budget and with batched nodes."""
+    with open(os.path.join(GOLDEN, "dense_n16_optimum.json")) as f:
+        g = json.load(f)
+    F, D, Bm = I.dense_instance(16, 0).arrays()
+    h = B.DualAscent(F, D, Bm)
+    for kw in ({}, dict(batch=64, node_iters=20)):
+        obj, perm, st = h.bnb_solve(**kw)
+        assert obj == g["optimum"], kw
+        assert O.qap_cost(F, D, Bm, perm) == g["optimum"]
+        assert sorted(perm.tolist()) == list(range(16))
+
+
 @pytest.mark.parametrize("inst", [I.random_instance(3, 20), I.random_instance(4, 21, lo=-3, hi=7)],
                          ids=lambda x: x.name)
 def test_bnb_smallest_sizes(inst):

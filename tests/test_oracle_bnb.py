@@ -90,15 +90,16 @@ def test_child_fold_identity(l, s):
     assert child.LB <= best + 1e-9 * best
 
 
-def test_golden_dense_n14_optimum_fixture():
-    """The n = 14 dense optimum used by the GPU B&B test was written by
+@pytest.mark.parametrize("n", [14, 16])
+def test_golden_dense_optimum_fixture(n):
+    """The dense optima used by the GPU B&B tests were written by
     tests/golden/make_golden.py (oracle only); both exact solvers agreed."""
-    with open(os.path.join(GOLDEN, "dense_n14_optimum.json")) as f:
+    with open(os.path.join(GOLDEN, f"dense_n{n}_optimum.json")) as f:
         g = json.load(f)
-    inst = I.dense_n14()
+    inst = I.dense_instance(n, 0)
     F, D, B = inst.arrays()
-    assert g["n"] == 14
+    assert g["n"] == n
     perm = np.array(g["perm"], dtype=np.int32)
-    assert sorted(perm.tolist()) == list(range(14))
+    assert sorted(perm.tolist()) == list(range(n))
     assert O.qap_cost(F, D, B, perm) == g["optimum"]
     assert g["optimum"] == g["glb_bnb_optimum"] == g["rlt2_bnb_optimum"]
