@@ -305,10 +305,14 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
     __syncthreads();
     double u, v, th;
     int p, st;
-    if (H == 1 && m <= 32)
-        lap_solve_scalar<1, 32>(lds, toff, soff, m, nt, u, v, p, th, st);
-    else
+    if constexpr (H == 1) {
+        if (m <= 32)
+            lap_solve_scalar1<32>(lds, toff[0], soff[0], m, u, v, p, th, st);
+        else
+            lap_solve_scalar1<64>(lds, toff[0], soff[0], m, u, v, p, th, st);
+    } else {
         lap_solve_scalar<H>(lds, toff, soff, m, nt, u, v, p, th, st);
+    }
     __builtin_amdgcn_wave_barrier();
     // v to the scratch after the potentials (matching and links are done)
     if (l < m && h < nt) scr[(size_t)h * 2 * m + m + l] = v;
@@ -361,7 +365,14 @@ __global__ __launch_bounds__(64) void k_lap_batch_s(const double *__restrict__ c
     __syncthreads();
     double u, v, th;
     int p, st;
-    lap_solve_scalar<H>(lds, toff, soff, m, nt, u, v, p, th, st);
+    if constexpr (H == 1) {
+        if (m <= 32)
+            lap_solve_scalar1<32>(lds, toff[0], soff[0], m, u, v, p, th, st);
+        else
+            lap_solve_scalar1<64>(lds, toff[0], soff[0], m, u, v, p, th, st);
+    } else {
+        lap_solve_scalar<H>(lds, toff, soff, m, nt, u, v, p, th, st);
+    }
     if (l < m && h < nt) {
         const long long t = t0 + h;
         uo[t * m + l] = u;

@@ -229,4 +229,130 @@ __device__ void lap_solve_scalar(double *lds, const int *tile_off, const int *sc
     steps = st;
 }
 
+// One LAP per wavefront (the H = 1 case above) with the per-column flags
+// held as wave masks in SGPRs rather than per-lane booleans: the tree rows,
+// the tree (used) columns and the unmatched columns.  A mask turns back into
+// a lane predicate for free (inverse ballot: the SGPR pair is the lane mask
+// of a v_cndmask or of exec), so the tie-break ballot is a single compare
+// and the flag updates are scalar bit operations.  Non-tree work columns
+// keep minv, every other lane holds +inf, so the step's minimum reads minv
+// directly.  Arithmetic, order and tie-break are those of lap_solve_scalar,
+// so the results are bitwise identical to it.
+// Arguments as lap_solve_scalar with one part: tile at lds + toff, scratch
+// at lds + soff (m doubles, then 2m ints); m <= RW.
+template <int RW>
+__device__ void lap_solve_scalar1(double *lds, int toff, int soff, int m, double &u, double &v, int &p,
+                                  double &theta, int &steps)
+{
+    const int l = (int)(threadIdx.x & 63);
+    const bool valid = l < m;
+    const double *M = lds + toff;
+    double *mlu = lds + soff;
+    int *mlp = (int *)(mlu + m);
+    int *mlw = mlp + m;
+    const unsigned long long validm = (m >= 64) ? ~0ull : ((1ull << m) - 1ull);
+
+    // column reduction: lane l scans column l
+    constexpr int kNone = 0x7fffffff;
+    u = 0.0;
+    v = 0.0;
+    p = -1;
+    int prop = 0;
+    if (valid) {
+        double best = M[l];
+        for (int i = 1; i < m; ++i) {
+            const double x = M[i * m + l];
+            if (x < best) {
+                best = x;
+                prop = i;
+            }
+        }
+        v = best;
+        mlw[l] = kNone;
+        mlu[l] = best;  // staged for the fold below
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (valid) atomicMin(&mlw[prop], l);
+    __builtin_amdgcn_wave_barrier();
+    // the LAP value starts at the left fold of the column minima
+    double th = mlu[0];
+    for (int j = 1; j < m; ++j) th = th + mlu[j];
+    __builtin_amdgcn_wave_barrier();
+    if (valid) {
+        p = (mlw[prop] == l) ? prop : -1;
+        mlp[l] = p;
+        mlu[l] = 0.0;
+    }
+    unsigned long long unm = __builtin_amdgcn_ballot_w64(valid && mlw[l] == kNone);  // rows to insert
+    unsigned long long freem = __builtin_amdgcn_ballot_w64(valid && p < 0);         // unmatched columns
+    __builtin_amdgcn_wave_barrier();
+    int st = 0;
+    if (unm) {
+        int i0 = (int)__builtin_ctzll(unm);
+        int r = i0, last = -1;
+        unsigned long long usedm = 0ull, treem = 1ull << i0;
+        double minv = kInf;
+        int way = -1;
+        for (;;) {
+            ++st;
+            const unsigned long long actm = validm & ~usedm;
+            const double ur = mlu[r];
+            const double mv = M[r * m + (valid ? l : 0)];
+            const double s = (mv - ur) - v;
+            const unsigned long long bm = __builtin_amdgcn_ballot_w64(s < minv) & actm;
+            minv = __builtin_amdgcn_inverse_ballot_w64(bm) ? s : minv;
+            way = __builtin_amdgcn_inverse_ballot_w64(bm) ? last : way;
+            const double mn = part_min<RW>(minv);
+            const unsigned long long eqm = __builtin_amdgcn_ballot_w64(minv == mn);
+            const unsigned long long bf = eqm & freem;
+            const int js = (int)__builtin_ctzll(bf != 0ull ? bf : (eqm | (1ull << 63)));
+            // masked adds kept as branches over exec (one VALU op each)
+            // rather than if-converted to add + two selects
+            if (__builtin_amdgcn_inverse_ballot_w64(treem)) asm volatile("v_add_f64 %0, %0, %1" : "+v"(u) : "v"(mn));
+            if (__builtin_amdgcn_inverse_ballot_w64(usedm)) asm volatile("v_add_f64 %0, %0, -%1" : "+v"(v) : "v"(mn));
+            minv = __builtin_amdgcn_inverse_ballot_w64(1ull << js) ? kInf : minv - mn;
+            th = th + mn;
+            const int pj = __builtin_amdgcn_readlane(p, js);
+            if (pj >= 0) {
+                usedm |= 1ull << js;
+                treem |= 1ull << pj;
+                r = pj;
+                last = js;
+                continue;
+            }
+            // flip the alternating path back to the root row; the path
+            // links are the lanes' own `way` registers
+            if (__builtin_amdgcn_inverse_ballot_w64(treem)) mlu[l] = u;
+            __builtin_amdgcn_wave_barrier();
+            unsigned long long onpath = 0ull;
+            int j = js;
+            while (j >= 0) {
+                onpath |= 1ull << j;
+                j = __builtin_amdgcn_readlane(way, j);
+            }
+            const bool flip = __builtin_amdgcn_inverse_ballot_w64(onpath);
+            int np = -1;
+            if (flip) np = (way < 0) ? i0 : mlp[way];
+            __builtin_amdgcn_wave_barrier();
+            if (flip) {
+                p = np;
+                mlp[l] = np;
+            }
+            __builtin_amdgcn_wave_barrier();
+            freem &= ~(1ull << js);
+            unm &= unm - 1ull;
+            if (!unm) break;
+            i0 = (int)__builtin_ctzll(unm);
+            r = i0;
+            last = -1;
+            usedm = 0ull;
+            treem = 1ull << i0;
+            minv = kInf;
+            way = -1;
+        }
+    }
+    theta = th;
+    steps = st;
+}
+
 }  // namespace qap
