@@ -311,7 +311,7 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
         else
             lap_solve_scalar1<64>(lds, toff[0], soff[0], m, u, v, p, th, st);
     } else {
-        lap_solve_scalar<H>(lds, toff, soff, m, nt, u, v, p, th, st);
+        lap_solve_scalar2(lds, toff, soff, m, nt, u, v, p, th, st);
     }
     __builtin_amdgcn_wave_barrier();
     // v to the scratch after the potentials (matching and links are done)
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(64) void k_lap_batch_s(const double *__restrict__ c
         else
             lap_solve_scalar1<64>(lds, toff[0], soff[0], m, u, v, p, th, st);
     } else {
-        lap_solve_scalar<H>(lds, toff, soff, m, nt, u, v, p, th, st);
+        lap_solve_scalar2(lds, toff, soff, m, nt, u, v, p, th, st);
     }
     if (l < m && h < nt) {
         const long long t = t0 + h;

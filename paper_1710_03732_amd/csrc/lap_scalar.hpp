@@ -1,16 +1,25 @@
 // lap_scalar.hpp -- the Hungarian LAP solver of lap_wave.hpp with its control
-// held in scalar registers: a wavefront solves H independent LAPs at once
-// (H = 1: one LAP on 64 lanes, m <= 64; H = 2: two LAPs on 32 lanes each,
-// m <= 32).  Lane l of part h owns row l and column l of LAP h.
+// held in scalar registers: a wavefront solves one LAP on 64 lanes (m <= 64,
+// lap_solve_scalar1) or two on 32 lanes each (m <= 32, lap_solve_scalar2).
+// Lane l of a part owns row l and column l of its LAP.
 //
 // Same algorithm, same arithmetic, same tie-break as lap_wave.hpp (column
 // reduction start, then shortest augmenting paths, Section 2.3 "LAP
 // Solution"; see there for the fixed choice of optimal duals), so results are
-// bitwise identical.  What differs is
-// the mapping: the current row, the chosen column, the matched row, the path
-// and the tree/used sets of each part are wave-uniform values (SGPRs, lane
-// masks), so the scalar unit runs the control flow and a Dijkstra step costs
-// about forty vector instructions for all H LAPs of the wave.
+// bitwise identical.  What differs is the mapping: the current row, the
+// chosen column, the matched row and the path are wave-uniform values in
+// SGPRs, and the per-column flags (tree rows, tree columns, unmatched
+// columns) are wave masks there too, so the scalar unit runs the control
+// flow and a Dijkstra step costs about thirty-three vector instructions.
+//
+// Data: the block's LDS array `lds` holds a part's matrix (row stride m) at
+// lds + tile offset and its scratch at lds + scratch offset (m doubles: row
+// potentials, then m ints: matching, then m ints: proposals).  Offsets rather
+// than pointers keep every access a known LDS access (a per-lane choice
+// between generic pointers compiles to flat loads).  Outputs for lane l of a
+// part: u (row l), v (column l), p (row matched to column l, -1 past m);
+// theta and steps of the lane's part.  On return the scratch holds the
+// part's row potentials.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -55,191 +64,16 @@ __device__ __forceinline__ double part_min(double x)
     return x;
 }
 
-__device__ __forceinline__ int sgpr(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
-// Solve H LAPs.  All data lives in the block's LDS array `lds`: part h's
-// matrix (row stride m) at lds + tile_off[h], its scratch at lds +
-// scr_off[h] (m doubles: row potentials, then m ints: matching, then m ints:
-// path links).  Offsets rather than pointers keep every access a known LDS
-// access (a per-lane choice between generic pointers compiles to flat
-// loads).  nparts <= H parts are live (the others are skipped).  Outputs for
-// lane l of part h: u (row l), v (column l), p (row matched to column l, -1
-// past m); theta and steps of the lane's part.  On return the scratch holds
-// that part's row potentials.
-// RW: width of the step's min reduction, 32 when every live column sits in
-// the lower half-wave (H = 2, or H = 1 with m <= 32: the upper lanes never
-// take part, and what they receive is never used), else 64.
-template <int H, int RW = (H == 1 ? 64 : 32)>
-__device__ void lap_solve_scalar(double *lds, const int *tile_off, const int *scr_off, int m, int nparts,
-                                 double &u, double &v, int &p, double &theta, int &steps)
-{
-    constexpr int W = 64 / H;  // lanes per part
-    const int lane = (int)(threadIdx.x & 63);
-    const int h = (H == 1) ? 0 : (lane >> 5);
-    const int l = lane & (W - 1);
-    const bool valid = l < m && h < nparts;
-    const int toff = (H == 1 || h == 0) ? tile_off[0] : tile_off[H - 1];
-    const int soff = (H == 1 || h == 0) ? scr_off[0] : scr_off[H - 1];
-    const double *M = lds + toff;
-    double *mlu = lds + soff;
-    int *mlp = (int *)(mlu + m);
-    int *mlw = mlp + m;
-
-    // column reduction: lane l scans column l of its part
-    constexpr int kNone = 0x7fffffff;
-    u = 0.0;
-    v = 0.0;
-    p = -1;
-    int prop = 0;
-    if (valid) {
-        double best = M[l];
-        for (int i = 1; i < m; ++i) {
-            const double x = M[i * m + l];
-            if (x < best) {
-                best = x;
-                prop = i;
-            }
-        }
-        v = best;
-        mlw[l] = kNone;
-    }
-    __builtin_amdgcn_wave_barrier();
-    if (valid) atomicMin(&mlw[prop], l);
-    __builtin_amdgcn_wave_barrier();
-    if (valid) {
-        p = (mlw[prop] == l) ? prop : -1;
-        mlp[l] = p;
-        mlu[l] = 0.0;
-    }
-    const unsigned long long unm_all = __builtin_amdgcn_ballot_w64(valid && mlw[l] == kNone);
-    __builtin_amdgcn_wave_barrier();
-    double minv = kInf;
-    int way = -1;
-    bool used = false;
-    bool intree = false;
-    double th = 0.0;
-    int st = 0;
-    // per-part scalar state: rows still to insert, current row, last column;
-    // the LAP value starts at the left fold of the part's column minima
-    unsigned long long unm[H];
-    int i0[H], r[H], last[H];
-#pragma unroll
-    for (int q = 0; q < H; ++q) {
-        unm[q] = (H == 1) ? unm_all : ((unm_all >> (32 * q)) & 0xffffffffull);
-        i0[q] = (q < nparts && unm[q]) ? (int)__builtin_ctzll(unm[q]) : m;
-        r[q] = i0[q];
-        last[q] = -1;
-        if (q < nparts) {
-            double f = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), q * W),
-                                        __builtin_amdgcn_readlane(__double2loint(v), q * W));
-            for (int j = 1; j < m; ++j)
-                f = f + __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), q * W + j),
-                                         __builtin_amdgcn_readlane(__double2loint(v), q * W + j));
-            if (H == 1 || h == q) th = f;
-        }
-    }
-    intree = valid && i0[(H == 1) ? 0 : h] == l;
-    for (;;) {
-        bool any = false;
-#pragma unroll
-        for (int q = 0; q < H; ++q) any = any || (i0[q] < m);
-        if (!any) break;
-        const int my_i0 = (H == 1 || h == 0) ? i0[0] : i0[H - 1];
-        const bool part_live = my_i0 < m;
-        const int my_r = (H == 1 || h == 0) ? r[0] : r[H - 1];
-        const int my_last = (H == 1 || h == 0) ? last[0] : last[H - 1];
-        if (part_live) ++st;
-        const bool act = valid && part_live && !used;
-        const double ur = mlu[my_r];
-        const double mv = M[my_r * m + (l < m ? l : 0)];
-        const double s = (mv - ur) - v;
-        if (act && s < minv) {
-            minv = s;
-            way = my_last;
-        }
-        const double mn = part_min<RW>(act ? minv : kInf);
-        const bool cand = act && minv == mn;
-        const unsigned long long bc = __builtin_amdgcn_ballot_w64(cand);
-        const unsigned long long bf = __builtin_amdgcn_ballot_w64(cand && p < 0);
-        int js[H];
-#pragma unroll
-        for (int q = 0; q < H; ++q) {
-            const unsigned long long cq = (H == 1) ? bc : ((bc >> (32 * q)) & 0xffffffffull);
-            const unsigned long long fq = (H == 1) ? bf : ((bf >> (32 * q)) & 0xffffffffull);
-            js[q] = (int)__builtin_ctzll(fq != 0ull ? fq : (cq | (1ull << 63)));
-        }
-        if (part_live) {
-            if (intree) u = u + mn;
-            if (valid) {
-                if (used)
-                    v = v - mn;
-                else
-                    minv = minv - mn;
-            }
-            th = th + mn;
-        }
-        const int my_js = (H == 1 || h == 0) ? js[0] : js[H - 1];
-        const int pjv = mlp[my_js < m ? my_js : 0];
-        int pj[H];
-#pragma unroll
-        for (int q = 0; q < H; ++q) pj[q] = __builtin_amdgcn_readlane(pjv, q * W);
-#pragma unroll
-        for (int q = 0; q < H; ++q) {
-            if (i0[q] >= m) continue;
-            const bool mine = (H == 1) || (h == q);
-            if (pj[q] >= 0) {
-                if (mine && l == js[q]) used = true;
-                if (mine && valid && l == pj[q]) intree = true;
-                r[q] = pj[q];
-                last[q] = js[q];
-                continue;
-            }
-            // flip the alternating path of part q back to its root row; the
-            // path links are the lanes' own `way` registers
-            if (mine && valid && intree) mlu[l] = u;
-            __builtin_amdgcn_wave_barrier();
-            unsigned long long onpath = 0ull;
-            int j = js[q];
-            while (j >= 0) {
-                onpath |= 1ull << j;
-                j = __builtin_amdgcn_readlane(way, q * W + j);
-            }
-            int np = -1;
-            const bool flip = mine && valid && ((onpath >> l) & 1ull);
-            if (flip) np = (way < 0) ? i0[q] : mlp[way];
-            __builtin_amdgcn_wave_barrier();
-            if (flip) {
-                p = np;
-                mlp[l] = np;
-            }
-            __builtin_amdgcn_wave_barrier();
-            unm[q] &= unm[q] - 1ull;
-            i0[q] = unm[q] ? (int)__builtin_ctzll(unm[q]) : m;
-            r[q] = i0[q];
-            last[q] = -1;
-            if (mine) {
-                minv = kInf;
-                way = -1;
-                used = false;
-                intree = valid && l == i0[q];
-            }
-        }
-    }
-    theta = th;
-    steps = st;
-}
-
-// One LAP per wavefront (the H = 1 case above) with the per-column flags
-// held as wave masks in SGPRs rather than per-lane booleans: the tree rows,
-// the tree (used) columns and the unmatched columns.  A mask turns back into
+// One LAP per wavefront with the per-column flags held as wave masks in
+// SGPRs rather than per-lane booleans: the tree rows, the tree (used)
+// columns and the unmatched columns.  A mask turns back into
 // a lane predicate for free (inverse ballot: the SGPR pair is the lane mask
 // of a v_cndmask or of exec), so the tie-break ballot is a single compare
-// and the flag updates are scalar bit operations.  Non-tree work columns
+// and the flag updates are scalar bit operations.  Non-tree valid columns
 // keep minv, every other lane holds +inf, so the step's minimum reads minv
-// directly.  Arithmetic, order and tie-break are those of lap_solve_scalar,
-// so the results are bitwise identical to it.
-// Arguments as lap_solve_scalar with one part: tile at lds + toff, scratch
-// at lds + soff (m doubles, then 2m ints); m <= RW.
+// directly.
+// Tile at lds + toff, scratch at lds + soff; m <= RW (RW = 32: every live
+// column sits in the lower half-wave and the minimum stops after 32 lanes).
 template <int RW>
 __device__ void lap_solve_scalar1(double *lds, int toff, int soff, int m, double &u, double &v, int &p,
                                   double &theta, int &steps)
@@ -353,6 +187,170 @@ __device__ void lap_solve_scalar1(double *lds, int toff, int soff, int m, double
     }
     theta = th;
     steps = st;
+}
+
+// Two LAPs per wavefront (m <= 32), part 0 on lanes 0-31 and part 1 on lanes
+// 32-63, with the flags as wave masks (part 1 in the upper 32 bits) as in
+// lap_solve_scalar1.  Each pass of the loop takes one Dijkstra step of every
+// live part: the vector work (row scan, relaxation, the 32-lane minimum,
+// masked updates) is shared, the choice of column, the matched row and the
+// path flip are per part in scalar registers.  Part h's tile and scratch
+// are at tile_off[h], scr_off[h]; nparts <= 2 parts are live.
+__device__ void lap_solve_scalar2(double *lds, const int *tile_off, const int *scr_off, int m, int nparts,
+                                  double &u, double &v, int &p, double &theta, int &steps)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int h = lane >> 5;
+    const int l = lane & 31;
+    const bool valid = l < m && h < nparts;
+    // (arithmetic, not a per-lane choice of array element: that would put
+    // the two-element arrays in scratch memory)
+    const int t0 = tile_off[0], t1 = tile_off[1], s0 = scr_off[0], s1 = scr_off[1];
+    const double *M = lds + (t0 + h * (t1 - t0));
+    double *mlu = lds + (s0 + h * (s1 - s0));
+    int *mlp = (int *)(mlu + m);
+    int *mlw = mlp + m;
+    const unsigned long long lowm = (m >= 32) ? 0xffffffffull : ((1ull << m) - 1ull);
+    const unsigned long long validm = lowm | (nparts > 1 ? (lowm << 32) : 0ull);
+
+    // column reduction, as lap_solve_scalar1, in both parts at once
+    constexpr int kNone = 0x7fffffff;
+    u = 0.0;
+    v = 0.0;
+    p = -1;
+    int prop = 0;
+    if (valid) {
+        double best = M[l];
+        for (int i = 1; i < m; ++i) {
+            const double x = M[i * m + l];
+            if (x < best) {
+                best = x;
+                prop = i;
+            }
+        }
+        v = best;
+        mlw[l] = kNone;
+        mlu[l] = best;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (valid) atomicMin(&mlw[prop], l);
+    __builtin_amdgcn_wave_barrier();
+    double th = mlu[0];
+    for (int j = 1; j < m; ++j) th = th + mlu[j];
+    __builtin_amdgcn_wave_barrier();
+    if (valid) {
+        p = (mlw[prop] == l) ? prop : -1;
+        mlp[l] = p;
+        mlu[l] = 0.0;
+    }
+    const unsigned long long unm_all = __builtin_amdgcn_ballot_w64(valid && mlw[l] == kNone);
+    unsigned long long freem = __builtin_amdgcn_ballot_w64(valid && p < 0);
+    __builtin_amdgcn_wave_barrier();
+    // per-part scalar state: rows still to insert, root row, current row,
+    // last column, steps
+    unsigned long long unm0 = unm_all & 0xffffffffull, unm1 = unm_all >> 32;
+    bool live0 = unm0 != 0ull, live1 = unm1 != 0ull;
+    int i00 = live0 ? (int)__builtin_ctzll(unm0) : 0, i01 = live1 ? (int)__builtin_ctzll(unm1) : 0;
+    int r0 = i00, r1 = i01, last0 = -1, last1 = -1, st0 = 0, st1 = 0;
+    unsigned long long usedm = 0ull;
+    unsigned long long treem = (live0 ? 1ull << i00 : 0ull) | (live1 ? 1ull << (32 + i01) : 0ull);
+    constexpr unsigned long long kUpper = 0xffffffffull << 32;  // part 1's lanes
+    double minv = kInf;
+    int way = -1;
+    while (live0 || live1) {
+        st0 += live0 ? 1 : 0;
+        st1 += live1 ? 1 : 0;
+        const unsigned long long livem = (live0 ? 0xffffffffull : 0ull) | (live1 ? kUpper : 0ull);
+        const unsigned long long actm = validm & ~usedm & livem;
+        // the lane's part picks its row: potential index and row offset are
+        // formed per part in scalar registers, then selected per lane
+        const int ui = __builtin_amdgcn_inverse_ballot_w64(kUpper) ? (s1 + r1) : (s0 + r0);
+        const int mi = __builtin_amdgcn_inverse_ballot_w64(kUpper) ? (t1 + r1 * m) : (t0 + r0 * m);
+        const double ur = lds[ui];
+        const double mv = lds[mi + (l < m ? l : 0)];
+        const double s = (mv - ur) - v;
+        const unsigned long long bm = __builtin_amdgcn_ballot_w64(s < minv) & actm;
+        minv = __builtin_amdgcn_inverse_ballot_w64(bm) ? s : minv;
+        way = __builtin_amdgcn_inverse_ballot_w64(bm) ? (__builtin_amdgcn_inverse_ballot_w64(kUpper) ? last1 : last0)
+                                                      : way;
+        const double mn = part_min<32>(minv);
+        const unsigned long long eqm = __builtin_amdgcn_ballot_w64(minv == mn) & actm;
+        const unsigned long long bf = eqm & freem;
+        const unsigned f0 = (unsigned)bf, c0 = (unsigned)eqm;
+        const unsigned f1 = (unsigned)(bf >> 32), c1 = (unsigned)(eqm >> 32);
+        const int js0 = __builtin_ctz(f0 != 0u ? f0 : (c0 | 0x80000000u));
+        const int js1 = __builtin_ctz(f1 != 0u ? f1 : (c1 | 0x80000000u));
+        const unsigned long long jsm = (live0 ? 1ull << js0 : 0ull) | (live1 ? 1ull << (32 + js1) : 0ull);
+        if (__builtin_amdgcn_inverse_ballot_w64(treem)) asm volatile("v_add_f64 %0, %0, %1" : "+v"(u) : "v"(mn));
+        if (__builtin_amdgcn_inverse_ballot_w64(usedm)) asm volatile("v_add_f64 %0, %0, -%1" : "+v"(v) : "v"(mn));
+        if (__builtin_amdgcn_inverse_ballot_w64(livem)) asm volatile("v_add_f64 %0, %0, %1" : "+v"(th) : "v"(mn));
+        minv = __builtin_amdgcn_inverse_ballot_w64(jsm) ? kInf : minv - mn;
+        const int pj0 = __builtin_amdgcn_readlane(p, js0);
+        const int pj1 = __builtin_amdgcn_readlane(p, 32 + js1);
+        const bool aug0 = live0 && pj0 < 0, aug1 = live1 && pj1 < 0;
+        // a matched column extends its part's tree by its row
+        if (live0 && !aug0) {
+            usedm |= 1ull << js0;
+            treem |= 1ull << pj0;
+            r0 = pj0;
+            last0 = js0;
+        }
+        if (live1 && !aug1) {
+            usedm |= 1ull << (32 + js1);
+            treem |= 1ull << (32 + pj1);
+            r1 = pj1;
+            last1 = js1;
+        }
+        if (!(aug0 || aug1)) continue;
+        // an unmatched column ends its part's search: flip the alternating
+        // paths of the parts that reached one (disjoint lanes, one pass)
+        const unsigned long long augm = (aug0 ? 0xffffffffull : 0ull) | (aug1 ? kUpper : 0ull);
+        if (__builtin_amdgcn_inverse_ballot_w64(treem & augm)) mlu[l] = u;
+        __builtin_amdgcn_wave_barrier();
+        unsigned long long onpath = 0ull;
+        if (aug0)
+            for (int j = js0; j >= 0; j = __builtin_amdgcn_readlane(way, j)) onpath |= 1ull << j;
+        if (aug1)
+            for (int j = js1; j >= 0; j = __builtin_amdgcn_readlane(way, 32 + j)) onpath |= 1ull << (32 + j);
+        const bool flip = __builtin_amdgcn_inverse_ballot_w64(onpath);
+        const int root = __builtin_amdgcn_inverse_ballot_w64(kUpper) ? i01 : i00;
+        int np = -1;
+        if (flip) np = (way < 0) ? root : mlp[way];
+        __builtin_amdgcn_wave_barrier();
+        if (flip) {
+            p = np;
+            mlp[l] = np;
+        }
+        __builtin_amdgcn_wave_barrier();
+        minv = __builtin_amdgcn_inverse_ballot_w64(augm) ? kInf : minv;
+        way = __builtin_amdgcn_inverse_ballot_w64(augm) ? -1 : way;
+        usedm &= ~augm;
+        treem &= ~augm;
+        if (aug0) {
+            freem &= ~(1ull << js0);
+            unm0 &= unm0 - 1ull;
+            live0 = unm0 != 0ull;
+            if (live0) {
+                i00 = (int)__builtin_ctzll(unm0);
+                r0 = i00;
+                last0 = -1;
+                treem |= 1ull << i00;
+            }
+        }
+        if (aug1) {
+            freem &= ~(1ull << (32 + js1));
+            unm1 &= unm1 - 1ull;
+            live1 = unm1 != 0ull;
+            if (live1) {
+                i01 = (int)__builtin_ctzll(unm1);
+                r1 = i01;
+                last1 = -1;
+                treem |= 1ull << (32 + i01);
+            }
+        }
+    }
+    theta = th;
+    steps = h ? st1 : st0;
 }
 
 }  // namespace qap
