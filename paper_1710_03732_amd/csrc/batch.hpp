@@ -187,7 +187,8 @@ __global__ __launch_bounds__(256) void k_bzlap(const BNode *__restrict__ nodes, 
     const int m = N.m, mm = m * m;
     const long long t = jg - pf.zl[b];
     double *src = N.Z + t * mm;
-    for (int e = l; e < mm; e += L) M[e] = src[e];
+    copy_to_lds(M, src, mm, l, L);
+    const double yc0 = N.Yc[t];  // read now, added to after the solve
     double *lu = M + mm;
     int *lp = (int *)(lu + m);
     int *lw = lp + m;
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(256) void k_bzlap(const BNode *__restrict__ nodes, 
     __builtin_amdgcn_wave_barrier();
     for (int e = l; e < mm; e += L) src[e] = (M[e] - lu[e / m]) - vs[e % m];
     if (l == 0) {
-        N.Yc[t] = N.Yc[t] + th;
+        N.Yc[t] = yc0 + th;
         atomicAdd(&N.bins[jg & (kStepBins - 1)], (unsigned long long)st);
     }
 }
@@ -231,15 +232,26 @@ __global__ __launch_bounds__(256) void k_bylap(const BNode *__restrict__ nodes, 
     const int i = ip / n, p = ip % n;
     const bool equalize = N.S->t >= 1;
     const long long base = (long long)ip * mm;
-    for (int e = l; e < mm; e += L) {
-        double a = N.Yc[base + e];
-        if (equalize) {
-            const int jp = e / m, qp = e % m;
-            const int j = jp + (jp >= i), q = qp + (qp >= p);
-            const long long tb = ((long long)(j * n + q) * m + (i - (i > j))) * m + (p - (p > q));
-            a = N.ophy * a + N.phy * N.Yc[tb];
+    const double xc0 = N.Xc[ip];  // read now, added to after the solve
+    for (int e0 = 0; e0 < mm; e0 += 8 * L) {
+        double av[8], bv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = e0 + l + L * k;
+            if (e < mm) {
+                av[k] = N.Yc[base + e];
+                if (equalize) {
+                    const int jp = e / m, qp = e % m;
+                    const int j = jp + (jp >= i), q = qp + (qp >= p);
+                    bv[k] = N.Yc[((long long)(j * n + q) * m + (i - (i > j))) * m + (p - (p > q))];
+                }
+            }
         }
-        M[e] = a;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = e0 + l + L * k;
+            if (e < mm) M[e] = equalize ? N.ophy * av[k] + N.phy * bv[k] : av[k];
+        }
     }
     double *lu = M + mm;
     int *lp = (int *)(lu + m);
@@ -254,7 +266,7 @@ __global__ __launch_bounds__(256) void k_bylap(const BNode *__restrict__ nodes, 
     __builtin_amdgcn_wave_barrier();
     for (int e = l; e < mm; e += L) N.Py[base + e] = (M[e] - lu[e / m]) - vs[e % m];
     if (l == 0) {
-        N.Xc[ip] = N.Xc[ip] + th;
+        N.Xc[ip] = xc0 + th;
         atomicAdd(&N.bins[jg & (kStepBins - 1)], (unsigned long long)st);
     }
 }
@@ -276,7 +288,7 @@ __global__ __launch_bounds__(64) void k_bxlap(const BNode *__restrict__ nodes, B
     __shared__ int improved;
     const int l = threadIdx.x;
     const int n = N.n, nn = n * n;
-    for (int e = l; e < nn; e += 64) M[e] = N.Xc[e];
+    copy_to_lds(M, N.Xc, nn, l, 64);
     __syncthreads();
     double u[1], v[1], th;
     int pc[1], st = 0;

@@ -50,6 +50,30 @@ __device__ __forceinline__ long long tile_of(int n, int f1, int l1, int f2, int 
     return ((long long)(f1 * n + l1) * (n - 1) + f2p) * (n - 1) + l2p;
 }
 
+// Copies count doubles from global src to LDS dst with the nthr threads
+// numbered tid.  Each thread issues a batch of kBatch loads before any of
+// their LDS writes, so it waits for HBM once per batch.  (A plain strided
+// loop with a run-time trip count compiles to load, wait, write per element:
+// one full memory latency per element.)
+template <int kBatch = 16>
+__device__ __forceinline__ void copy_to_lds(double *__restrict__ dst, const double *__restrict__ src, int count,
+                                            int tid, int nthr)
+{
+    for (int base = 0; base < count; base += kBatch * nthr) {
+        double buf[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int e = base + tid + nthr * k;
+            if (e < count) buf[k] = src[e];
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int e = base + tid + nthr * k;
+            if (e < count) dst[e] = buf[k];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ init --
 __global__ void k_fill(double *__restrict__ a, size_t count, double val)
 {
@@ -241,14 +265,15 @@ __global__ __launch_bounds__(256) void k_zlap(double *__restrict__ Z, double *__
     const long long left = T - t0;
     const int nt = (int)(left < G ? left : G);
     double *src = Z + t0 * mm;
-    for (int e = threadIdx.x; e < nt * mm; e += blockDim.x) lds[e] = src[e];
+    copy_to_lds(lds, src, nt * mm, threadIdx.x, blockDim.x);
+    const long long t = t0 + g;
+    const double yc0 = (g < nt) ? Yc[t] : 0.0;  // read now, added to after the solve
     double *scr = lds + (size_t)G * mm + (size_t)g * 2 * m;
     double *lu = scr;
     int *lp = (int *)(scr + m);
     int *lw = lp + m;
     if (threadIdx.x == 0) bsteps = 0ull;
     __syncthreads();
-    const long long t = t0 + g;
     int st = 0;
     if (g < nt) {
         double u[C], v[C], th;
@@ -262,7 +287,7 @@ __global__ __launch_bounds__(256) void k_zlap(double *__restrict__ Z, double *__
             if (j < m) vs[j] = v[c];
         }
         if (l == 0) {
-            Yc[t] = Yc[t] + th;
+            Yc[t] = yc0 + th;
             atomicAdd(&bsteps, (unsigned long long)st);
         }
     }
@@ -293,7 +318,8 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
     const long long left = T - t0;
     const int nt = (int)(left < H ? left : H);
     double *src = Z + t0 * mm;
-    for (int e = lane; e < nt * mm; e += 64) lds[e] = src[e];
+    copy_to_lds(lds, src, nt * mm, lane, 64);
+    const double yc0 = (h < nt) ? Yc[t0 + h] : 0.0;  // read now, added to after the solve
     double *scr = lds + (size_t)H * mm;
     int toff[H], soff[H];
 #pragma unroll
@@ -332,7 +358,7 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
             for (int r = sub; r < m; r += (two ? 2 : 1)) dst[r * m + col] = (tl[r * m + col] - us[r]) - vc;
         }
     }
-    if (l == 0 && h < nt) Yc[t0 + h] = Yc[t0 + h] + th;
+    if (l == 0 && h < nt) Yc[t0 + h] = yc0 + th;
     int stt = st;
     if (H == 2) stt = __builtin_amdgcn_readlane(st, 0) + (nt > 1 ? __builtin_amdgcn_readlane(st, 32) : 0);
     if (lane == 0) atomicAdd(&bins[blockIdx.x & (kStepBins - 1)], (unsigned long long)stt);
@@ -354,7 +380,7 @@ __global__ __launch_bounds__(64) void k_lap_batch_s(const double *__restrict__ c
     const long long left = count - t0;
     const int nt = (int)(left < H ? left : H);
     const double *src = cost + t0 * mm;
-    for (int e = lane; e < nt * mm; e += 64) lds[e] = src[e];
+    copy_to_lds(lds, src, nt * mm, lane, 64);
     int toff[H], soff[H];
 #pragma unroll
     for (int q = 0; q < H; ++q) {
@@ -409,20 +435,39 @@ __global__ __launch_bounds__(256) void k_ylap(const double *__restrict__ Yc, dou
     int *lw = lp + m;
     if (threadIdx.x == 0) bsteps = 0ull;
     const bool active = ip < n * n;
+    const double xc0 = active ? Xc[ip] : 0.0;  // read now, added to after the solve
     if (active) {
         const int i = ip / n, p = ip % n;
         const long long base = (long long)ip * mm;
-        for (int e = l; e < mm; e += L) {
-            double a = Yc[base + e];
-            if (equalize) {
-                const int jp = e / m, qp = e % m;
-                const int j = jp + (jp >= i), q = qp + (qp >= p);
-                const long long tb = ((long long)(j * n + q) * m + (i - (i > j))) * m + (p - (p > q));
-                const double b = Yc[tb];
-                if (Ut) Ut[base + e] = Ut[base + e] + phy * (a - b);
-                a = ophy * a + phy * b;
+        // batches of loads (own entry, and the partner entry of the y-pair
+        // rule) issued before their use, as in copy_to_lds
+        for (int e0 = 0; e0 < mm; e0 += 8 * L) {
+            double av[8], bv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int e = e0 + l + L * k;
+                if (e < mm) {
+                    av[k] = Yc[base + e];
+                    if (equalize) {
+                        const int jp = e / m, qp = e % m;
+                        const int j = jp + (jp >= i), q = qp + (qp >= p);
+                        bv[k] = Yc[((long long)(j * n + q) * m + (i - (i > j))) * m + (p - (p > q))];
+                    }
+                }
             }
-            M[e] = a;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int e = e0 + l + L * k;
+                if (e < mm) {
+                    double a = av[k];
+                    if (equalize) {
+                        const double b = bv[k];
+                        if (Ut) Ut[base + e] = Ut[base + e] + phy * (a - b);
+                        a = ophy * a + phy * b;
+                    }
+                    M[e] = a;
+                }
+            }
         }
     }
     __syncthreads();
@@ -441,7 +486,7 @@ __global__ __launch_bounds__(256) void k_ylap(const double *__restrict__ Yc, dou
         const long long base = (long long)ip * mm;
         for (int e = l; e < mm; e += L) Py[base + e] = (M[e] - lu[e / m]) - vs[e % m];
         if (l == 0) {
-            Xc[ip] = Xc[ip] + th;
+            Xc[ip] = xc0 + th;
             atomicAdd(&bsteps, (unsigned long long)st);
         }
     }
@@ -469,7 +514,7 @@ __global__ __launch_bounds__(64) void k_xlap(const double *__restrict__ Xc, doub
     __shared__ int improved;
     const int l = threadIdx.x;
     const int nn = n * n;
-    for (int e = l; e < nn; e += 64) M[e] = Xc[e];
+    copy_to_lds(M, Xc, nn, l, 64);
     __syncthreads();
     double u[1], v[1], th;
     int pc[1], st = 0;
@@ -549,7 +594,7 @@ __global__ __launch_bounds__(256) void k_lap_batch(const double *__restrict__ co
     const long long left = count - t0;
     const int nt = (int)(left < G ? left : G);
     const double *src = cost + t0 * mm;
-    for (int e = threadIdx.x; e < nt * mm; e += blockDim.x) lds[e] = src[e];
+    copy_to_lds(lds, src, nt * mm, threadIdx.x, blockDim.x);
     double *scr = lds + (size_t)G * mm + (size_t)g * 2 * m;
     __syncthreads();
     if (g < nt) {
