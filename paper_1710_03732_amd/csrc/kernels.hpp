@@ -160,12 +160,35 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
     const int X2[6] = {1, 2, 0, 2, 0, 1};
     const int X3[6] = {2, 1, 2, 0, 1, 0};
     constexpr int PER = (SB * SB * SB) / 256;  // member elements per thread and member
+    // pi_y of the block's tiles and pi_x of its (facility, location) pairs,
+    // read once per block: member e's tile is fixed by its first two cube
+    // coordinates (a1 along axis X1[e], a2 along X2[e]), its x parent by the
+    // first.  Entries outside the instance hold 0 and are never used.
+    __shared__ double pys[6 * SB * SB];
+    __shared__ double pxs[3 * SB];
+#pragma unroll
+    for (int rep = 0; rep < (6 * SB * SB + 255) / 256; ++rep) {
+        const int a = threadIdx.x + 256 * rep;
+        if (a < 6 * SB * SB) {
+            const int e = a / (SB * SB), a1 = (a / SB) % SB, a2 = a % SB;
+            const int x1 = e >> 1, x2 = (0x102021 >> (4 * e)) & 0xf;  // X1[e], X2[e]
+            const int f1 = x1 == 0 ? fi : (x1 == 1 ? fj : fk), f2 = x2 == 0 ? fi : (x2 == 1 ? fj : fk);
+            const int l1 = (x1 == 0 ? base[0] : (x1 == 1 ? base[1] : base[2])) + a1;
+            const int l2 = (x2 == 0 ? base[0] : (x2 == 1 ? base[1] : base[2])) + a2;
+            pys[a] = (l1 < n && l2 < n && l1 != l2) ? Py[tile_of(n, f1, l1, f2, l2)] : 0.0;
+        }
+    }
+    if (threadIdx.x < 3 * SB) {
+        const int x = threadIdx.x / SB, l = (x == 0 ? base[0] : (x == 1 ? base[1] : base[2])) + threadIdx.x % SB;
+        const int f = x == 0 ? fi : (x == 1 ? fj : fk);
+        pxs[threadIdx.x] = l < n ? Px[f * n + l] : 0.0;
+    }
     long long za[6][PER];
     int li[6][PER];
     bool ok[6][PER];
-    double pz[6][PER], py[6][PER], px[6][PER];
-    // addresses of this thread's member-major elements (runs along each
-    // member's own last location axis)
+    double pz[6][PER];
+    // this thread's member-major elements (runs along each member's own last
+    // location axis); pi_z goes to the cube for the orbit phase
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
 #pragma unroll
@@ -186,17 +209,16 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
             za[e][w] = t * mm + (long long)row * m + col;
             li[e][w] = cube_idx(loc[0] - base[0], loc[1] - base[1], loc[2] - base[2]);
             pz[e][w] = Z[za[e][w]];
-            py[e][w] = Py[t];
-            px[e][w] = Px[v ? f1 * n + l1 : 0];
         }
     }
 #pragma unroll
     for (int e = 0; e < 6; ++e)
 #pragma unroll
         for (int w = 0; w < PER; ++w)
-            if (ok[e][w]) gs[e * SB_CUBE + li[e][w]] = (K.kz * pz[e][w] + K.ky2 * py[e][w]) + K.kx3 * px[e][w];
+            if (ok[e][w]) gs[e * SB_CUBE + li[e][w]] = pz[e][w];
     __syncthreads();
-    // orbit phase: phi * (left fold of the partners' g), canonical order
+    // orbit phase: g of the six members, then phi * (left fold of the
+    // partners' g), canonical order
 #pragma unroll
     for (int w = 0; w < PER; ++w) {
         const int u = threadIdx.x + 256 * w;
@@ -204,9 +226,14 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
         const int p = base[0] + pl, q = base[1] + ql, r = base[2] + rl;
         if (p < n && q < n && r < n && p != q && p != r && q != r) {
             const int c = cube_idx(pl, ql, rl);
+            const int lc[3] = {pl, ql, rl};
             double g[6];
 #pragma unroll
-            for (int e = 0; e < 6; ++e) g[e] = gs[e * SB_CUBE + c];
+            for (int e = 0; e < 6; ++e) {
+                const double y = pys[(e * SB + lc[X1[e]]) * SB + lc[X2[e]]];
+                const double x = pxs[X1[e] * SB + lc[X1[e]]];
+                g[e] = (K.kz * gs[e * SB_CUBE + c] + K.ky2 * y) + K.kx3 * x;
+            }
             gs[0 * SB_CUBE + c] = K.phi * ((((g[1] + g[2]) + g[3]) + g[4]) + g[5]);
             gs[1 * SB_CUBE + c] = K.phi * ((((g[0] + g[2]) + g[3]) + g[4]) + g[5]);
             gs[2 * SB_CUBE + c] = K.phi * ((((g[0] + g[1]) + g[3]) + g[4]) + g[5]);
@@ -225,7 +252,11 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
                 const double share = gs[e * SB_CUBE + li[e][w]];
                 Z[za[e][w]] = K.okz * pz[e][w] + share;
                 if (TRACK) {
-                    const double g = (K.kz * pz[e][w] + K.ky2 * py[e][w]) + K.kx3 * px[e][w];
+                    const int u = threadIdx.x + 256 * w;
+                    const int a2 = (u / SB) % SB, a1 = u / (SB * SB);
+                    const double y = pys[(e * SB + a1) * SB + a2];
+                    const double x = pxs[X1[e] * SB + a1];
+                    const double g = (K.kz * pz[e][w] + K.ky2 * y) + K.kx3 * x;
                     Vt[za[e][w]] = Vt[za[e][w]] + (g - share);
                 }
             }
