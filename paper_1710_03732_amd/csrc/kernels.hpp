@@ -188,13 +188,18 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
     bool ok[6][PER];
     double pz[6][PER];
     // this thread's member-major elements (runs along each member's own last
-    // location axis); pi_z goes to the cube for the orbit phase
+    // location axis); pi_z goes to the cube for the orbit phase.  Element
+    // (a1, a2, a3) of thread u = tid + 256 w has a1 = tid/64 + 4 w, the same
+    // for the whole wave, so the tile row (f1, l1, f2) and the z row are a
+    // scalar offset; only l2' * m^2 + col varies across the lanes (a 24-bit
+    // product instead of 64-bit tile arithmetic per element).
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int a2 = (int)(threadIdx.x >> 3) & (SB - 1), a3 = (int)threadIdx.x & (SB - 1);
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
 #pragma unroll
         for (int w = 0; w < PER; ++w) {
-            const int u = threadIdx.x + 256 * w;
-            const int a3 = u % SB, a2 = (u / SB) % SB, a1 = u / (SB * SB);
+            const int a1 = wid + (256 / (SB * SB)) * w;
             int loc[3];
             loc[X1[e]] = base[X1[e]] + a1;
             loc[X2[e]] = base[X2[e]] + a2;
@@ -202,11 +207,13 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
             const int l1 = loc[X1[e]], l2 = loc[X2[e]], l3 = loc[X3[e]];
             const bool v = l1 < n && l2 < n && l3 < n && l1 != l2 && l1 != l3 && l2 != l3;
             const int f1 = F1[e], f2 = F2[e], f3 = F3[e];
-            const long long t = v ? tile_of(n, f1, l1, f2, l2) : 0;
+            const int f2p = f2 - (f2 > f1);
             const int row = f3 - (f3 > f1) - (f3 > f2);
-            const int col = v ? (l3 - (l3 > l1) - (l3 > l2)) : 0;
+            const long long zrow = ((long long)(f1 * n + l1) * (n - 1) + f2p) * (n - 1) * mm + (long long)row * m;
+            const int l2p = l2 - (l2 > l1);
+            const int col = l3 - (l3 > l1) - (l3 > l2);
             ok[e][w] = v;
-            za[e][w] = t * mm + (long long)row * m + col;
+            za[e][w] = v ? zrow + (long long)(__umul24((unsigned)l2p, (unsigned)mm) + col) : 0;
             li[e][w] = cube_idx(loc[0] - base[0], loc[1] - base[1], loc[2] - base[2]);
             pz[e][w] = Z[za[e][w]];
         }
