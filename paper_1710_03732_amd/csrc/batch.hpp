@@ -44,6 +44,7 @@ struct BatchCtl {
     double min_improve;  // 0 disables the window rule
     int window;
     int nnodes;
+    int *nstopped;       // nodes that stopped during this batch (the host ends the batch when all have)
 };
 
 struct BatchPrefix {
@@ -92,16 +93,40 @@ __global__ __launch_bounds__(256) void k_bsweep(const BNode *__restrict__ nodes,
     const int X2[6] = {1, 2, 0, 2, 0, 1};
     const int X3[6] = {2, 1, 2, 0, 1, 0};
     constexpr int PER = (SB * SB * SB) / 256;
+    // pi_y of the block's tiles and pi_x of its (facility, location) pairs,
+    // read once per block into LDS (as k_sweep)
+    __shared__ double pys[6 * SB * SB];
+    __shared__ double pxs[3 * SB];
+#pragma unroll
+    for (int rep = 0; rep < (6 * SB * SB + 255) / 256; ++rep) {
+        const int a = threadIdx.x + 256 * rep;
+        if (a < 6 * SB * SB) {
+            const int e = a / (SB * SB), a1 = (a / SB) % SB, a2 = a % SB;
+            const int x1 = e >> 1, x2 = (0x102021 >> (4 * e)) & 0xf;  // X1[e], X2[e]
+            const int f1 = x1 == 0 ? fi : (x1 == 1 ? fj : fk), f2 = x2 == 0 ? fi : (x2 == 1 ? fj : fk);
+            const int l1 = (x1 == 0 ? base[0] : (x1 == 1 ? base[1] : base[2])) + a1;
+            const int l2 = (x2 == 0 ? base[0] : (x2 == 1 ? base[1] : base[2])) + a2;
+            pys[a] = (l1 < n && l2 < n && l1 != l2) ? N.Py[tile_of(n, f1, l1, f2, l2)] : 0.0;
+        }
+    }
+    if (threadIdx.x < 3 * SB) {
+        const int x = threadIdx.x / SB, l = (x == 0 ? base[0] : (x == 1 ? base[1] : base[2])) + threadIdx.x % SB;
+        const int f = x == 0 ? fi : (x == 1 ? fj : fk);
+        pxs[threadIdx.x] = l < n ? N.Px[f * n + l] : 0.0;
+    }
     long long za[6][PER];
     int li[6][PER];
     bool ok[6][PER];
     double pz[6][PER];
+    // element addresses: the wave-uniform tile row and z row as a scalar
+    // offset, l2' * m^2 + col per lane (as k_sweep)
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int a2 = (int)(threadIdx.x >> 3) & (SB - 1), a3 = (int)threadIdx.x & (SB - 1);
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
 #pragma unroll
         for (int w = 0; w < PER; ++w) {
-            const int u = threadIdx.x + 256 * w;
-            const int a3 = u % SB, a2 = (u / SB) % SB, a1 = u / (SB * SB);
+            const int a1 = wid + (256 / (SB * SB)) * w;
             int loc[3];
             loc[X1[e]] = base[X1[e]] + a1;
             loc[X2[e]] = base[X2[e]] + a2;
@@ -109,14 +134,16 @@ __global__ __launch_bounds__(256) void k_bsweep(const BNode *__restrict__ nodes,
             const int l1 = loc[X1[e]], l2 = loc[X2[e]], l3 = loc[X3[e]];
             const bool v = l1 < n && l2 < n && l3 < n && l1 != l2 && l1 != l3 && l2 != l3;
             const int f1 = F1[e], f2 = F2[e], f3 = F3[e];
-            const long long t = v ? tile_of(n, f1, l1, f2, l2) : 0;
+            const int f2p = f2 - (f2 > f1);
             const int row = f3 - (f3 > f1) - (f3 > f2);
-            const int col = v ? (l3 - (l3 > l1) - (l3 > l2)) : 0;
+            const long long zrow = ((long long)(f1 * n + l1) * (n - 1) + f2p) * (n - 1) * mm + (long long)row * m;
+            const int l2p = l2 - (l2 > l1);
+            const int col = l3 - (l3 > l1) - (l3 > l2);
             ok[e][w] = v;
-            za[e][w] = t * mm + (long long)row * m + col;
+            za[e][w] = v ? zrow + (long long)(__umul24((unsigned)l2p, (unsigned)mm) + col) : 0;
             li[e][w] = cube_idx(loc[0] - base[0], loc[1] - base[1], loc[2] - base[2]);
             pz[e][w] = v ? Z[za[e][w]] : 0.0;
-            if (v) gs[e * SB_CUBE + li[e][w]] = (N.kz * pz[e][w] + N.ky2 * N.Py[t]) + N.kx3 * N.Px[f1 * n + l1];
+            if (v) gs[e * SB_CUBE + li[e][w]] = pz[e][w];
         }
     }
     __syncthreads();
@@ -127,9 +154,14 @@ __global__ __launch_bounds__(256) void k_bsweep(const BNode *__restrict__ nodes,
         const int p = base[0] + pl, q = base[1] + ql, r = base[2] + rl;
         if (p < n && q < n && r < n && p != q && p != r && q != r) {
             const int c = cube_idx(pl, ql, rl);
+            const int lc[3] = {pl, ql, rl};
             double g[6];
 #pragma unroll
-            for (int e = 0; e < 6; ++e) g[e] = gs[e * SB_CUBE + c];
+            for (int e = 0; e < 6; ++e) {
+                const double y = pys[(e * SB + lc[X1[e]]) * SB + lc[X2[e]]];
+                const double x = pxs[X1[e] * SB + lc[X1[e]]];
+                g[e] = (N.kz * gs[e * SB_CUBE + c] + N.ky2 * y) + N.kx3 * x;
+            }
             gs[0 * SB_CUBE + c] = N.phi * ((((g[1] + g[2]) + g[3]) + g[4]) + g[5]);
             gs[1 * SB_CUBE + c] = N.phi * ((((g[0] + g[2]) + g[3]) + g[4]) + g[5]);
             gs[2 * SB_CUBE + c] = N.phi * ((((g[0] + g[1]) + g[3]) + g[4]) + g[5]);
@@ -362,6 +394,7 @@ __global__ __launch_bounds__(64) void k_bxlap(const BNode *__restrict__ nodes, B
         }
         S->stopped = stop;
         S->reason = reason;
+        if (stop) atomicAdd(ctl.nstopped, 1);
         improved = better ? 1 : 0;
     }
     __syncthreads();

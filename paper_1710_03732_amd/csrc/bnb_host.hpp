@@ -142,11 +142,12 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
     // node table and prefix tables
     std::vector<BNode> nodes(count);
     std::vector<long long> zl(count + 1, 0), yl(count + 1, 0), sw(count + 1, 0), sc(count + 1, 0);
-    int mz = 1, my = 1;
+    int mz = 1, my = 1, stopped0 = 0;
     for (int b = 0; b < count; ++b) {
         qap_ctx *h = hs[b];
         DevScalars s{};
         HIPCHK(h0, hipMemcpy(&s, h->S, sizeof(s), hipMemcpyDeviceToHost));
+        stopped0 += s.stopped ? 1 : 0;
         int rc = ensure_trace(h, s.t + bp->iters + 1);
         if (rc != QAP_OK) return rc;
         BNode &N = nodes[b];
@@ -191,10 +192,10 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
         mz = std::max(mz, h->m);
         my = std::max(my, h->n - 1);
     }
-    // device copies (one allocation)
+    // device copies (one allocation): node table, prefix tables, stop counter
     const size_t nb_bytes = round_up(sizeof(BNode) * count), pf_bytes = round_up(sizeof(long long) * (count + 1));
     void *dmem = nullptr;
-    HIPCHK(h0, hipMalloc(&dmem, nb_bytes + 4 * pf_bytes));
+    HIPCHK(h0, hipMalloc(&dmem, nb_bytes + 4 * pf_bytes + 256));
     std::unique_ptr<void, void (*)(void *)> guard(dmem, [](void *p) { (void)hipFree(p); });
     char *dp = (char *)dmem;
     BNode *dnodes = (BNode *)dp;
@@ -205,8 +206,11 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
     HIPCHK(h0, hipMemcpyAsync(dyl, yl.data(), sizeof(long long) * (count + 1), hipMemcpyHostToDevice, stream));
     HIPCHK(h0, hipMemcpyAsync(dsw, sw.data(), sizeof(long long) * (count + 1), hipMemcpyHostToDevice, stream));
     HIPCHK(h0, hipMemcpyAsync(dsc, sc.data(), sizeof(long long) * (count + 1), hipMemcpyHostToDevice, stream));
+    int *dnstop = (int *)(dp + nb_bytes + 4 * pf_bytes);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, stream, (double *)dnstop, (size_t)1, 0.0);  // zeroes the counter
+    HIPCHK(h0, hipGetLastError());
     BatchPrefix pf{dzl, dyl, dsw, dsc};
-    BatchCtl ctl{bp->ub_cut, bp->min_improve, bp->window, count};
+    BatchCtl ctl{bp->ub_cut, bp->min_improve, bp->window, count, dnstop};
     const int Lz = mz <= 8 ? 8 : mz <= 16 ? 16 : mz <= 32 ? 32 : 64;
     const int Ly = my <= 8 ? 8 : my <= 16 ? 16 : my <= 32 ? 32 : 64;
     auto launch_all = [&]() -> hipError_t {
@@ -254,8 +258,18 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
         hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (ie != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch graph: ") + hipGetErrorString(ie));
+        // replays; every kPoll of them the host reads how many nodes have
+        // stopped and ends the batch once all have (further replays would
+        // only launch jobs that find their node stopped)
+        constexpr int kPoll = 4;
         for (int it = 0; it < bp->iters; ++it) {
             hipError_t e2 = hipGraphLaunch(ge, stream);
+            if (e2 == hipSuccess && (it + 1) % kPoll == 0 && it + 1 < bp->iters) {
+                int ns = 0;
+                e2 = hipMemcpyAsync(&ns, dnstop, sizeof(int), hipMemcpyDeviceToHost, stream);
+                if (e2 == hipSuccess) e2 = hipStreamSynchronize(stream);
+                if (e2 == hipSuccess && stopped0 + ns >= count) break;
+            }
             if (e2 != hipSuccess) {
                 (void)hipGraphExecDestroy(ge);
                 return fail(h0, QAP_EDEVICE, std::string("batch replay: ") + hipGetErrorString(e2));
