@@ -149,6 +149,15 @@ def bnb_leg():
     return out
 
 
+def mapping_text(da) -> str:
+    """The Z-LAP mapping the handle used and how it was chosen."""
+    lanes, cols, us = da.zlap_mapping()
+    what = {-1: "one LAP per wavefront", -2: "two LAPs per wavefront"}.get(lanes, f"{lanes}-lane groups x {cols} cols")
+    if us >= 0:
+        return f"{what} (autotuned: {us:.0f} us on the tuning batch)"
+    return f"{what} ({'requested' if da.params.zlap_lanes else 'rule-based'})"
+
+
 def calibrate_copy(nbytes: int = 1 << 31):
     """A plain device copy of known size, for scaling PMC byte counters."""
     import torch
@@ -253,7 +262,7 @@ def main(argv=None):
             "z_laps_per_iter": T,
             "laps_per_iter": laps_per_iter,
             "z_entries": V,
-            "zlap_mapping": f"{da.params.zlap_lanes or 'auto'}x{da.params.zlap_cols or 'auto'}",
+            "zlap_mapping": mapping_text(da),
         },
         "laps_per_s": its * laps_per_iter,
         "iterations_done": done,

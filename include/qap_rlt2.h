@@ -69,8 +69,10 @@ typedef struct qap_params {
     double phi_y;
     double min_gap;        /* stop when (UB - LB)/|UB| < min_gap; 0 disables */
     int device;            /* HIP device ordinal */
-    int zlap_lanes;        /* Z-LAP lanes per LAP (8/16/32/64); 0 = autotuned */
-    int zlap_cols;         /* columns per lane (1/2); 0 = autotuned */
+    int zlap_lanes;        /* Z-LAP mapping: lanes per LAP group (8/16/32/64), -1 one
+                              LAP per wavefront, -2 two per wavefront (m <= 32);
+                              0 = chosen by the autotuner (see qap_zlap_mapping) */
+    int zlap_cols;         /* columns per lane for lane groups (1/2/4); 0 = autotuned */
     int timing;            /* 1: launch each kernel between HIP events on the
                               handle's stream and report per-phase device time
                               in qap_da_stats (no graph replay) */
@@ -172,6 +174,20 @@ int qap_rlt2_init(const double *F, const double *D, const double *B, int n,
                   const qap_params *p, qap_handle *out);
 
 int qap_destroy(qap_handle h);
+
+/* The Z-LAP mapping a handle uses (Section 2.3 "LAP Solution": every mapping
+ * solves the same LAPs with bitwise-identical results; the mapping decides
+ * only the speed).  With zlap_lanes = 0 the first qap_dual_ascent call
+ * measures every mapping that holds m = n-2 on a fixed synthetic batch of
+ * tiles and keeps the fastest, once per process, device and m (and, when the
+ * environment variable QAP_TUNE_CACHE names a file, in that JSON file, keyed
+ * by GPU architecture, kernel, m and kernel revision, for later processes).
+ * Before that call the rule-based choice is reported.  lanes: lanes per LAP
+ * group, or -1 / -2 for one / two LAPs per wavefront; cols: columns per lane;
+ * tuned_us: the chosen mapping's time over the synthetic batch in
+ * microseconds, or -1 if it was not measured.  Any output pointer may be
+ * NULL.  Errors: QAP_EINVAL (h NULL). */
+int qap_zlap_mapping(qap_handle h, int *lanes, int *cols, double *tuned_us);
 
 /* Run `iters` more F1 iterations (Algorithm 1 steps 2-5): ascent sweep of the
  * Type 1-3 rules (t >= 1), Z-LAPs, y-pair rule (t >= 1), Y-LAPs, X-LAP,

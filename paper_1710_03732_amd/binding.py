@@ -92,7 +92,7 @@ EXPORTED = ("qap_version", "qap_default_params", "qap_workspace_bytes", "qap_rlt
             "qap_orbit_count", "qap_multiplier_scale", "qap_orbit_features", "qap_orbit_targets",
             "qap_warm_start_outputs", "qap_mlp_create", "qap_mlp_destroy", "qap_mlp_set_stream",
             "qap_mlp_get_params", "qap_mlp_forward", "qap_mlp_gradients", "qap_mlp_train_step",
-            "qap_orbit_outputs", "qap_warm_start", "qap_set_allocator")
+            "qap_orbit_outputs", "qap_warm_start", "qap_set_allocator", "qap_zlap_mapping")
 
 
 def lib():
@@ -108,6 +108,8 @@ def lib():
         L.qap_workspace_bytes.restype = C.c_size_t
         L.qap_rlt2_init.argtypes = [_dp, _dp, _dp, C.c_int, C.POINTER(QapParams), C.POINTER(C.c_void_p)]
         L.qap_destroy.argtypes = [C.c_void_p]
+        L.qap_zlap_mapping.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                       C.POINTER(C.c_double)]
         L.qap_dual_ascent.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, C.POINTER(QapDaStats)]
         L.qap_get_trace.argtypes = [C.c_void_p, _dp, C.c_int, C.POINTER(C.c_int)]
         L.qap_get_assignment.argtypes = [C.c_void_p, _i32p, _i32p]
@@ -222,6 +224,14 @@ class DualAscent:
         if getattr(self, "h", None) is not None and self.h.value:
             lib().qap_destroy(self.h)
         self.h = None
+
+    def zlap_mapping(self):
+        """(lanes, cols, tuned_us) of the Z-LAP mapping in use; lanes -1 / -2
+        mean one / two LAPs per wavefront; tuned_us is -1 when the mapping
+        was requested or not yet measured (see qap_zlap_mapping)."""
+        lanes, cols, us = C.c_int(0), C.c_int(0), C.c_double(0.0)
+        _check(lib().qap_zlap_mapping(self.h, C.byref(lanes), C.byref(cols), C.byref(us)), self.h)
+        return lanes.value, cols.value, us.value
 
     def __del__(self):
         try:

@@ -239,6 +239,43 @@ __global__ __launch_bounds__(256) void k_bzlap(const BNode *__restrict__ nodes, 
     }
 }
 
+// Batched Z-LAPs with the scalar-controlled solver (m <= 32): one wavefront
+// per tile, its node found by binary search as in k_bzlap; the work per tile
+// is k_zlap_s<1>'s, in the same order.
+__global__ __launch_bounds__(64) void k_bzlap_s(const BNode *__restrict__ nodes, BatchPrefix pf, int nnodes)
+{
+    extern __shared__ double lds[];
+    const long long jg = blockIdx.x;
+    if (jg >= pf.zl[nnodes]) return;
+    const int b = find_node(pf.zl, nnodes, jg);
+    const BNode &N = nodes[b];
+    if (N.S->stopped) return;  // the whole block (one wave) leaves together
+    const int lane = threadIdx.x;
+    const int m = N.m, mm = m * m;
+    const long long t = jg - pf.zl[b];
+    double *src = N.Z + t * mm;
+    copy_to_lds(lds, src, mm, lane, 64);
+    const double yc0 = N.Yc[t];  // read now, added to after the solve
+    __syncthreads();
+    double u, v, th;
+    int p, st;
+    lap_solve_scalar1<32>(lds, 0, mm, m, u, v, p, th, st);
+    __builtin_amdgcn_wave_barrier();
+    double *scr = lds + mm;  // row potentials; v over the matching/links area
+    if (lane < m) scr[m + lane] = v;
+    __syncthreads();
+    // slacks back in place; the two half-waves take alternate rows
+    const int sub = lane >> 5, col = lane & 31;
+    if (col < m) {
+        const double vc = scr[m + col];
+        for (int r = sub; r < m; r += 2) src[r * m + col] = (lds[r * m + col] - scr[r]) - vc;
+    }
+    if (lane == 0) {
+        N.Yc[t] = yc0 + th;
+        atomicAdd(&N.bins[jg & (kStepBins - 1)], (unsigned long long)st);
+    }
+}
+
 // ----------------------------------------------------------------- Y-LAP --
 template <int L>
 __global__ __launch_bounds__(256) void k_bylap(const BNode *__restrict__ nodes, BatchPrefix pf, int nnodes,

@@ -211,7 +211,7 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
     HIPCHK(h0, hipGetLastError());
     BatchPrefix pf{dzl, dyl, dsw, dsc};
     BatchCtl ctl{bp->ub_cut, bp->min_improve, bp->window, count, dnstop};
-    const int Lz = mz <= 8 ? 8 : mz <= 16 ? 16 : mz <= 32 ? 32 : 64;
+    const int Lz = tuned_batch_lanes(h0->prm.device, stream, mz);  // measured once per tile size
     const int Ly = my <= 8 ? 8 : my <= 16 ? 16 : my <= 32 ? 32 : 64;
     auto launch_all = [&]() -> hipError_t {
         hipError_t e;
@@ -231,6 +231,8 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
     if (Lz == LL) hipLaunchKernelGGL((k_bzlap<LL>), dim3(blocks), dim3(G * LL), G * per, stream, dnodes, pf, count, mz);
             QAP_BZ(8) QAP_BZ(16) QAP_BZ(32) QAP_BZ(64)
 #undef QAP_BZ
+            if (Lz == -1)  // one tile per wavefront
+                hipLaunchKernelGGL(k_bzlap_s, dim3((unsigned)zl[count]), dim3(64), per, stream, dnodes, pf, count);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         {

@@ -52,6 +52,9 @@ struct qap_ctx {
     bool integer_data = false;
     int zl = 0, zc = 0;  // Z-LAP mapping
     int zlap_waves = 1;  // waves per Z-LAP block
+    bool zl_auto = false;     // mapping left to the autotuner (zlap_lanes = 0)
+    bool zl_tuned = false;    // the autotuner has chosen it
+    double zl_tune_us = -1.0; // its time over the tuner's synthetic tiles (< 0: rule-based)
     double offset = 0.0; // constant added to every permutation cost (B&B nodes)
     std::vector<double> hF, hD, hB;
     std::string err;
@@ -409,6 +412,7 @@ int create_ctx(int n, const double *F, const double *D, const double *B, const q
                       std::fabs(offset) < 9.0e15 && offset == std::floor(offset);
     derive_constants(h);
     pick_zlap(h->m, prm.zlap_lanes, prm.zlap_cols, h->zl, h->zc);
+    h->zl_auto = prm.zlap_lanes == 0;
 
     auto cleanup = [&](int code) {
         const std::string e = h->err;
@@ -488,9 +492,20 @@ int create_ctx(int n, const double *F, const double *D, const double *B, const q
 
 }  // namespace
 
+#include "tune_host.hpp"
+
 extern "C" {
 
 const char *qap_version(void) { return "qap-rlt2-mi355x 0.1 (gfx950, F1 FULL)"; }
+
+int qap_zlap_mapping(qap_handle h, int *lanes, int *cols, double *tuned_us)
+{
+    if (!h) return QAP_EINVAL;
+    if (lanes) *lanes = h->zl;
+    if (cols) *cols = h->zc;
+    if (tuned_us) *tuned_us = h->zl_tuned ? h->zl_tune_us : -1.0;
+    return QAP_OK;
+}
 
 int qap_default_params(qap_params *p)
 {
@@ -573,6 +588,15 @@ int qap_dual_ascent(qap_handle h, int iters, double *lb_out, double *alpha_out, 
     if (!h) return QAP_EINVAL;
     if (iters < 0) return fail(h, QAP_EINVAL, "iters < 0");
     HIPCHK(h, hipSetDevice(h->prm.device));
+    if (h->zl_auto && !h->zl_tuned && iters > 0) {
+        // pick the Z-LAP mapping by measurement before anything is captured
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        tune_handle_zlap(h);
+        if (h->graph) {
+            (void)hipGraphExecDestroy(h->graph);
+            h->graph = nullptr;
+        }
+    }
     auto t0 = std::chrono::steady_clock::now();
     DevScalars before{};
     HIPCHK(h, hipMemcpyAsync(&before, h->S, sizeof(before), hipMemcpyDeviceToHost, h->stream));

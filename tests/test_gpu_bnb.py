@@ -168,3 +168,22 @@ def test_bnb_depth_cap_keeps_the_optimum(inst):
         obj, perm, st = B.DualAscent(F, D, Bm).bnb_solve(node_iters=3, depth_cap=cap)
         assert obj == opt and O.qap_cost(F, D, Bm, perm) == opt
         assert st["nodes"] > 1
+
+
+def test_batched_lane_counts_are_tuned(tmp_path, monkeypatch):
+    """The batched Z-LAP kernel (lane groups, or one tile per wavefront for
+    m <= 32) is chosen by timing per tile size; the optimum is unaffected
+    and the choices land in the cache file."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("QAP_TUNE_CACHE", str(cache))
+    F, D, Bm = I.dense_instance(9, 5).arrays()
+    opt, _ = O.bruteforce(F, D, Bm)
+    obj, perm, st = B.DualAscent(F, D, Bm).bnb_solve(node_iters=3)
+    assert obj == opt and st["nodes"] > 1
+    entries = json.loads(cache.read_text())
+    tuned = {k: v for k, v in entries.items() if "/bzlap/m" in k}
+    assert tuned
+    for k, (lanes, cols, us) in tuned.items():
+        m = int(k.split("/m")[1].split("/")[0])
+        assert cols == 1 and us > 0.0
+        assert (lanes == -1 and m <= 32) or (lanes in (8, 16, 32, 64) and lanes >= m)

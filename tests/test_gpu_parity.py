@@ -7,6 +7,7 @@ zero), which is stricter than the 1e-9 relative bound tolerance the method's
 results are held to; that tolerance is asserted as well.
 """
 import itertools
+import json
 
 import numpy as np
 import pytest
@@ -345,3 +346,33 @@ def test_arena_from_a_caller_allocator():
     assert got and got[0] == B.workspace_bytes(8) - 8 * 1024
     a.close()
     assert len(freed) == 1
+
+
+def test_autotuned_mapping_is_bitwise_the_requested_one(tmp_path, monkeypatch):
+    """With zlap_lanes = 0 the first dual ascent times every Z-LAP mapping
+    that holds m and keeps the fastest. The choice holds m, is written to the
+    QAP_TUNE_CACHE file, and the run equals a run with that mapping
+    requested (every mapping solves the same LAPs bitwise)."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("QAP_TUNE_CACHE", str(cache))
+    inst = I.grid_instance(15, 3, 5, 0.4, 1, 10, 41)
+    F, D, Bm = inst.arrays()
+    m = inst.n - 2
+    auto = B.DualAscent(F, D, Bm)
+    assert auto.zlap_mapping()[2] == -1.0  # nothing measured before the first run
+    auto.run(6)
+    lanes, cols, us = auto.zlap_mapping()
+    assert us > 0.0
+    if lanes == -1:
+        assert cols == 1
+    elif lanes == -2:
+        assert cols == 1 and m <= 32
+    else:
+        assert lanes in (8, 16, 32, 64) and lanes * cols >= m
+    forced = B.DualAscent(F, D, Bm, zlap_lanes=lanes, zlap_cols=cols)
+    forced.run(6)
+    assert forced.zlap_mapping()[:2] == (lanes, cols) and forced.zlap_mapping()[2] == -1.0
+    assert np.array_equal(auto.trace(), forced.trace())
+    entries = json.loads(cache.read_text())
+    keys = [k for k in entries if f"/zlap/m{m}/" in k]
+    assert len(keys) == 1 and entries[keys[0]][:2] == [lanes, cols]
