@@ -14,6 +14,8 @@ stream, each phase between HIP events recorded on that stream.
 
 Prints one JSON line.  `roofline` is for the kernel with the largest device
 time; its `achieved` is algorithmic bytes per launch / average launch time.
+`frac` is against the 8 TB/s peak and `frac_of_copy` against a plain 2 GiB
+device copy measured in the same run (after the timed region).
 `time_to_bound` compares 100 cold iterations with the learned warm start
 (trained weights from train_warm.py) reaching the same bound; its
 `mlp_roofline` gives the inference kernel's TFLOP/s against the bf16 MFMA
@@ -158,6 +160,30 @@ def mapping_text(da) -> str:
     return f"{what} ({'requested' if da.params.zlap_lanes else 'rule-based'})"
 
 
+def measure_copy_gbs(nbytes: int = 1 << 31, reps: int = 5) -> float:
+    """Read + write GB/s of a plain device copy of nbytes, best of reps
+    after one warm-up: the practical bandwidth beside the 8 TB/s peak."""
+    import torch
+
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    best = None
+    for rep in range(reps + 1):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        if rep > 0 and (best is None or ms < best):
+            best = ms
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (best * 1e-3) / 1e9
+
+
 def calibrate_copy(nbytes: int = 1 << 31):
     """A plain device copy of known size, for scaling PMC byte counters."""
     import torch
@@ -238,6 +264,7 @@ def main(argv=None):
     achieved = ab[dom] / dom_s / 1e9
     traffic = load_traffic(dom, inst.name)
     iter_bytes = sum(ab.values())
+    copy_gbs = measure_copy_gbs()  # after the timed region
     steps_per_zlap = r["dijkstra_steps"] / max(1, done * laps_per_iter)
 
     out = {
@@ -272,12 +299,13 @@ def main(argv=None):
         "gap": r["gap"],
         "dijkstra_steps_per_lap": steps_per_zlap,
         "iteration_hbm": {"bytes": iter_bytes, "achieved_gbs": iter_bytes / (el / done) / 1e9,
-                          "frac": iter_bytes / (el / done) / 1e9 / HBM_PEAK_GBS},
+                          "frac": iter_bytes / (el / done) / 1e9 / HBM_PEAK_GBS,
+                          "copy_gbs": copy_gbs, "frac_of_copy": iter_bytes / (el / done) / 1e9 / copy_gbs},
         "roofline": {"bound": "hbm", "kernel": {"zlap": "k_zlap", "sweep": "k_sweep+k_scale_xy"}[dom],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": ab[dom],
-                     "avg_launch_ms": phase_ms[dom]},
+                     "avg_launch_ms": phase_ms[dom], "frac_of_copy": achieved / copy_gbs},
         "bnb": None,
         "time_to_bound": None,
         "cpu_baseline": None,
