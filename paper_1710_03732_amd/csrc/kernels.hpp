@@ -117,10 +117,12 @@ __global__ void k_init_xy(const double *__restrict__ F, const double *__restrict
 // 3-D array over the locations (p,q,r): member e is contiguous along its
 // third location.  A block takes one triple and one SB^3 cube of locations
 // and transposes through LDS: load phase (each member read as runs of SB
-// contiguous doubles along its own last axis, g and pi staged in a padded
-// [p][q][r] layout), orbit phase (one thread per orbit), store phase (runs
-// again).  Block numbering keeps all cubes of one triple on one XCD, back to
-// back, so the partial cache lines at run ends merge in that XCD's L2.
+// contiguous doubles along its own last axis, pi_z staged in a padded
+// [p][q][r] layout, pi_y / pi_x of the block's tiles and pairs read once),
+// orbit phase (one thread per orbit forms the six g and the shares), store
+// phase (runs again).  Block numbering keeps all cubes of one triple on one
+// XCD, back to back, so the partial cache lines at run ends merge in that
+// XCD's L2.
 constexpr int SB = 8;                       // cube edge
 constexpr int SB_Q = SB + 1;                // padded q pitch
 constexpr int SB_P = SB * SB_Q + 1;         // padded p pitch
