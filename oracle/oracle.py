@@ -69,6 +69,7 @@ def lib():
         L.orc_da_iter0_xy.argtypes = [C.c_void_p]
         L.orc_iter1_tile.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
         L.orc_da_track.argtypes = [C.c_void_p]
+        L.orc_da_set_half.argtypes = [C.c_void_p]
         L.orc_da_multipliers.argtypes = [C.c_void_p, _dp, _dp]
         L.orc_da_from_multipliers.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_da_from_multipliers.restype = C.c_void_p
@@ -99,6 +100,9 @@ def max_threads() -> int:
 
 
 FULL = (5.0 / 6.0, 1.0, 1.0, 1.0 / 5.0, 0.5)
+# HALF scheme of Section 5: upper-member kz = 2/3, ky = kx = 1, upper share
+# phi = 1/2, y-pair 1/2; the trailing 1 selects the scheme (orc_da_set_half)
+HALF = (2.0 / 3.0, 1.0, 1.0, 0.5, 0.5, 1.0)
 
 
 def lap(M):
@@ -157,10 +161,13 @@ class DualAscent:
         self._keep = (F, D, B)
         P = _f64(params)
         self._params = P
-        h = _handle if _handle is not None else lib().orc_da_create(self.n, _d(F), _d(D), _d(B), _d(P))
+        h = _handle if _handle is not None else lib().orc_da_create(self.n, _d(F), _d(D), _d(B), _d(P[:5]))
         if not h:
             raise ValueError("oracle: bad instance")
         self.h = C.c_void_p(h)
+        self.half = len(P) > 5 and P[5] == 1.0
+        if self.half and lib().orc_da_set_half(self.h) != 0:
+            raise ValueError("oracle: HALF needs zero lower z costs and no tracking")
 
     @classmethod
     def from_arrays(cls, F, D, B, params, LB, X, Y, Z):

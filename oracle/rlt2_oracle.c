@@ -309,6 +309,7 @@ typedef struct orc_da {
     double *trace;          /* LB after each iteration */
     int trace_len, trace_cap;
     double *Vt, *Ut;        /* tracked S-form multipliers v (n^6), u (n^4), or NULL */
+    int half;               /* HALF scheme (orc_da_set_half) */
 } orc_da;
 
 static void orc_da_derive(orc_da *s)
@@ -406,6 +407,32 @@ orc_da *orc_da_from_arrays(int n, const double *F, const double *D, const double
     return s;
 }
 
+/* Switch a fresh state to the HALF scheme (Section 5, after Goncalves
+ * 2017).  In every orbit the three members whose first two facilities
+ * ascend (the upper members) keep (1 - kz) of their z slack and take shares;
+ * the three lower members give everything (kz = 1) and take nothing, so
+ * their costs stay 0, their Z-LAPs (tiles with i > j) are all-zero LAPs of
+ * value 0 and are not solved.  Shares: an upper giver's g goes half to each
+ * other upper member (phi, 1/2); a lower giver's g a third to each of its
+ * three upper partners.  Uses kz and phi from the params (2/3 and 1/2 in
+ * the HALF preset).  Needs every lower z cost (first facility above the
+ * second) to be 0, as on a fresh state, and no tracking; returns 0, or -1
+ * when that does not hold. */
+int orc_da_set_half(orc_da *s)
+{
+    if (!s || s->Vt) return -1;
+    int n = s->n;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j)
+            for (int k = 0; k < n; ++k)
+                for (int p = 0; p < n; ++p)
+                    for (int q = 0; q < n; ++q)
+                        for (int r = 0; r < n; ++r)
+                            if (s->Z[IX6(n, i, j, k, p, q, r)] != 0.0) return -1;
+    s->half = 1;
+    return 0;
+}
+
 /* The six members of the orbit {A=(i,p), B=(j,q), C=(k,r)} (i<j<k) in the
  * canonical order (A,B,C), (A,C,B), (B,A,C), (B,C,A), (C,A,B), (C,B,A); the
  * member (P1,P2,P3) is z_{P1.f P2.f P3.f P1.l P2.l P3.l}, the symmetric
@@ -420,6 +447,11 @@ static void orbit_members(int i, int j, int k, int p, int q, int r, int fac[6][3
             loc[e][c] = L3[ord[e][c]];
         }
 }
+
+/* HALF scheme, lower giver: its g is split equally among its three upper
+ * partners (the reading of Section 5's fractions that gives away exactly
+ * the giver's g; 1/2 each would give away 3/2 of it). */
+#define ORC_HALF_PHI_LOW (1.0 / 3.0)
 
 void orc_da_sweep(orc_da *s)
 {
@@ -438,6 +470,30 @@ void orc_da_sweep(orc_da *s)
                             size_t zi[6];
                             double g[6], pz[6];
                             orbit_members(i, j, k, p, q, r, fac, loc);
+                            if (s->half) {
+                                /* upper members: the first two facilities ascend,
+                                 * (A,B,C), (A,C,B), (B,C,A) = 0, 1, 3; lower: 2, 4, 5 */
+                                static const int up[3] = {0, 1, 3};
+                                for (int e = 0; e < 6; ++e) {
+                                    const int upper = fac[e][0] < fac[e][1];
+                                    zi[e] = IX6(n, fac[e][0], fac[e][1], fac[e][2], loc[e][0], loc[e][1], loc[e][2]);
+                                    pz[e] = Z[zi[e]];
+                                    double py = Y[IX4(n, fac[e][0], fac[e][1], loc[e][0], loc[e][1])];
+                                    double px = X[IX2(n, fac[e][0], loc[e][0])];
+                                    g[e] = ((upper ? s->kz : 1.0) * pz[e] + s->ky2 * py) + s->kx3 * px;
+                                }
+                                double acc_low = (g[2] + g[4]) + g[5];
+                                for (int a = 0; a < 3; ++a) {
+                                    int e = up[a];
+                                    int f1 = up[a == 0 ? 1 : 0], f2 = up[a == 2 ? 1 : 2];
+                                    double acc_up = g[f1] + g[f2];
+                                    Z[zi[e]] = s->okz * pz[e] + (s->phi * acc_up + ORC_HALF_PHI_LOW * acc_low);
+                                }
+                                Z[zi[2]] = 0.0;
+                                Z[zi[4]] = 0.0;
+                                Z[zi[5]] = 0.0;
+                                continue;
+                            }
                             for (int e = 0; e < 6; ++e) {
                                 zi[e] = IX6(n, fac[e][0], fac[e][1], fac[e][2], loc[e][0], loc[e][1], loc[e][2]);
                                 pz[e] = Z[zi[e]];
@@ -483,6 +539,7 @@ void orc_da_zphase(orc_da *s)
         int rc[ORC_MAXM], ks[ORC_MAXM], rs[ORC_MAXM];
         for (int j = 0; j < n; ++j) {
             if (j == i) continue;
+            if (s->half && j < i) continue;  /* HALF: lower tiles stay all-zero (theta 0) */
             int c = 0;
             for (int k = 0; k < n; ++k) if (k != i && k != j) ks[c++] = k;
             for (int p = 0; p < n; ++p)
@@ -660,6 +717,7 @@ void orc_da_export(const orc_da *s, double *X, double *Y, double *Z)
  * Both are zero-sum over an orbit / a pair.  Tracking starts at zero. */
 int orc_da_track(orc_da *s)
 {
+    if (s->half) return -1;  /* tracking follows the FULL shares */
     size_t n2 = (size_t)s->n * s->n, n4 = n2 * n2;
     if (!s->Vt) s->Vt = calloc(n4 * n2, sizeof(double));
     if (!s->Ut) s->Ut = calloc(n4, sizeof(double));

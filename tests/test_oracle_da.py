@@ -282,3 +282,127 @@ def test_tracked_multipliers_reproduce_the_bound(inst):
     s.run(1)
     assert s.LB >= da.LB - 1e-9 * max(1.0, abs(da.LB))
     assert s.LB <= O.bruteforce(F, D, Bm)[0] + 1e-9
+
+
+# ---- HALF scheme (Section 5): only the Z-LAPs of tiles with i < j ----------
+
+def _lower(m):
+    """A member index tuple (i, j, k, p, q, r) is lower when i > j."""
+    return m[0] > m[1]
+
+
+@pytest.mark.parametrize("inst", INSTANCES[1:], ids=lambda x: x.name)
+def test_half_bound_below_optimum_and_monotone(inst):
+    F, D, B = inst.arrays()
+    opt = brute_opt(F, D, B)
+    da = O.DualAscent(F, D, B, O.HALF)
+    da.run(40)
+    tr = da.trace()
+    assert np.all(np.diff(tr) >= -1e-9 * max(1.0, abs(opt)))          # Theorem 1
+    assert np.all(tr <= opt + 1e-9 * max(1.0, abs(opt)))              # Eq. lgduality
+    assert da.UB >= opt
+    if da.proven():
+        assert da.UB == opt
+
+
+@pytest.mark.parametrize("inst", [I.random_instance(5, 3), I.grid_instance(6, 2, 3, 0.4, 1, 9, 4),
+                                  I.random_instance(6, 8, lo=0, hi=20)], ids=lambda x: x.name)
+def test_half_reformulation_identity_every_phase(inst):
+    """HALF moves (sweep with the upper/lower shares, the Z-LAPs of tiles
+    with i < j only, y-pair rule, Y/X extraction) keep the identity for every
+    permutation and reduced costs >= 0 (a share that gives away more or less
+    than the giver's g breaks the identity); lower z costs stay exactly 0."""
+    F, D, B = inst.arrays()
+    n = F.shape[0]
+    perms = [np.array(p, dtype=np.int32) for p in itertools.permutations(range(n))]
+    lower = np.zeros((n,) * 6, dtype=bool)
+    for i in range(n):
+        lower[i, :i] = True
+    da = O.DualAscent(F, D, B, O.HALF)
+    for t in range(4):
+        if t >= 1:
+            da.sweep()
+            _check_identity(da, F, D, B, perms)
+            assert not da.export()[2][lower].any()
+        da.zphase()
+        _check_identity(da, F, D, B, perms)
+        assert not da.export()[2][lower].any()
+        if t >= 1:
+            da.yequal()
+        da.yphase()
+        da.xphase()
+        _check_identity(da, F, D, B, perms)
+
+
+def test_half_sweep_shares_by_hand():
+    """One HALF sweep from upper z slack and y/x slack: every upper member
+    keeps (1 - 2/3) of its own z slack and receives half of each other upper
+    member's g and a third of each lower member's g, where
+    g = kz*pi_z + pi_y(P1P2)/(n-2) + pi_x(P1)/((n-1)(n-2)) and lower members
+    have pi_z = 0, kz = 1; lower members end at 0; the orbit total is
+    conserved."""
+    n = 6
+    rng = np.random.default_rng(21)
+    F = rng.integers(0, 9, size=(n, n)).astype(float)
+    D = rng.integers(0, 9, size=(n, n)).astype(float)
+    X = rng.random((n, n))
+    Y = rng.random((n,) * 4)
+    Z = rng.random((n,) * 6)
+    for i in range(n):
+        Z[i, :i] = 0.0  # lower members hold no z cost
+    da = O.DualAscent.from_arrays(F, D, np.zeros((n, n)), O.HALF, 0.0, X, Y, Z)
+    da.sweep()
+    X1, Y1, Z1 = da.export()
+    valid_y = np.ones((n,) * 4, dtype=bool)
+    for a in range(n):
+        valid_y[a, a] = False
+        valid_y[:, :, a, a] = False
+    assert not X1.any() and not Y1[valid_y].any()  # ky = kx = 1 empty the x and y levels
+    for (i, j, k) in [(0, 1, 2), (1, 3, 5), (0, 4, 5), (2, 3, 4)]:
+        for (p, q, r) in [(0, 1, 2), (5, 3, 1), (2, 0, 4), (4, 5, 3)]:
+            mem = _orbit_members(i, j, k, p, q, r)
+            g = []
+            for m in mem:
+                a, b, c, x, y, z = m
+                kz = 1.0 if _lower(m) else 2.0 / 3.0
+                g.append(kz * Z[m] + Y[a, b, x, y] / (n - 2) + X[a, x] / ((n - 1) * (n - 2)))
+            ups = [e for e, m in enumerate(mem) if not _lower(m)]
+            lows = [e for e, m in enumerate(mem) if _lower(m)]
+            assert ups == [0, 1, 3] and lows == [2, 4, 5]
+            total = 0.0
+            for e in ups:
+                expect = Z[mem[e]] / 3.0 + 0.5 * sum(g[f] for f in ups if f != e) + sum(g[f] for f in lows) / 3.0
+                assert abs(Z1[mem[e]] - expect) <= 1e-13 * max(1.0, expect)
+                total += Z1[mem[e]]
+            for e in lows:
+                assert Z1[mem[e]] == 0.0
+            assert abs(total - sum(g) - sum(Z[mem[e]] / 3.0 for e in ups)) <= 1e-12 * total
+
+
+def test_half_keeps_up_with_full_on_the_grid():
+    """The paper's claim for HALF: about the bound of solving every Z-LAP
+    for half the Z-LAPs. On the 2x4 grid instance both reach within 1 % of
+    the optimum in 60 iterations."""
+    inst = I.grid_n8()
+    F, D, B = inst.arrays()
+    opt = brute_opt(F, D, B)
+    full = O.DualAscent(F, D, B)
+    half = O.DualAscent(F, D, B, O.HALF)
+    full.run(60)
+    half.run(60)
+    assert half.LB <= opt and full.LB <= opt
+    assert half.LB >= 0.99 * opt and full.LB >= 0.99 * opt
+
+
+def test_half_refuses_nonzero_lower_costs_and_tracking():
+    n = 5
+    rng = np.random.default_rng(3)
+    F = rng.integers(0, 9, size=(n, n)).astype(float)
+    D = rng.integers(0, 9, size=(n, n)).astype(float)
+    Z = np.zeros((n,) * 6)
+    Z[3, 1, 0, 0, 1, 2] = 1.0  # a lower member with cost
+    with pytest.raises(ValueError):
+        O.DualAscent.from_arrays(F, D, np.zeros((n, n)), O.HALF, 0.0, np.zeros((n, n)), np.zeros((n,) * 4), Z)
+    da = O.DualAscent(F, D, None, O.HALF)
+    with pytest.raises(Exception):
+        da.track()
