@@ -49,7 +49,7 @@ extern "C" {
 #define QAP_ENOMEM (-2)       /* device arena larger than free memory (checked first) */
 #define QAP_EDEVICE (-3)      /* HIP runtime error (text in qap_last_error) */
 #define QAP_ESTATE (-4)       /* call out of order, or bad checksum on import */
-#define QAP_EUNSUPPORTED (-5) /* n outside the supported range 3..64 */
+#define QAP_EUNSUPPORTED (-5) /* n outside 3..64, or a call a HALF handle refuses */
 
 typedef struct qap_ctx *qap_handle;
 
@@ -62,7 +62,22 @@ typedef void (*qap_free_fn)(void *ptr, void *ctx);
  * is the share each of the five symmetric partners receives (the phi^z_k of
  * the rules, all equal); phi_y the share of the y-pair rule (Eq. da:yrule1).
  * qap_default_params() gives the FULL preset: kappa_z = 5/6,
- * kappa_y = kappa_x = 1, phi_z = 1/5, phi_y = 1/2. */
+ * kappa_y = kappa_x = 1, phi_z = 1/5, phi_y = 1/2.
+ *
+ * scheme = QAP_SCHEME_HALF selects the HALF scheme of Section 5: only the
+ * z variables whose first two facilities ascend (i < j) are kept; the Z-LAPs
+ * of the other n^2 (n-1)^2 / 2 tiles are not solved and their entries stay 0.
+ * In the sweep an upper member keeps (1 - kappa_z) of its slack and receives
+ * phi_z of each upper partner's share plus 1/3 of each lower partner's (the
+ * lower members, with no multiplier of their own, give their whole y and x
+ * shares).  HALF needs phi_z = 1/2 (two upper partners), the scalar Z-LAP
+ * mapping (zlap_lanes 0 or -1) and starts from the zero z costs of
+ * qap_rlt2_init; multiplier tracking, qap_set_multipliers, warm starts and
+ * branch-and-bound refuse a HALF handle (QAP_EUNSUPPORTED).  The HALF preset
+ * is kappa_z = 2/3, kappa_y = kappa_x = 1, phi_z = phi_y = 1/2. */
+#define QAP_SCHEME_FULL 0
+#define QAP_SCHEME_HALF 1
+
 typedef struct qap_params {
     double kappa_z, kappa_y, kappa_x;
     double phi_z;
@@ -76,6 +91,7 @@ typedef struct qap_params {
     int timing;            /* 1: launch each kernel between HIP events on the
                               handle's stream and report per-phase device time
                               in qap_da_stats (no graph replay) */
+    int scheme;            /* QAP_SCHEME_FULL (0) or QAP_SCHEME_HALF (1) */
     qap_alloc_fn alloc;    /* optional device allocator */
     qap_free_fn free_fn;
     void *alloc_ctx;
@@ -89,7 +105,7 @@ typedef struct qap_da_stats {
     double gap;            /* (ub - lb)/|ub| */
     int proven;            /* 1 when lb certifies ub optimal (feasibility check) */
     int pad;
-    long long laps;        /* LAPs solved by this call: iters*(T + n^2 + 1) */
+    long long laps;        /* LAPs solved by this call: iters*(T + n^2 + 1), T/2 for HALF */
     long long dijkstra_steps; /* Dijkstra steps of all LAPs of this call */
     double seconds;        /* wall time of the call (device-synchronised) */
     double ms_sweep;       /* with params.timing: summed device milliseconds of */
@@ -221,7 +237,8 @@ int qap_export_state(qap_handle h, qap_state_header *hdr, double *x, double *y, 
 int qap_export_z_tiles(qap_handle h, const int64_t *tiles, int count, double *out);
 
 /* Replace the state with exported arrays (resume).  hdr->checksum must match;
- * the next iteration runs with t = hdr->t.  Errors: QAP_ESTATE on mismatch. */
+ * the next iteration runs with t = hdr->t.  Errors: QAP_ESTATE on mismatch;
+ * QAP_EINVAL on a HALF handle when a z entry of a tile with i > j is not 0. */
 int qap_import_state(qap_handle h, const qap_state_header *hdr, const double *x,
                      const double *y, const double *z);
 

@@ -339,10 +339,13 @@ class Iter0XY:
         B = np.zeros_like(F) if B is None else _f64(B)
         self._keep = (F, D, B)
         P = _f64(params)
-        h = lib().orc_da_create_xy(self.n, _d(F), _d(D), _d(B), _d(P))
+        h = lib().orc_da_create_xy(self.n, _d(F), _d(D), _d(B), _d(P[:5]))
         if not h:
             raise ValueError("oracle: bad instance")
         self.h = C.c_void_p(h)
+        self.half = len(P) > 5 and P[5] == 1.0
+        if self.half and lib().orc_da_set_half(self.h) != 0:
+            raise ValueError("oracle: HALF switch refused")
         if lib().orc_da_iter0_xy(self.h) != 0:
             raise RuntimeError("iteration 0 failed")
 

@@ -417,11 +417,13 @@ orc_da *orc_da_from_arrays(int n, const double *F, const double *D, const double
  * three upper partners.  Uses kz and phi from the params (2/3 and 1/2 in
  * the HALF preset).  Needs every lower z cost (first facility above the
  * second) to be 0, as on a fresh state, and no tracking; returns 0, or -1
- * when that does not hold. */
+ * when that does not hold.  A state without the z array (orc_da_create_xy)
+ * may switch too: orc_iter1_tile then forms HALF tiles. */
 int orc_da_set_half(orc_da *s)
 {
     if (!s || s->Vt) return -1;
     int n = s->n;
+    if (s->Z)
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < i; ++j)
             for (int k = 0; k < n; ++k)
@@ -805,7 +807,9 @@ void orc_da_min_entries(const orc_da *s, double *out3)
  * orc_da_iter0_xy runs that iteration.  orc_iter1_tile then forms one tile of
  * the iteration-1 Z-LAPs entry by entry from the sweep formula (pi_z = 0 at
  * t = 0, so g_f = (kz*0 + ky2*pi_y) + kx3*pi_x, new_e = okz*0 + phi*sum) and
- * solves it.
+ * solves it.  Under HALF only upper tiles (i < j) are formed, with the HALF
+ * shares of orc_da_sweep (a lower member's g has factor 1 on its zero z).
+ * Iteration 0 is the same under both schemes: every Z-LAP is all-zero.
  * ---------------------------------------------------------------------- */
 orc_da *orc_da_create_xy(int n, const double *F, const double *D, const double *B,
                          const double *params)
@@ -883,6 +887,7 @@ int orc_iter1_tile(const orc_da *s, int i, int j, int p, int q, double *M_out, d
 {
     int n = s->n, m = n - 2;
     if (s->t != 1 || i == j || p == q || m < 1 || m > ORC_MAXM) return -1;
+    if (s->half && i > j) return -1;  /* lower tiles stay all-zero */
     double *M = malloc(sizeof(double) * m * m);
     int a = 0;
     for (int k = 0; k < n; ++k) {
@@ -906,9 +911,24 @@ int orc_iter1_tile(const orc_da *s, int i, int j, int p, int q, double *M_out, d
                 double pz = 0.0;
                 double py = s->Y[IX4(n, fac[e][0], fac[e][1], loc[e][0], loc[e][1])];
                 double px = s->X[IX2(n, fac[e][0], loc[e][0])];
-                g[e] = (s->kz * pz + s->ky2 * py) + s->kx3 * px;
+                const double kze = (s->half && fac[e][0] > fac[e][1]) ? 1.0 : s->kz;
+                g[e] = (kze * pz + s->ky2 * py) + s->kx3 * px;
                 if (fac[e][0] == i && fac[e][1] == j && fac[e][2] == k &&
                     loc[e][0] == p && loc[e][1] == q && loc[e][2] == r) me = e;
+            }
+            if (s->half) {
+                /* me is an upper member (i < j): 0, 1 or 3 */
+                double acc_up = 0.0;
+                int first = 1;
+                for (int e = 0; e < 6; ++e) {
+                    if (e == me || e == 2 || e == 4 || e == 5) continue;
+                    if (first) { acc_up = g[e]; first = 0; }
+                    else acc_up = acc_up + g[e];
+                }
+                double acc_low = (g[2] + g[4]) + g[5];
+                M[a * m + b] = s->okz * 0.0 + (s->phi * acc_up + ORC_HALF_PHI_LOW * acc_low);
+                ++b;
+                continue;
             }
             double acc = 0.0;
             int first = 1;

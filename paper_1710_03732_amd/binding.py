@@ -27,8 +27,12 @@ class QapParams(C.Structure):
     _fields_ = [("kappa_z", C.c_double), ("kappa_y", C.c_double), ("kappa_x", C.c_double),
                 ("phi_z", C.c_double), ("phi_y", C.c_double), ("min_gap", C.c_double),
                 ("device", C.c_int), ("zlap_lanes", C.c_int), ("zlap_cols", C.c_int),
-                ("timing", C.c_int), ("alloc", _alloc_fn), ("free_fn", _free_fn),
-                ("alloc_ctx", C.c_void_p)]
+                ("timing", C.c_int), ("scheme", C.c_int), ("alloc", _alloc_fn),
+                ("free_fn", _free_fn), ("alloc_ctx", C.c_void_p)]
+
+
+SCHEME_FULL = 0
+SCHEME_HALF = 1
 
 
 class QapDaStats(C.Structure):
@@ -175,9 +179,21 @@ def _dptr(a):
 def default_params(**kw) -> QapParams:
     p = QapParams()
     _check(lib().qap_default_params(C.byref(p)))
+    names = {f[0] for f in QapParams._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown qap_params field {k!r}")
         setattr(p, k, v)
     return p
+
+
+def half_params(**kw) -> QapParams:
+    """The HALF preset of Section 5: kappa_z = 2/3, kappa_y = kappa_x = 1,
+    phi_z = phi_y = 1/2, scalar Z-LAP mapping."""
+    base = dict(kappa_z=2.0 / 3.0, kappa_y=1.0, kappa_x=1.0, phi_z=0.5, phi_y=0.5,
+                zlap_lanes=-1, scheme=SCHEME_HALF)
+    base.update(kw)
+    return default_params(**base)
 
 
 def version() -> str:

@@ -53,6 +53,7 @@ struct qap_ctx {
     int zl = 0, zc = 0;  // Z-LAP mapping
     int zlap_waves = 1;  // waves per Z-LAP block
     bool zl_auto = false;     // mapping left to the autotuner (zlap_lanes = 0)
+    bool half = false;        // HALF scheme: only the tiles with i < j are solved
     bool zl_tuned = false;    // the autotuner has chosen it
     double zl_tune_us = -1.0; // its time over the tuner's synthetic tiles (< 0: rule-based)
     double offset = 0.0; // constant added to every permutation cost (B&B nodes)
@@ -126,8 +127,12 @@ Sizes sizes_for(int n, int trace_cap)
 bool params_ok(const qap_params &p)
 {
     auto in01 = [](double x) { return std::isfinite(x) && x >= 0.0 && x <= 1.0; };
-    return in01(p.kappa_z) && in01(p.kappa_y) && in01(p.kappa_x) && in01(p.phi_z) && in01(p.phi_y) &&
-           std::fabs(5.0 * p.phi_z - 1.0) < 1e-12 && std::isfinite(p.min_gap) && p.min_gap >= 0.0;
+    // each member shares among its partners: five under FULL, two upper ones under HALF
+    const double partners = p.scheme == QAP_SCHEME_HALF ? 2.0 : 5.0;
+    const bool mapping = p.scheme != QAP_SCHEME_HALF || p.zlap_lanes == 0 || p.zlap_lanes == -1;
+    return (p.scheme == QAP_SCHEME_FULL || p.scheme == QAP_SCHEME_HALF) && mapping && in01(p.kappa_z) &&
+           in01(p.kappa_y) && in01(p.kappa_x) && in01(p.phi_z) && in01(p.phi_y) &&
+           std::fabs(partners * p.phi_z - 1.0) < 1e-12 && std::isfinite(p.min_gap) && p.min_gap >= 0.0;
 }
 
 // Z-LAP lane mapping for size m (lanes per LAP, columns per lane).
@@ -166,9 +171,11 @@ hipError_t launch_zlap_s(qap_ctx *h)
 {
     const int m = h->m;
     const size_t per = ((size_t)m * m + 2 * m) * sizeof(double) * H;
-    const long long blocks = (h->T + H - 1) / H;
+    // HALF: one block per tile with i < j (half of them; H = 1 only)
+    const int half = (H == 1 && h->half) ? 1 : 0;
+    const long long blocks = half ? h->T / 2 : (h->T + H - 1) / H;
     hipLaunchKernelGGL((k_zlap_s<H>), dim3((unsigned)blocks), dim3(64), per, h->stream, h->Z, h->Yc, m,
-                       h->T, h->S, h->bins);
+                       h->T, h->S, h->bins, half);
     return hipGetLastError();
 }
 
@@ -215,16 +222,19 @@ hipError_t launch_sweep(qap_ctx *h)
 {
     hipError_t e;
     {
-        SweepConsts K{h->kz, h->okz, h->ky2, h->kx3, h->phi};
+        SweepConsts K{h->kz, h->okz, h->ky2, h->kx3, h->phi, 1.0 / 3.0};
         const unsigned groups8 = (unsigned)((h->ntriples + 7) / 8);
         const int nb = (h->n + SB - 1) / SB;
         const unsigned blocks = groups8 * 8u * (unsigned)(nb * nb * nb);
-        if (h->Vt)
-            hipLaunchKernelGGL(k_sweep<true>, dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py, h->Px,
-                               h->triples, h->ntriples, h->n, nb, K, h->S, h->Vt);
+        if (h->half)
+            hipLaunchKernelGGL((k_sweep<false, true>), dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py,
+                               h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, (double *)nullptr);
+        else if (h->Vt)
+            hipLaunchKernelGGL((k_sweep<true, false>), dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py,
+                               h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, h->Vt);
         else
-            hipLaunchKernelGGL(k_sweep<false>, dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py, h->Px,
-                               h->triples, h->ntriples, h->n, nb, K, h->S, (double *)nullptr);
+            hipLaunchKernelGGL((k_sweep<false, false>), dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py,
+                               h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, (double *)nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const long long work = std::max<long long>(h->T, (long long)h->n * h->n);
         const unsigned sb = (unsigned)std::min<long long>((work + 255) / 256, 65535);
@@ -411,8 +421,10 @@ int create_ctx(int n, const double *F, const double *D, const double *B, const q
     h->integer_data = integer_all(F, n) && integer_all(D, n) && integer_all(h->hB.data(), n) &&
                       std::fabs(offset) < 9.0e15 && offset == std::floor(offset);
     derive_constants(h);
-    pick_zlap(h->m, prm.zlap_lanes, prm.zlap_cols, h->zl, h->zc);
-    h->zl_auto = prm.zlap_lanes == 0;
+    h->half = prm.scheme == QAP_SCHEME_HALF;
+    // HALF solves the upper tiles with the scalar solver (one LAP per wave)
+    pick_zlap(h->m, h->half ? -1 : prm.zlap_lanes, prm.zlap_cols, h->zl, h->zc);
+    h->zl_auto = !h->half && prm.zlap_lanes == 0;
 
     auto cleanup = [&](int code) {
         const std::string e = h->err;
@@ -496,7 +508,7 @@ int create_ctx(int n, const double *F, const double *D, const double *B, const q
 
 extern "C" {
 
-const char *qap_version(void) { return "qap-rlt2-mi355x 0.1 (gfx950, F1 FULL)"; }
+const char *qap_version(void) { return "qap-rlt2-mi355x 0.1 (gfx950, F1 FULL and HALF)"; }
 
 int qap_zlap_mapping(qap_handle h, int *lanes, int *cols, double *tuned_us)
 {
@@ -540,7 +552,9 @@ int qap_rlt2_init(const double *F, const double *D, const double *B, int n, cons
         prm = *p;
     else
         qap_default_params(&prm);
-    if (!params_ok(prm)) return fail(nullptr, QAP_EINVAL, "kappa/phi outside [0,1] or 5*phi_z != 1");
+    if (!params_ok(prm))
+        return fail(nullptr, QAP_EINVAL,
+                    "kappa/phi outside [0,1], phi_z not 1/5 (FULL) or 1/2 (HALF), or bad scheme/mapping");
     return create_ctx(n, F, D, B, prm, 0.0, nullptr, true, out);
 }
 
@@ -664,7 +678,8 @@ int qap_dual_ascent(qap_handle h, int iters, double *lb_out, double *alpha_out, 
         st->ub = after.ub;
         st->gap = (after.ub < HUGE_VAL && after.ub != 0.0) ? (after.ub - after.lb) / std::fabs(after.ub) : HUGE_VAL;
         st->proven = after.proven;
-        st->laps = (long long)st->iterations_done * (h->T + (long long)h->n * h->n + 1);
+        const long long zlaps = h->half ? h->T / 2 : h->T;  // HALF: tiles with i < j
+        st->laps = (long long)st->iterations_done * (zlaps + (long long)h->n * h->n + 1);
         int rs = read_steps(h, after, steps_after);
         if (rs != QAP_OK) return rs;
         st->dijkstra_steps = (long long)(steps_after - steps_before);
@@ -769,6 +784,18 @@ int qap_import_state(qap_handle h, const qap_state_header *hdr, const double *x,
     cs = fnv1a(cs, y, sizeof(double) * h->T);
     cs = fnv1a(cs, z, sizeof(double) * h->Vz);
     if (cs != hdr->checksum) return fail(h, QAP_ESTATE, "state checksum mismatch");
+    if (h->half) {
+        // tiles (i,p,j',q') with j < i, i.e. j' < i, must hold zeros
+        const int n = h->n;
+        const size_t mm = (size_t)h->m * h->m;
+        for (long long t = 0; t < h->T; ++t) {
+            const long long ip = t / ((long long)(n - 1) * (n - 1));
+            const int jp = (int)((t / (n - 1)) % (n - 1));
+            if (jp >= ip / n) continue;
+            for (size_t a = 0; a < mm; ++a)
+                if (z[t * mm + a] != 0.0) return fail(h, QAP_EINVAL, "HALF state with a nonzero lower z entry");
+        }
+    }
     const bool post = hdr->t > 0;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     HIPCHK(h, hipMemcpy(post ? h->Px : h->Xc, x, sizeof(double) * nn, hipMemcpyHostToDevice));

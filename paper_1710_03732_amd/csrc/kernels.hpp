@@ -40,6 +40,7 @@ struct DevScalars {
 
 struct SweepConsts {
     double kz, okz, ky2, kx3, phi;
+    double phil;  // HALF: share of a lower member's g for each upper partner
 };
 
 // Tile index of the ordered pair ((f1,l1),(f2,l2)), f1 != f2, l1 != l2.
@@ -48,6 +49,25 @@ __device__ __forceinline__ long long tile_of(int n, int f1, int l1, int f2, int 
     const int f2p = f2 - (f2 > f1);
     const int l2p = l2 - (l2 > l1);
     return ((long long)(f1 * n + l1) * (n - 1) + f2p) * (n - 1) + l2p;
+}
+
+// Tile index of the b-th tile (i,p,j,q) with i < j, in ascending tile order
+// (the tiles the HALF scheme solves).  Facility i owns n (n-1-i) (n-1) of
+// them (any p, j' >= i, any q').  b < n^2 (n-1)^2 / 2 fits 32 bits; the loop
+// and the divisions are wave-uniform.
+__device__ __forceinline__ long long upper_tile(unsigned b, int n)
+{
+    const unsigned n1 = (unsigned)n - 1u;
+    unsigned i = 0u, per = (unsigned)n * n1 * n1;
+    while (b >= per) {
+        b -= per;
+        ++i;
+        per = (unsigned)n * (n1 - i) * n1;
+    }
+    const unsigned row = (n1 - i) * n1;  // tiles per (i, p)
+    const unsigned p = b / row, r2 = b % row;
+    const unsigned jp = i + r2 / n1, qp = r2 % n1;
+    return (((long long)i * n + p) * n1 + jp) * n1 + qp;
 }
 
 // Copies count doubles from global src to LDS dst with the nthr threads
@@ -134,7 +154,15 @@ __device__ __forceinline__ int cube_idx(int pl, int ql, int rl) { return pl * SB
 // With TRACK the sweep also accumulates each entry's Lagrange multiplier
 // change, g_e - phi * sum_{f != e} g_f (its own shares minus what it
 // receives from its partners, Eq. ch4:proof:2), into Vt (same layout as Z).
-template <bool TRACK>
+//
+// HALF (Section 5): only the upper members, whose first two facilities
+// ascend (canonical positions 0, 1, 3), hold z entries; the lower ones
+// (2, 4, 5) sit in unsolved tiles and stay 0, so they are neither read nor
+// written.  A lower member's g is its y and x shares alone (its z value is
+// 0), and
+//   new_e = okz*pi_z(e) + (phi*(g of the two upper partners, canonical order)
+//                          + phil*((g_2 + g_4) + g_5))   for e in {0, 1, 3}.
+template <bool TRACK, bool HALF>
 __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const double *__restrict__ Py,
                                                const double *__restrict__ Px,
                                                const int *__restrict__ triples, int ntriples, int n,
@@ -199,6 +227,7 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
     const int a2 = (int)(threadIdx.x >> 3) & (SB - 1), a3 = (int)threadIdx.x & (SB - 1);
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
+        if (HALF && (e == 2 || e == 4 || e == 5)) continue;
 #pragma unroll
         for (int w = 0; w < PER; ++w) {
             const int a1 = wid + (256 / (SB * SB)) * w;
@@ -221,10 +250,12 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
         }
     }
 #pragma unroll
-    for (int e = 0; e < 6; ++e)
+    for (int e = 0; e < 6; ++e) {
+        if (HALF && (e == 2 || e == 4 || e == 5)) continue;
 #pragma unroll
         for (int w = 0; w < PER; ++w)
             if (ok[e][w]) gs[e * SB_CUBE + li[e][w]] = pz[e][w];
+    }
     __syncthreads();
     // orbit phase: g of the six members, then phi * (left fold of the
     // partners' g), canonical order
@@ -241,7 +272,17 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
             for (int e = 0; e < 6; ++e) {
                 const double y = pys[(e * SB + lc[X1[e]]) * SB + lc[X2[e]]];
                 const double x = pxs[X1[e] * SB + lc[X1[e]]];
-                g[e] = (K.kz * gs[e * SB_CUBE + c] + K.ky2 * y) + K.kx3 * x;
+                if (HALF && (e == 2 || e == 4 || e == 5))
+                    g[e] = (1.0 * 0.0 + K.ky2 * y) + K.kx3 * x;
+                else
+                    g[e] = (K.kz * gs[e * SB_CUBE + c] + K.ky2 * y) + K.kx3 * x;
+            }
+            if (HALF) {
+                const double low = K.phil * ((g[2] + g[4]) + g[5]);
+                gs[0 * SB_CUBE + c] = K.phi * (g[1] + g[3]) + low;
+                gs[1 * SB_CUBE + c] = K.phi * (g[0] + g[3]) + low;
+                gs[3 * SB_CUBE + c] = K.phi * (g[0] + g[1]) + low;
+                continue;
             }
             gs[0 * SB_CUBE + c] = K.phi * ((((g[1] + g[2]) + g[3]) + g[4]) + g[5]);
             gs[1 * SB_CUBE + c] = K.phi * ((((g[0] + g[2]) + g[3]) + g[4]) + g[5]);
@@ -254,7 +295,8 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
     __syncthreads();
     // store phase: new_e = okz*pi_z(e) + phi*sum, back along the same runs
 #pragma unroll
-    for (int e = 0; e < 6; ++e)
+    for (int e = 0; e < 6; ++e) {
+        if (HALF && (e == 2 || e == 4 || e == 5)) continue;
 #pragma unroll
         for (int w = 0; w < PER; ++w)
             if (ok[e][w]) {
@@ -269,6 +311,7 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
                     Vt[za[e][w]] = Vt[za[e][w]] + (g - share);
                 }
             }
+    }
 }
 
 // R_y <- (1-ky) pi_y, R_x <- (1-kx) pi_x (after the sweep has read them).
@@ -345,7 +388,7 @@ __global__ __launch_bounds__(256) void k_zlap(double *__restrict__ Z, double *__
 template <int H>
 __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *__restrict__ Yc, int m,
                                                long long T, DevScalars *__restrict__ S,
-                                               unsigned long long *__restrict__ bins)
+                                               unsigned long long *__restrict__ bins, int half)
 {
     if (S->stopped) return;
     extern __shared__ double lds[];
@@ -353,7 +396,8 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
     const int lane = threadIdx.x;
     const int h = (H == 1) ? 0 : (lane >> 5);
     const int l = lane & (W - 1);
-    const long long t0 = (long long)blockIdx.x * H;
+    // HALF (H = 1): block b solves the b-th tile with i < j
+    const long long t0 = (H == 1 && half) ? upper_tile(blockIdx.x, m + 2) : (long long)blockIdx.x * H;
     const int mm = m * m;
     const long long left = T - t0;
     const int nt = (int)(left < H ? left : H);

@@ -279,6 +279,7 @@ extern "C" {
 int qap_track(qap_handle h, int on)
 {
     if (!h) return QAP_EINVAL;
+    if (h->half) return fail(h, QAP_EUNSUPPORTED, "multiplier tracking follows the FULL shares");
     HIPCHK(h, hipStreamSynchronize(h->stream));
     if (!on) {
         dev_free(h, h->Vt);
@@ -328,6 +329,7 @@ int qap_get_multipliers(qap_handle h, double *v, double *u)
 int qap_set_multipliers(qap_handle h, const double *v, const double *u)
 {
     if (!h) return QAP_EINVAL;
+    if (h->half) return fail(h, QAP_EUNSUPPORTED, "z multipliers are FULL-scheme only");
     const int n = h->n;
     // zero sums: every orbit of v, every y pair of u
     if (v) {
@@ -447,6 +449,7 @@ int qap_orbit_targets(qap_handle h, const int64_t *ids, int64_t count, double sc
 int qap_warm_start_outputs(qap_handle h, const float *y, double scale)
 {
     if (!h || !y || !(scale > 0.0) || !std::isfinite(scale)) return QAP_EINVAL;
+    if (h->half) return fail(h, QAP_EUNSUPPORTED, "warm starts are FULL-scheme only");
     const int nb = (h->n + SB - 1) / SB;
     const unsigned groups8 = (unsigned)((h->ntriples + 7) / 8);
     const unsigned blocks = groups8 * 8u * (unsigned)(nb * nb * nb);
@@ -613,6 +616,7 @@ int qap_orbit_outputs(qap_handle h, qap_mlp_handle p, float *y)
 int qap_warm_start(qap_handle h, qap_mlp_handle p, double gain, qap_warm_stats *st)
 {
     if (!h || !p) return QAP_EINVAL;
+    if (h->half) return fail(h, QAP_EUNSUPPORTED, "warm starts are FULL-scheme only");
     if (!(gain > 0.0) || !std::isfinite(gain)) return fail(h, QAP_EINVAL, "gain must be positive and finite");
     auto t0 = std::chrono::steady_clock::now();
     const long long count = orbit_count_of(h->n);

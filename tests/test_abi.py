@@ -70,6 +70,24 @@ def test_init_rejects_bad_params():
     assert e.value.code == -1
 
 
+def test_half_parameters_are_validated_before_any_device_call():
+    """HALF needs phi_z = 1/2 (two upper partners) and the scalar Z-LAP
+    mapping; an unknown scheme or field is refused."""
+    F = np.ones((5, 5))
+    p = B.half_params()
+    assert (p.kappa_z, p.kappa_y, p.kappa_x, p.phi_z, p.phi_y) == (2.0 / 3.0, 1.0, 1.0, 0.5, 0.5)
+    assert p.scheme == B.SCHEME_HALF and p.zlap_lanes == -1
+    for bad in [dict(phi_z=0.2), dict(zlap_lanes=16, zlap_cols=2), dict(scheme=2)]:
+        with pytest.raises(B.QapError) as e:
+            B.DualAscent(F, F, params=B.half_params(**bad))
+        assert e.value.code == -1, bad
+    with pytest.raises(B.QapError) as e:
+        B.DualAscent(F, F, phi_z=0.5)  # FULL with the HALF share
+    assert e.value.code == -1
+    with pytest.raises(TypeError):
+        B.default_params(shceme=1)
+
+
 def test_lap_batch_rejects_bad_sizes():
     lib = B.lib()
     assert lib.qap_lap_batch(None, 1, 0, None, None, None, None, 0, 0, None) == -1

@@ -406,3 +406,28 @@ def test_half_refuses_nonzero_lower_costs_and_tracking():
     da = O.DualAscent(F, D, None, O.HALF)
     with pytest.raises(Exception):
         da.track()
+
+
+@pytest.mark.parametrize("inst", [I.grid_instance(7, 2, 4, 0.4, 1, 9, 1), I.random_instance(6, 77)],
+                         ids=lambda x: x.name)
+def test_half_sampled_tiles_match_full_half_oracle(inst):
+    """The single-tile path under HALF (used at n = 30) reproduces the dense
+    HALF oracle's iteration-1 upper tiles exactly and refuses lower ones."""
+    F, D, B = inst.arrays()
+    n = inst.n
+    full = O.DualAscent(F, D, B, O.HALF)
+    full.run(1)
+    X0, Y0, _ = full.export()
+    red = O.Iter0XY(F, D, B, O.HALF)
+    Xr, Yr = red.xy()
+    assert red.LB == full.LB and np.array_equal(Xr, X0) and np.array_equal(Yr, Y0)
+    full.sweep()
+    full.zphase()
+    _, _, Z1 = full.export()
+    for (i, j, p, q) in [(0, 1, 0, 1), (0, 2, 3, 1), (n - 2, n - 1, 0, n - 1), (1, 3, 4, 2)]:
+        M, pi, th = red.tile1(i, j, p, q)
+        ks = [k for k in range(n) if k not in (i, j)]
+        rs = [r for r in range(n) if r not in (p, q)]
+        assert np.array_equal(pi, np.array([[Z1[i, j, k, p, q, r] for r in rs] for k in ks]))
+    with pytest.raises(ValueError):
+        red.tile1(1, 0, 0, 1)
