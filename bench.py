@@ -16,6 +16,8 @@ Prints one JSON line.  `roofline` is for the kernel with the largest device
 time; its `achieved` is algorithmic bytes per launch / average launch time.
 `frac` is against the 8 TB/s peak and `frac_of_copy` against a plain 2 GiB
 device copy measured in the same run (after the timed region).
+`half` runs the HALF scheme (Section 5: only the Z-LAPs of tiles with i < j)
+on the same workload and times it to the FULL bound of 100 iterations.
 `time_to_bound` compares 100 cold iterations with the learned warm start
 (trained weights from train_warm.py) reaching the same bound; its
 `mlp_roofline` gives the inference kernel's TFLOP/s against the bf16 MFMA
@@ -55,6 +57,19 @@ def algorithmic_bytes(n: int) -> dict:
         "ylap": 8 * (3 * T + 2 * nn),
         "xlap": 8 * (5 * nn),
     }
+
+
+def algorithmic_bytes_half(n: int) -> dict:
+    """The same under the HALF scheme: only the upper half of the z array
+    (tiles with i < j) is read and written; pi_y of every tile still feeds
+    the sweep."""
+    m = n - 2
+    T = n * n * (n - 1) * (n - 1)
+    V = T * m * m
+    nn = n * n
+    full = algorithmic_bytes(n)
+    return {"zlap": 8 * (V + T), "sweep": 8 * (V + T + nn) + 8 * (2 * T + 2 * nn),
+            "ylap": full["ylap"], "xlap": full["xlap"]}
 
 
 def kernel_source_sha() -> str:
@@ -125,6 +140,67 @@ def warm_vs_cold(inst, cold_iters: int):
                            "ms": ms}
     mlp.close()
     return res
+
+
+def half_leg(inst, steps: int, warmup: int, full_trace, cold_iters: int, stream):
+    """The HALF scheme (Section 5) on the same workload: iterations/s with
+    the same warmup and step count, its per-phase HBM rates, the bound after
+    as many iterations as the FULL line, and the wall time HALF needs to
+    reach the FULL bound after `cold_iters` iterations (if it does within
+    3 x cold_iters) against FULL's time for those iterations."""
+    import torch
+
+    from paper_1710_03732_amd import binding
+
+    F, D, B = inst.arrays()
+    n = inst.n
+    T = n * n * (n - 1) * (n - 1)
+    h = binding.DualAscent(F, D, B, params=binding.half_params(timing=1))
+    h.set_stream(stream.cuda_stream)
+    if warmup > 0:
+        h.run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = h.run(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    done = r["iterations_done"]
+    h.close()
+    if done <= 0:
+        return {"skipped": "bound proved optimal during warmup"}
+    phase_ms = {"sweep": r["ms_sweep"] / done, "zlap": r["ms_zlap"] / done,
+                "ylap": r["ms_ylap"] / done, "xlap": r["ms_xlap"] / done}
+    ab = algorithmic_bytes_half(n)
+    out = {"iterations_per_s": done / el, "ms_per_step": 1e3 * el / done,
+           "laps_per_s": done / el * (T // 2 + n * n + 1), "z_laps_per_iter": T // 2,
+           "phase_ms_per_iter": phase_ms,
+           "phase_gbs": {k: ab[k] / (phase_ms[k] * 1e-3) / 1e9 for k in ("zlap", "sweep")},
+           "lb_after": r["lb"], "lb_full_after_same_iterations": full_trace[-1] if len(full_trace) else None}
+    # time to FULL's bound after cold_iters iterations (plain handles, graph replay)
+    if len(full_trace) >= cold_iters:
+        target = float(full_trace[cold_iters - 1])
+        probe = binding.DualAscent(F, D, B, params=binding.half_params())
+        probe.run(3 * cold_iters)
+        tr = probe.trace()
+        probe.close()
+        need = next((k + 1 for k, v in enumerate(tr) if v >= target), None)
+        res = {"target_lb": target, "full_iterations": cold_iters, "half_iterations": need}
+        timed = {}
+        for label, prm, iters in (("full", binding.default_params(), cold_iters),
+                                  ("half", binding.half_params(), need)):
+            if not iters:
+                continue
+            hd = binding.DualAscent(F, D, B, params=prm)  # own stream: graph replay
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hd.run(iters)  # returns after synchronising the handle's stream
+            timed[label] = time.perf_counter() - t0
+            hd.close()
+        res["full_seconds"] = timed["full"]
+        res["half_seconds"] = timed.get("half")
+        res["speedup"] = timed["full"] / timed["half"] if "half" in timed else None
+        out["time_to_full_bound"] = res
+    return out
 
 
 def bnb_leg():
@@ -210,6 +286,7 @@ def main(argv=None):
     ap.add_argument("--zlap-cols", type=int, default=0)
     ap.add_argument("--no-time-to-bound", action="store_true")
     ap.add_argument("--no-bnb", action="store_true", help="skip the branch-and-bound leg (n = 14 and 18)")
+    ap.add_argument("--no-half", action="store_true", help="skip the HALF-scheme leg")
     ap.add_argument("--cold-iters", type=int, default=100,
                     help="cold iterations whose bound the learned warm start must reach")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -264,6 +341,7 @@ def main(argv=None):
     achieved = ab[dom] / dom_s / 1e9
     traffic = load_traffic(dom, inst.name)
     iter_bytes = sum(ab.values())
+    full_trace = da.trace()
     copy_gbs = measure_copy_gbs()  # after the timed region
     steps_per_zlap = r["dijkstra_steps"] / max(1, done * laps_per_iter)
 
@@ -306,11 +384,14 @@ def main(argv=None):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": ab[dom],
                      "avg_launch_ms": phase_ms[dom], "frac_of_copy": achieved / copy_gbs},
+        "half": None,
         "bnb": None,
         "time_to_bound": None,
         "cpu_baseline": None,
     }
     da.close()
+    if not args.no_half:
+        out["half"] = half_leg(inst, args.steps, args.warmup, full_trace, args.cold_iters, stream)
     if not args.no_bnb and inst.name == "dense_n30":
         out["bnb"] = bnb_leg()
     if not args.no_time_to_bound:

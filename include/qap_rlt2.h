@@ -242,7 +242,9 @@ int qap_export_z_tiles(qap_handle h, const int64_t *tiles, int count, double *ou
 int qap_import_state(qap_handle h, const qap_state_header *hdr, const double *x,
                      const double *y, const double *z);
 
-/* Use the given HIP stream (hipStream_t passed as void*) for all work. */
+/* Use the given HIP stream (hipStream_t passed as void*) for all work.  On
+ * the null stream (0) iterations are launched kernel by kernel instead of as
+ * a replayed HIP graph, since HIP cannot capture that stream. */
 int qap_set_stream(qap_handle h, void *hip_stream);
 
 /* Solve the QAP held by h to optimality by branch-and-bound (Section 4):

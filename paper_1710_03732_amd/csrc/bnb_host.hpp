@@ -252,22 +252,26 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
         return hipGetLastError();
     };
     if (bp->iters > 0) {
-        hipGraph_t g = nullptr;
+        // one captured graph per batch, replayed; the legacy null stream
+        // cannot be captured, there every replay launches the kernels
         hipGraphExec_t ge = nullptr;
-        HIPCHK(h0, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        hipError_t le = launch_all();
-        hipError_t ce = hipStreamEndCapture(stream, &g);
-        if (le != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch launch: ") + hipGetErrorString(le));
-        if (ce != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch capture: ") + hipGetErrorString(ce));
-        hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ie != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch graph: ") + hipGetErrorString(ie));
+        if (stream != nullptr) {
+            hipGraph_t g = nullptr;
+            HIPCHK(h0, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            hipError_t le = launch_all();
+            hipError_t ce = hipStreamEndCapture(stream, &g);
+            if (le != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch launch: ") + hipGetErrorString(le));
+            if (ce != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch capture: ") + hipGetErrorString(ce));
+            hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ie != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch graph: ") + hipGetErrorString(ie));
+        }
         // replays; every kPoll of them the host reads how many nodes have
         // stopped and ends the batch once all have (further replays would
         // only launch jobs that find their node stopped)
         constexpr int kPoll = 4;
         for (int it = 0; it < bp->iters; ++it) {
-            hipError_t e2 = hipGraphLaunch(ge, stream);
+            hipError_t e2 = ge ? hipGraphLaunch(ge, stream) : launch_all();
             if (e2 == hipSuccess && (it + 1) % kPoll == 0 && it + 1 < bp->iters) {
                 int ns = 0;
                 e2 = hipMemcpyAsync(&ns, dnstop, sizeof(int), hipMemcpyDeviceToHost, stream);
@@ -275,11 +279,11 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
                 if (e2 == hipSuccess && stopped0 + ns >= count) break;
             }
             if (e2 != hipSuccess) {
-                (void)hipGraphExecDestroy(ge);
+                if (ge) (void)hipGraphExecDestroy(ge);
                 return fail(h0, QAP_EDEVICE, std::string("batch replay: ") + hipGetErrorString(e2));
             }
         }
-        (void)hipGraphExecDestroy(ge);
+        if (ge) (void)hipGraphExecDestroy(ge);
     }
     HIPCHK(h0, hipStreamSynchronize(stream));
     if (st) {

@@ -633,7 +633,9 @@ int qap_dual_ascent(qap_handle h, int iters, double *lb_out, double *alpha_out, 
         if (h->prm.timing) {
             hipError_t e = launch_iteration_timed(h, t, &evs[(size_t)5 * it]);
             if (e != hipSuccess) return fail(h, QAP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
-        } else if (t >= 1) {
+        } else if (t >= 1 && h->stream != nullptr) {
+            // graph replay (the legacy null stream cannot be captured: there
+            // the iterations are launched one kernel at a time below)
             if (!h->graph) {
                 hipGraph_t g = nullptr;
                 HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));

@@ -376,3 +376,28 @@ def test_autotuned_mapping_is_bitwise_the_requested_one(tmp_path, monkeypatch):
     entries = json.loads(cache.read_text())
     keys = [k for k in entries if f"/zlap/m{m}/" in k]
     assert len(keys) == 1 and entries[keys[0]][:2] == [lanes, cols]
+
+
+def test_null_stream_runs_without_graph_capture():
+    """On the legacy null stream (which HIP cannot capture) iterations and
+    batched iterations are launched kernel by kernel, with the same results
+    as graph replay on the handle's own stream."""
+    inst = I.random_instance(9, 21)
+    F, D, Bm = inst.arrays()
+    a = B.DualAscent(F, D, Bm)
+    a.run(12)
+    b = B.DualAscent(F, D, Bm)
+    b.set_stream(0)
+    b.run(12)
+    assert np.array_equal(a.trace(), b.trace())
+    _, xa, ya, za = a.export_state()
+    _, xb, yb, zb = b.export_state()
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(za, zb)
+    c = B.DualAscent(F, D, Bm)
+    c.run(1)
+    c.set_stream(0)
+    d = B.DualAscent(F, D, Bm)
+    d.run(1)
+    B.batch_run([c], 6)
+    B.batch_run([d], 6)
+    assert np.array_equal(c.trace(), d.trace())
