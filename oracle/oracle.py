@@ -70,6 +70,8 @@ def lib():
         L.orc_iter1_tile.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
         L.orc_da_track.argtypes = [C.c_void_p]
         L.orc_da_set_half.argtypes = [C.c_void_p]
+        L.orc_da_set_two_phase.argtypes = [C.c_void_p]
+        L.orc_da_pool.argtypes = [C.c_void_p]
         L.orc_da_multipliers.argtypes = [C.c_void_p, _dp, _dp]
         L.orc_da_from_multipliers.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_da_from_multipliers.restype = C.c_void_p
@@ -154,7 +156,7 @@ def rule3_order(F):
 class DualAscent:
     """The F1 RLT2 dual ascent on dense reduced-cost arrays."""
 
-    def __init__(self, F, D, B=None, params=FULL, _handle=None):
+    def __init__(self, F, D, B=None, params=FULL, _handle=None, two_phase=False):
         F, D = _f64(F), _f64(D)
         self.n = F.shape[0]
         B = np.zeros_like(F) if B is None else _f64(B)
@@ -168,6 +170,9 @@ class DualAscent:
         self.half = len(P) > 5 and P[5] == 1.0
         if self.half and lib().orc_da_set_half(self.h) != 0:
             raise ValueError("oracle: HALF needs zero lower z costs and no tracking")
+        self.two_phase = bool(two_phase)
+        if self.two_phase and lib().orc_da_set_two_phase(self.h) != 0:
+            raise ValueError("oracle: F2 is not combined with HALF or tracking")
 
     @classmethod
     def from_arrays(cls, F, D, B, params, LB, X, Y, Z):
@@ -190,6 +195,10 @@ class DualAscent:
 
     def zphase(self):
         lib().orc_da_zphase(self.h)
+
+    def pool(self):
+        """F2's pooling of the orbit slacks (S_N onto S_B)."""
+        lib().orc_da_pool(self.h)
 
     def yequal(self):
         lib().orc_da_yequal(self.h)

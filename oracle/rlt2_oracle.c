@@ -310,6 +310,7 @@ typedef struct orc_da {
     int trace_len, trace_cap;
     double *Vt, *Ut;        /* tracked S-form multipliers v (n^6), u (n^4), or NULL */
     int half;               /* HALF scheme (orc_da_set_half) */
+    int two_phase;          /* F2: pool and re-solve the Z-LAPs (orc_da_set_two_phase) */
 } orc_da;
 
 static void orc_da_derive(orc_da *s)
@@ -648,10 +649,71 @@ static void orc_trace_push(orc_da *s, double lb)
     s->trace[s->trace_len++] = lb;
 }
 
+/* Two-phase variant F2 (Section 3.4): after the Z-LAPs, in every orbit
+ * {(i,p),(j,q),(k,r)} with i < j < k and distinct p, q, r the six members
+ * are split by their dual slack into S_B (slack 0) and S_N (slack > 0).
+ * The S_N members' costs drop by their slack (to 0) and the slack total
+ * (left fold in the canonical member order) is shared equally among the S_B
+ * members; orbits with S_B or S_N empty are unchanged.  In the F-form the
+ * arrays hold the slacks themselves, so "slack 0" reads as <= 0 (a slack
+ * that rounding left negative belongs to S_B).  The transfer is zero-sum
+ * per orbit (a multiplier move on the symmetry constraints), so the bound
+ * stays valid. */
+void orc_da_pool(orc_da *s)
+{
+    int n = s->n;
+    double *Z = s->Z;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j)
+            for (int k = j + 1; k < n; ++k)
+                for (int p = 0; p < n; ++p)
+                    for (int q = 0; q < n; ++q) {
+                        if (q == p) continue;
+                        for (int r = 0; r < n; ++r) {
+                            if (r == p || r == q) continue;
+                            int fac[6][3], loc[6][3];
+                            size_t zi[6];
+                            double pi[6];
+                            orbit_members(i, j, k, p, q, r, fac, loc);
+                            double slack = 0.0;
+                            int first = 1, nbasic = 0;
+                            for (int e = 0; e < 6; ++e) {
+                                zi[e] = IX6(n, fac[e][0], fac[e][1], fac[e][2], loc[e][0], loc[e][1], loc[e][2]);
+                                pi[e] = Z[zi[e]];
+                                if (pi[e] > 0.0) {
+                                    if (first) { slack = pi[e]; first = 0; }
+                                    else slack = slack + pi[e];
+                                } else {
+                                    ++nbasic;
+                                }
+                            }
+                            if (nbasic == 0 || nbasic == 6) continue;
+                            double share = slack / (double)nbasic;
+                            for (int e = 0; e < 6; ++e) Z[zi[e]] = pi[e] > 0.0 ? 0.0 : pi[e] + share;
+                        }
+                    }
+}
+
+/* Switch a state to the two-phase variant F2.  Not with HALF or tracking
+ * (the pooling moves multipliers the tracker does not follow); 0 or -1. */
+int orc_da_set_two_phase(orc_da *s)
+{
+    if (!s || s->half || s->Vt) return -1;
+    s->two_phase = 1;
+    return 0;
+}
+
 void orc_da_iterate(orc_da *s)
 {
     if (s->t >= 1) orc_da_sweep(s);
     orc_da_zphase(s);
+    if (s->two_phase && s->t >= 1) {
+        /* F2: pool within the orbits, then re-solve the Z-LAPs on the pooled
+         * slacks (their values add to Theta, as in the first solve) */
+        orc_da_pool(s);
+        orc_da_zphase(s);
+    }
     if (s->t >= 1) orc_da_yequal(s);
     orc_da_yphase(s);
     orc_da_xphase(s);
@@ -719,7 +781,7 @@ void orc_da_export(const orc_da *s, double *X, double *Y, double *Z)
  * Both are zero-sum over an orbit / a pair.  Tracking starts at zero. */
 int orc_da_track(orc_da *s)
 {
-    if (s->half) return -1;  /* tracking follows the FULL shares */
+    if (s->half || s->two_phase) return -1;  /* tracking follows the F1 FULL transfers */
     size_t n2 = (size_t)s->n * s->n, n4 = n2 * n2;
     if (!s->Vt) s->Vt = calloc(n4 * n2, sizeof(double));
     if (!s->Ut) s->Ut = calloc(n4, sizeof(double));

@@ -431,3 +431,134 @@ def test_half_sampled_tiles_match_full_half_oracle(inst):
         assert np.array_equal(pi, np.array([[Z1[i, j, k, p, q, r] for r in rs] for k in ks]))
     with pytest.raises(ValueError):
         red.tile1(1, 0, 0, 1)
+
+
+# ---- two-phase variant F2 (Section 3.4): pool the orbit slacks, re-solve ----
+
+def _pool_state(n, orbits):
+    """A fresh state whose z slacks are the given orbits' six values (in the
+    canonical member order) and zero elsewhere."""
+    rng = np.random.default_rng(n)
+    F = rng.integers(0, 9, size=(n, n)).astype(float)
+    D = rng.integers(0, 9, size=(n, n)).astype(float)
+    Z = np.zeros((n,) * 6)
+    for (i, j, k, p, q, r), vals in orbits:
+        for mem, v in zip(_orbit_members(i, j, k, p, q, r), vals):
+            Z[mem] = v
+    da = O.DualAscent.from_arrays(F, D, np.zeros((n, n)), O.FULL, 0.0, np.zeros((n, n)),
+                                  np.zeros((n,) * 4), Z)
+    return da, Z
+
+
+def test_f2_pool_worked_example():
+    """Three members with slack 3, 1.5 and 6 give their 10.5 to the three
+    with slack 0 (3.5 each) and drop to 0; an orbit with no zero slack, one
+    with only zeros and the members outside every pooled orbit are
+    untouched; a slack rounding left negative counts as zero."""
+    n = 5
+    a = (0, 1, 2, 0, 1, 2)
+    b = (0, 1, 3, 4, 2, 0)
+    c = (1, 2, 4, 3, 0, 1)
+    d = (0, 3, 4, 1, 2, 3)
+    orbits = [(a, [3.0, 0.0, 0.0, 1.5, 0.0, 6.0]),
+              (b, [1.0, 2.0, 3.0, 4.0, 5.0, 6.0]),
+              (c, [0.0] * 6),
+              (d, [2.0, -1e-15, 0.0, 0.0, 0.0, 0.0])]
+    da, Z0 = _pool_state(n, orbits)
+    da.pool()
+    Z = da.export()[2]
+    got = lambda o: [Z[mem] for mem in _orbit_members(*o)]
+    assert got(a) == [0.0, 3.5, 3.5, 0.0, 3.5, 0.0]
+    assert got(b) == [1.0, 2.0, 3.0, 4.0, 5.0, 6.0]
+    assert got(c) == [0.0] * 6
+    assert got(d) == [0.0, -1e-15 + 0.4, 0.4, 0.4, 0.4, 0.4]
+    touched = np.zeros_like(Z, dtype=bool)
+    for o in (a, d):
+        for mem in _orbit_members(*o):
+            touched[mem] = True
+    assert np.array_equal(Z[~touched], Z0[~touched])
+
+
+@pytest.mark.parametrize("inst", [I.random_instance(6, 14), I.grid_instance(7, 2, 4, 0.4, 1, 9, 3)],
+                         ids=lambda x: x.name)
+def test_f2_pool_conserves_orbits_on_a_real_state(inst):
+    """After a Z-LAP phase at t >= 1: every orbit's slack total is kept (to
+    rounding), S_N members end at 0, S_B members all gain the same amount."""
+    F, D, B = inst.arrays()
+    n = inst.n
+    da = O.DualAscent(F, D, B)
+    da.run(3)
+    da.sweep()
+    da.zphase()
+    Z0 = da.export()[2].copy()
+    da.pool()
+    Z1 = da.export()[2]
+    pooled = 0
+    for (i, j, k) in itertools.combinations(range(n), 3):
+        for (p, q, r) in itertools.permutations(range(n), 3):
+            mem = _orbit_members(i, j, k, p, q, r)
+            v0 = np.array([Z0[x] for x in mem])
+            v1 = np.array([Z1[x] for x in mem])
+            assert abs(v1.sum() - v0.sum()) <= 1e-12 * max(1.0, np.abs(v0).sum())
+            nb = int((v0 <= 0.0).sum())
+            if nb in (0, 6):
+                assert np.array_equal(v0, v1)
+                continue
+            pooled += 1
+            assert np.all(v1[v0 > 0.0] == 0.0)
+            gain = v1[v0 <= 0.0] - v0[v0 <= 0.0]
+            assert np.allclose(gain, v0[v0 > 0.0].sum() / nb, rtol=1e-12, atol=0.0)
+    assert pooled > 0
+
+
+@pytest.mark.parametrize("inst", [I.random_instance(5, 3), I.grid_instance(6, 2, 3, 0.4, 1, 9, 4)],
+                         ids=lambda x: x.name)
+def test_f2_identity_every_phase(inst):
+    """The pooling and the second Z-LAP solve keep the reformulation
+    identity for every permutation, with reduced costs >= 0."""
+    F, D, B = inst.arrays()
+    n = F.shape[0]
+    perms = [np.array(p, dtype=np.int32) for p in itertools.permutations(range(n))]
+    da = O.DualAscent(F, D, B, two_phase=True)
+    da.run(1)
+    for _ in range(3):
+        da.sweep()
+        da.zphase()
+        da.pool()
+        _check_identity(da, F, D, B, perms)
+        da.zphase()
+        _check_identity(da, F, D, B, perms)
+        da.yequal()
+        da.yphase()
+        da.xphase()
+        _check_identity(da, F, D, B, perms)
+
+
+@pytest.mark.parametrize("inst", [I.grid_n8(), I.random_instance(8, 3), I.dense_instance(9, 5)],
+                         ids=lambda x: x.name)
+def test_f2_bound_valid_monotone_and_at_least_f1(inst):
+    """F2 bounds stay below the brute-force optimum and never fall; after 30
+    iterations they are at least F1's on these instances (the paper's claim
+    for two-phase variants), and on the 2x4 grid F2 proves the optimum."""
+    F, D, B = inst.arrays()
+    opt = brute_opt(F, D, B)
+    f1 = O.DualAscent(F, D, B)
+    f2 = O.DualAscent(F, D, B, two_phase=True)
+    f1.run(30)
+    f2.run(30)
+    tr = f2.trace()
+    assert np.all(np.diff(tr) >= 0.0)
+    assert tr[-1] <= opt + 1e-9 * max(1.0, opt)
+    assert f2.LB >= f1.LB - 1e-9 * max(1.0, opt)  # both may sit at the optimum, to rounding
+    if inst.name.startswith("grid2x4"):
+        assert f2.proven() and f2.UB == opt
+
+
+def test_f2_refuses_half_and_tracking():
+    inst = I.random_instance(5, 2)
+    F, D, B = inst.arrays()
+    with pytest.raises(ValueError):
+        O.DualAscent(F, D, B, O.HALF, two_phase=True)
+    da = O.DualAscent(F, D, B, two_phase=True)
+    with pytest.raises(Exception):
+        da.track()
