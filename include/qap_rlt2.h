@@ -49,7 +49,7 @@ extern "C" {
 #define QAP_ENOMEM (-2)       /* device arena larger than free memory (checked first) */
 #define QAP_EDEVICE (-3)      /* HIP runtime error (text in qap_last_error) */
 #define QAP_ESTATE (-4)       /* call out of order, or bad checksum on import */
-#define QAP_EUNSUPPORTED (-5) /* n outside 3..64, or a call a HALF handle refuses */
+#define QAP_EUNSUPPORTED (-5) /* n outside 3..64, or a call a HALF or F2 handle refuses */
 
 typedef struct qap_ctx *qap_handle;
 
@@ -92,6 +92,15 @@ typedef struct qap_params {
                               handle's stream and report per-phase device time
                               in qap_da_stats (no graph replay) */
     int scheme;            /* QAP_SCHEME_FULL (0) or QAP_SCHEME_HALF (1) */
+    int two_phase;         /* 0: F1; 1: F2, the two-phase variant of Section 3.4:
+                              from t = 1 on, after the Z-LAPs every orbit's
+                              slacks are pooled (the members with slack > 0 drop
+                              to 0, their total is shared equally by those with
+                              slack <= 0; unchanged if either set is empty) and
+                              the Z-LAPs are solved again, their values adding to
+                              the y costs as well.  FULL scheme only; tracking,
+                              child folds, batched and B&B ascent refuse an F2
+                              handle (QAP_EUNSUPPORTED) */
     qap_alloc_fn alloc;    /* optional device allocator */
     qap_free_fn free_fn;
     void *alloc_ctx;
@@ -105,7 +114,8 @@ typedef struct qap_da_stats {
     double gap;            /* (ub - lb)/|ub| */
     int proven;            /* 1 when lb certifies ub optimal (feasibility check) */
     int pad;
-    long long laps;        /* LAPs solved by this call: iters*(T + n^2 + 1), T/2 for HALF */
+    long long laps;        /* LAPs solved by this call: iters*(T + n^2 + 1), T/2 for
+                              HALF, 2T at t >= 1 for F2 */
     long long dijkstra_steps; /* Dijkstra steps of all LAPs of this call */
     double seconds;        /* wall time of the call (device-synchronised) */
     double ms_sweep;       /* with params.timing: summed device milliseconds of */

@@ -130,7 +130,8 @@ bool params_ok(const qap_params &p)
     // each member shares among its partners: five under FULL, two upper ones under HALF
     const double partners = p.scheme == QAP_SCHEME_HALF ? 2.0 : 5.0;
     const bool mapping = p.scheme != QAP_SCHEME_HALF || p.zlap_lanes == 0 || p.zlap_lanes == -1;
-    return (p.scheme == QAP_SCHEME_FULL || p.scheme == QAP_SCHEME_HALF) && mapping && in01(p.kappa_z) &&
+    const bool variant = p.two_phase == 0 || (p.two_phase == 1 && p.scheme == QAP_SCHEME_FULL);
+    return (p.scheme == QAP_SCHEME_FULL || p.scheme == QAP_SCHEME_HALF) && mapping && variant && in01(p.kappa_z) &&
            in01(p.kappa_y) && in01(p.kappa_x) && in01(p.phi_z) && in01(p.phi_y) &&
            std::fabs(partners * p.phi_z - 1.0) < 1e-12 && std::isfinite(p.min_gap) && p.min_gap >= 0.0;
 }
@@ -236,11 +237,35 @@ hipError_t launch_sweep(qap_ctx *h)
             hipLaunchKernelGGL((k_sweep<false, false>), dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py,
                                h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, (double *)nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        const long long work = std::max<long long>(h->T, (long long)h->n * h->n);
+        const long long work = std::max<long long>(h->T, (long long)h->n * h->n);  // x/y scaling
         const unsigned sb = (unsigned)std::min<long long>((work + 255) / 256, 65535);
         hipLaunchKernelGGL(k_scale_xy, dim3(sb), dim3(256), 0, h->stream, h->Yc, h->Py, h->Xc, h->Px,
                            h->T, h->n * h->n, h->oky, h->okx, h->S);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// F2 pooling between the two Z-LAP solves (the sweep's transpose, POOL mode).
+hipError_t launch_pool(qap_ctx *h)
+{
+    SweepConsts K{h->kz, h->okz, h->ky2, h->kx3, h->phi, 1.0 / 3.0};
+    const unsigned groups8 = (unsigned)((h->ntriples + 7) / 8);
+    const int nb = (h->n + SB - 1) / SB;
+    const unsigned blocks = groups8 * 8u * (unsigned)(nb * nb * nb);
+    hipLaunchKernelGGL((k_sweep<false, false, true>), dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py, h->Px,
+                       h->triples, h->ntriples, h->n, nb, K, h->S, (double *)nullptr);
+    return hipGetLastError();
+}
+
+// Z-LAP phase: one solve (F1), or solve, pool, solve (F2 from t = 1 on).
+hipError_t launch_zphase(qap_ctx *h, int t)
+{
+    hipError_t e;
+    if ((e = launch_zlap(h)) != hipSuccess) return e;
+    if (h->prm.two_phase && t >= 1) {
+        if ((e = launch_pool(h)) != hipSuccess) return e;
+        if ((e = launch_zlap(h)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -256,7 +281,7 @@ hipError_t launch_iteration(qap_ctx *h, int t)
 {
     hipError_t e;
     if (t >= 1 && (e = launch_sweep(h)) != hipSuccess) return e;
-    if ((e = launch_zlap(h)) != hipSuccess) return e;
+    if ((e = launch_zphase(h, t)) != hipSuccess) return e;
     if ((e = launch_ylap(h, t >= 1 ? 1 : 0)) != hipSuccess) return e;
     return launch_xlap(h);
 }
@@ -268,7 +293,7 @@ hipError_t launch_iteration_timed(qap_ctx *h, int t, hipEvent_t *ev)
     if ((e = hipEventRecord(ev[0], h->stream)) != hipSuccess) return e;
     if (t >= 1 && (e = launch_sweep(h)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev[1], h->stream)) != hipSuccess) return e;
-    if ((e = launch_zlap(h)) != hipSuccess) return e;
+    if ((e = launch_zphase(h, t)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev[2], h->stream)) != hipSuccess) return e;
     if ((e = launch_ylap(h, t >= 1 ? 1 : 0)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev[3], h->stream)) != hipSuccess) return e;
@@ -508,7 +533,7 @@ int create_ctx(int n, const double *F, const double *D, const double *B, const q
 
 extern "C" {
 
-const char *qap_version(void) { return "qap-rlt2-mi355x 0.1 (gfx950, F1 FULL and HALF)"; }
+const char *qap_version(void) { return "qap-rlt2-mi355x 0.1 (gfx950, F1 and F2; FULL and HALF)"; }
 
 int qap_zlap_mapping(qap_handle h, int *lanes, int *cols, double *tuned_us)
 {
@@ -554,7 +579,7 @@ int qap_rlt2_init(const double *F, const double *D, const double *B, int n, cons
         qap_default_params(&prm);
     if (!params_ok(prm))
         return fail(nullptr, QAP_EINVAL,
-                    "kappa/phi outside [0,1], phi_z not 1/5 (FULL) or 1/2 (HALF), or bad scheme/mapping");
+                    "kappa/phi outside [0,1], phi_z not 1/5 (FULL) or 1/2 (HALF), or bad scheme/mapping/variant");
     return create_ctx(n, F, D, B, prm, 0.0, nullptr, true, out);
 }
 
@@ -682,6 +707,8 @@ int qap_dual_ascent(qap_handle h, int iters, double *lb_out, double *alpha_out, 
         st->proven = after.proven;
         const long long zlaps = h->half ? h->T / 2 : h->T;  // HALF: tiles with i < j
         st->laps = (long long)st->iterations_done * (zlaps + (long long)h->n * h->n + 1);
+        if (h->prm.two_phase)  // F2 solves the Z-LAPs twice at t >= 1
+            st->laps += (long long)std::max(0, after.t - std::max(before.t, 1)) * zlaps;
         int rs = read_steps(h, after, steps_after);
         if (rs != QAP_OK) return rs;
         st->dijkstra_steps = (long long)(steps_after - steps_before);

@@ -162,7 +162,13 @@ __device__ __forceinline__ int cube_idx(int pl, int ql, int rl) { return pl * SB
 // 0), and
 //   new_e = okz*pi_z(e) + (phi*(g of the two upper partners, canonical order)
 //                          + phil*((g_2 + g_4) + g_5))   for e in {0, 1, 3}.
-template <bool TRACK, bool HALF>
+//
+// POOL is the two-phase variant's pooling between its two Z-LAP solves
+// (Section 3.4), on the same transpose: the orbit phase splits the six
+// slacks into S_N (> 0) and S_B (<= 0); when both are non-empty the S_N
+// members become 0 and each S_B member gains (left fold of the S_N slacks,
+// canonical order) / |S_B|.  No y or x duals are involved.
+template <bool TRACK, bool HALF, bool POOL = false>
 __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const double *__restrict__ Py,
                                                const double *__restrict__ Px,
                                                const int *__restrict__ triples, int ntriples, int n,
@@ -197,7 +203,7 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
     __shared__ double pys[6 * SB * SB];
     __shared__ double pxs[3 * SB];
 #pragma unroll
-    for (int rep = 0; rep < (6 * SB * SB + 255) / 256; ++rep) {
+    for (int rep = 0; rep < (POOL ? 0 : (6 * SB * SB + 255) / 256); ++rep) {
         const int a = threadIdx.x + 256 * rep;
         if (a < 6 * SB * SB) {
             const int e = a / (SB * SB), a1 = (a / SB) % SB, a2 = a % SB;
@@ -208,7 +214,7 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
             pys[a] = (l1 < n && l2 < n && l1 != l2) ? Py[tile_of(n, f1, l1, f2, l2)] : 0.0;
         }
     }
-    if (threadIdx.x < 3 * SB) {
+    if (!POOL && threadIdx.x < 3 * SB) {
         const int x = threadIdx.x / SB, l = (x == 0 ? base[0] : (x == 1 ? base[1] : base[2])) + threadIdx.x % SB;
         const int f = x == 0 ? fi : (x == 1 ? fj : fk);
         pxs[threadIdx.x] = l < n ? Px[f * n + l] : 0.0;
@@ -266,6 +272,27 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
         const int p = base[0] + pl, q = base[1] + ql, r = base[2] + rl;
         if (p < n && q < n && r < n && p != q && p != r && q != r) {
             const int c = cube_idx(pl, ql, rl);
+            if (POOL) {
+                double v[6], slack = 0.0;
+                int nbasic = 0;
+                bool first = true;
+#pragma unroll
+                for (int e = 0; e < 6; ++e) {
+                    v[e] = gs[e * SB_CUBE + c];
+                    if (v[e] > 0.0) {
+                        slack = first ? v[e] : slack + v[e];
+                        first = false;
+                    } else {
+                        ++nbasic;
+                    }
+                }
+                if (nbasic != 0 && nbasic != 6) {
+                    const double share = slack / (double)nbasic;
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) gs[e * SB_CUBE + c] = v[e] > 0.0 ? 0.0 : v[e] + share;
+                }
+                continue;
+            }
             const int lc[3] = {pl, ql, rl};
             double g[6];
 #pragma unroll
@@ -301,7 +328,7 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
         for (int w = 0; w < PER; ++w)
             if (ok[e][w]) {
                 const double share = gs[e * SB_CUBE + li[e][w]];
-                Z[za[e][w]] = K.okz * pz[e][w] + share;
+                Z[za[e][w]] = POOL ? share : K.okz * pz[e][w] + share;
                 if (TRACK) {
                     const int u = threadIdx.x + 256 * w;
                     const int a2 = (u / SB) % SB, a1 = u / (SB * SB);

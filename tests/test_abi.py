@@ -86,6 +86,10 @@ def test_half_parameters_are_validated_before_any_device_call():
     assert e.value.code == -1
     with pytest.raises(TypeError):
         B.default_params(shceme=1)
+    for bad in [B.half_params(two_phase=1), B.default_params(two_phase=2)]:
+        with pytest.raises(B.QapError) as e:  # F2 is FULL-only; 0/1 only
+            B.DualAscent(F, F, params=bad)
+        assert e.value.code == -1
 
 
 def test_lap_batch_rejects_bad_sizes():
