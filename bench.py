@@ -16,8 +16,9 @@ Prints one JSON line.  `roofline` is for the kernel with the largest device
 time; its `achieved` is algorithmic bytes per launch / average launch time.
 `frac` is against the 8 TB/s peak and `frac_of_copy` against a plain 2 GiB
 device copy measured in the same run (after the timed region).
-`half` runs the HALF scheme (Section 5: only the Z-LAPs of tiles with i < j)
-on the same workload and times it to the FULL bound of 100 iterations.
+`variants` runs the HALF scheme (Section 5: only the Z-LAPs of tiles with
+i < j) and the two-phase F2 (Section 3.4) on the same workload and times
+each to the F1 bound of 100 iterations.
 `time_to_bound` compares 100 cold iterations with the learned warm start
 (trained weights from train_warm.py) reaching the same bound; its
 `mlp_roofline` gives the inference kernel's TFLOP/s against the bf16 MFMA
@@ -142,20 +143,21 @@ def warm_vs_cold(inst, cold_iters: int):
     return res
 
 
-def half_leg(inst, steps: int, warmup: int, full_trace, cold_iters: int, stream):
-    """The HALF scheme (Section 5) on the same workload: iterations/s with
-    the same warmup and step count, its per-phase HBM rates, the bound after
-    as many iterations as the FULL line, and the wall time HALF needs to
-    reach the FULL bound after `cold_iters` iterations (if it does within
-    3 x cold_iters) against FULL's time for those iterations."""
+def variant_leg(inst, label: str, make_params, z_laps: int, ab: dict, steps: int, warmup: int,
+                full_trace, cold_iters: int, stream):
+    """One variant of the ascent on the same workload: iterations/s with the
+    same warmup and step count, its per-phase HBM rates against its own
+    algorithmic bytes, its bound against FULL F1's after as many iterations,
+    and the wall time it needs to reach the F1 bound of `cold_iters`
+    iterations (if it does within 3 x cold_iters) against F1's time for
+    those iterations."""
     import torch
 
     from paper_1710_03732_amd import binding
 
     F, D, B = inst.arrays()
     n = inst.n
-    T = n * n * (n - 1) * (n - 1)
-    h = binding.DualAscent(F, D, B, params=binding.half_params(timing=1))
+    h = binding.DualAscent(F, D, B, params=make_params(timing=1))
     h.set_stream(stream.cuda_stream)
     if warmup > 0:
         h.run(warmup)
@@ -170,37 +172,53 @@ def half_leg(inst, steps: int, warmup: int, full_trace, cold_iters: int, stream)
         return {"skipped": "bound proved optimal during warmup"}
     phase_ms = {"sweep": r["ms_sweep"] / done, "zlap": r["ms_zlap"] / done,
                 "ylap": r["ms_ylap"] / done, "xlap": r["ms_xlap"] / done}
-    ab = algorithmic_bytes_half(n)
     out = {"iterations_per_s": done / el, "ms_per_step": 1e3 * el / done,
-           "laps_per_s": done / el * (T // 2 + n * n + 1), "z_laps_per_iter": T // 2,
+           "laps_per_s": r["laps"] / el, "z_laps_per_iter": z_laps,
            "phase_ms_per_iter": phase_ms,
            "phase_gbs": {k: ab[k] / (phase_ms[k] * 1e-3) / 1e9 for k in ("zlap", "sweep")},
-           "lb_after": r["lb"], "lb_full_after_same_iterations": full_trace[-1] if len(full_trace) else None}
-    # time to FULL's bound after cold_iters iterations (plain handles, graph replay)
+           "lb_after": r["lb"], "lb_f1_after_same_iterations": full_trace[-1] if len(full_trace) else None}
+    # time to F1's bound after cold_iters iterations (plain handles, graph replay)
     if len(full_trace) >= cold_iters:
         target = float(full_trace[cold_iters - 1])
-        probe = binding.DualAscent(F, D, B, params=binding.half_params())
+        probe = binding.DualAscent(F, D, B, params=make_params())
         probe.run(3 * cold_iters)
         tr = probe.trace()
         probe.close()
         need = next((k + 1 for k, v in enumerate(tr) if v >= target), None)
-        res = {"target_lb": target, "full_iterations": cold_iters, "half_iterations": need}
+        res = {"target_lb": target, "f1_iterations": cold_iters, f"{label}_iterations": need}
         timed = {}
-        for label, prm, iters in (("full", binding.default_params(), cold_iters),
-                                  ("half", binding.half_params(), need)):
+        for who, prm, iters in (("f1", binding.default_params(), cold_iters), (label, make_params(), need)):
             if not iters:
                 continue
             hd = binding.DualAscent(F, D, B, params=prm)  # own stream: graph replay
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             hd.run(iters)  # returns after synchronising the handle's stream
-            timed[label] = time.perf_counter() - t0
+            timed[who] = time.perf_counter() - t0
             hd.close()
-        res["full_seconds"] = timed["full"]
-        res["half_seconds"] = timed.get("half")
-        res["speedup"] = timed["full"] / timed["half"] if "half" in timed else None
-        out["time_to_full_bound"] = res
+        res["f1_seconds"] = timed["f1"]
+        res[f"{label}_seconds"] = timed.get(label)
+        res["speedup"] = timed["f1"] / timed[label] if label in timed else None
+        out["time_to_f1_bound"] = res
     return out
+
+
+def variant_legs(inst, steps: int, warmup: int, full_trace, cold_iters: int, stream):
+    """HALF (Section 5: only the Z-LAPs of tiles with i < j) and the
+    two-phase F2 (Section 3.4: solve, pool each orbit's slacks, solve)."""
+    from paper_1710_03732_amd import binding
+
+    n = inst.n
+    T = n * n * (n - 1) * (n - 1)
+    V = T * (n - 2) * (n - 2)
+    f1 = algorithmic_bytes(n)
+    f2_bytes = dict(f1, zlap=2 * f1["zlap"] + 8 * 2 * V)  # two solves and the pooling pass
+    return {
+        "half": variant_leg(inst, "half", binding.half_params, T // 2, algorithmic_bytes_half(n), steps,
+                            warmup, full_trace, cold_iters, stream),
+        "f2": variant_leg(inst, "f2", lambda **kw: binding.default_params(two_phase=1, **kw), 2 * T, f2_bytes,
+                          steps, warmup, full_trace, cold_iters, stream),
+    }
 
 
 def bnb_leg():
@@ -286,7 +304,7 @@ def main(argv=None):
     ap.add_argument("--zlap-cols", type=int, default=0)
     ap.add_argument("--no-time-to-bound", action="store_true")
     ap.add_argument("--no-bnb", action="store_true", help="skip the branch-and-bound leg (n = 14 and 18)")
-    ap.add_argument("--no-half", action="store_true", help="skip the HALF-scheme leg")
+    ap.add_argument("--no-variants", action="store_true", help="skip the HALF and F2 legs")
     ap.add_argument("--cold-iters", type=int, default=100,
                     help="cold iterations whose bound the learned warm start must reach")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -384,14 +402,14 @@ def main(argv=None):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": ab[dom],
                      "avg_launch_ms": phase_ms[dom], "frac_of_copy": achieved / copy_gbs},
-        "half": None,
+        "variants": None,
         "bnb": None,
         "time_to_bound": None,
         "cpu_baseline": None,
     }
     da.close()
-    if not args.no_half:
-        out["half"] = half_leg(inst, args.steps, args.warmup, full_trace, args.cold_iters, stream)
+    if not args.no_variants:
+        out["variants"] = variant_legs(inst, args.steps, args.warmup, full_trace, args.cold_iters, stream)
     if not args.no_bnb and inst.name == "dense_n30":
         out["bnb"] = bnb_leg()
     if not args.no_time_to_bound:

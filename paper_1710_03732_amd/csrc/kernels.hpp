@@ -328,6 +328,9 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
         for (int w = 0; w < PER; ++w)
             if (ok[e][w]) {
                 const double share = gs[e * SB_CUBE + li[e][w]];
+                // POOL leaves most orbits as they are (no zero slack among
+                // the six): store only entries whose bits changed
+                if (POOL && __double_as_longlong(share) == __double_as_longlong(pz[e][w])) continue;
                 Z[za[e][w]] = POOL ? share : K.okz * pz[e][w] + share;
                 if (TRACK) {
                     const int u = threadIdx.x + 256 * w;
