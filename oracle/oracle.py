@@ -72,6 +72,17 @@ def lib():
         L.orc_da_set_half.argtypes = [C.c_void_p]
         L.orc_da_set_two_phase.argtypes = [C.c_void_p]
         L.orc_da_pool.argtypes = [C.c_void_p]
+        L.orc_splitmix64.argtypes = [C.c_ulonglong, C.c_ulonglong]
+        L.orc_splitmix64.restype = C.c_ulonglong
+        L.orc_sa_uniform.argtypes = [C.c_ulonglong, C.c_ulonglong]
+        L.orc_sa_uniform.restype = C.c_double
+        L.orc_sa_exp.argtypes = [C.c_double]
+        L.orc_sa_exp.restype = C.c_double
+        L.orc_da_set_annealing.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int,
+                                           C.c_ulonglong]
+        L.orc_da_type4.argtypes = [C.c_void_p, C.c_int]
+        L.orc_da_sa_accepted.argtypes = [C.c_void_p]
+        L.orc_da_sa_accepted.restype = C.c_longlong
         L.orc_da_multipliers.argtypes = [C.c_void_p, _dp, _dp]
         L.orc_da_from_multipliers.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_da_from_multipliers.restype = C.c_void_p
@@ -199,6 +210,22 @@ class DualAscent:
     def pool(self):
         """F2's pooling of the orbit slacks (S_N onto S_B)."""
         lib().orc_da_pool(self.h)
+
+    def set_annealing(self, t0: float, kappa_max: float = 0.25, cool: float = 0.99, period: int = 100,
+                      seed: int = 0):
+        """Type 4 ascent with simulated annealing after every iteration t >= 1
+        (t0 <= 0 turns it off)."""
+        if lib().orc_da_set_annealing(self.h, float(t0), float(kappa_max), float(cool), int(period),
+                                      int(seed)) != 0:
+            raise ValueError("oracle: bad annealing parameters, or tracking is on")
+
+    def type4(self, it: int) -> bool:
+        """One Type 4 step for iteration index `it` on the current state."""
+        return bool(lib().orc_da_type4(self.h, int(it)))
+
+    @property
+    def sa_accepted(self) -> int:
+        return int(lib().orc_da_sa_accepted(self.h))
 
     def yequal(self):
         lib().orc_da_yequal(self.h)
@@ -387,3 +414,15 @@ class Iter0XY:
         if lib().orc_iter1_tile(self.h, i, j, p, q, _d(M), _d(pi), C.byref(th)) != 0:
             raise ValueError("bad tile")
         return M, pi, th.value
+
+
+def splitmix64(seed: int, c: int) -> int:
+    return int(lib().orc_splitmix64(int(seed), int(c)))
+
+
+def sa_uniform(seed: int, c: int) -> float:
+    return float(lib().orc_sa_uniform(int(seed), int(c)))
+
+
+def sa_exp(x: float) -> float:
+    return float(lib().orc_sa_exp(float(x)))

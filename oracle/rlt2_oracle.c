@@ -311,6 +311,12 @@ typedef struct orc_da {
     double *Vt, *Ut;        /* tracked S-form multipliers v (n^6), u (n^4), or NULL */
     int half;               /* HALF scheme (orc_da_set_half) */
     int two_phase;          /* F2: pool and re-solve the Z-LAPs (orc_da_set_two_phase) */
+    double min_gap;         /* gap stop of the running orc_da_run (no kick on a stopping iteration) */
+    int sa_on;              /* Type 4 ascent with annealing (orc_da_set_annealing) */
+    int sa_period;
+    double sa_t0, sa_kmax, sa_cool;
+    unsigned long long sa_seed;
+    long long sa_accepted;  /* Type 4 steps taken */
 } orc_da;
 
 static void orc_da_derive(orc_da *s)
@@ -640,6 +646,122 @@ void orc_da_xphase(orc_da *s)
     free(M);
 }
 
+/* ------------------------------------------------------------------------
+ * Type 4 ascent with simulated annealing (Section 2.3, last ascent rule;
+ * schedule of Section 5).
+ *
+ * Random numbers: SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) used as a
+ * counter-based generator: the c-th output (c >= 1) of the stream seeded
+ * with `seed` mixes seed + c * 0x9e3779b97f4a7c15 with the published
+ * finaliser; a uniform double in [0, 1) is its top 53 bits times 2^-53.
+ * ---------------------------------------------------------------------- */
+unsigned long long orc_splitmix64(unsigned long long seed, unsigned long long c)
+{
+    unsigned long long z = seed + c * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+double orc_sa_uniform(unsigned long long seed, unsigned long long c)
+{
+    return (double)(orc_splitmix64(seed, c) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* exp(x) for x <= 0, written out so that every platform computes the same
+ * bits: x = k ln2 + r with k = floor(x log2(e) + 1/2) and |r| <= ln2 / 2
+ * (ln2 split in a high part with trailing zero bits, so k * high is exact),
+ * then the Taylor polynomial of degree 13 in Horner form (truncation below
+ * 1e-17 relative) scaled by 2^k.  Returns 0 below -745. */
+double orc_sa_exp(double x)
+{
+    const double ln2_hi = 6.93147180369123816490e-01;  /* ln 2 to 32 bits */
+    const double ln2_lo = 1.90821492927058770002e-10;  /* ln 2 - ln2_hi */
+    const double log2e = 1.44269504088896338700e+00;
+    if (x < -745.0) return 0.0;
+    double k = floor(x * log2e + 0.5);
+    double r = (x - k * ln2_hi) - k * ln2_lo;
+    double p = 1.0 / 6227020800.0;                    /* 1/13! */
+    p = p * r + 1.0 / 479001600.0;
+    p = p * r + 1.0 / 39916800.0;
+    p = p * r + 1.0 / 3628800.0;
+    p = p * r + 1.0 / 362880.0;
+    p = p * r + 1.0 / 40320.0;
+    p = p * r + 1.0 / 5040.0;
+    p = p * r + 1.0 / 720.0;
+    p = p * r + 1.0 / 120.0;
+    p = p * r + 1.0 / 24.0;
+    p = p * r + 1.0 / 6.0;
+    p = p * r + 0.5;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    return ldexp(p, (int)k);
+}
+
+/* Enable annealing: temperature t0 (cost units; Section 5 starts at 4 % of
+ * the best known UB) multiplied by `cool` every `period` iterations, at most
+ * kappa_max of the bound offered per step, SplitMix64 seed.  t0 <= 0 turns
+ * it off.  Not with tracking (the step moves bound into the x costs, which
+ * the tracked multipliers do not follow).  0 or -1. */
+int orc_da_set_annealing(orc_da *s, double t0, double kappa_max, double cool, int period,
+                         unsigned long long seed)
+{
+    if (!s || s->Vt) return -1;
+    if (!(t0 > 0.0)) { s->sa_on = 0; return 0; }
+    if (!(kappa_max >= 0.0 && kappa_max <= 1.0) || !(cool > 0.0 && cool <= 1.0) || period < 1) return -1;
+    s->sa_on = 1;
+    s->sa_t0 = t0;
+    s->sa_kmax = kappa_max;
+    s->sa_cool = cool;
+    s->sa_period = period;
+    s->sa_seed = seed;
+    return 0;
+}
+
+/* One Type 4 step after the X-LAP of iteration it (bound nu = LB).  Draws
+ * for this iteration, counters it*(2n+2) + 1 ... + 2n+2: u_s (size), u_a
+ * (acceptance), w_1..w_2n (one per facility, then one per location).
+ * kappa^lb = kappa_max * u_s is split over the 2n fractions in proportion to
+ * the w (kappa_k = (kappa^lb * w_k) / W, W the left fold of the w); facility
+ * i offers a_i = kappa_i * nu, location p offers a_p = kappa_p * nu, and the
+ * offer A is the left fold of all 2n.  With temperature
+ * T = t0 * cool^floor(it / period) (repeated products) the step is taken
+ * when u_a <= exp(-A / T): every x slack of row i and column p grows,
+ * pi_x[i][p] = (pi_x[i][p] + a_i) + a_p, and LB drops by A.  A permutation
+ * meets each row and each column once, so cost = LB + reduced costs still
+ * holds and all slacks stay >= 0: the bound stays valid.  No step when
+ * nu <= 0.  Returns 1 when the step was taken. */
+int orc_da_type4(orc_da *s, int it)
+{
+    int n = s->n;
+    double nu = s->LB;
+    if (!(nu > 0.0)) return 0;
+    unsigned long long base = (unsigned long long)it * (unsigned long long)(2 * n + 2);
+    double us = orc_sa_uniform(s->sa_seed, base + 1);
+    double ua = orc_sa_uniform(s->sa_seed, base + 2);
+    double w[2 * ORC_MAXM + 4], a[2 * ORC_MAXM + 4];
+    double W = 0.0;
+    for (int k = 0; k < 2 * n; ++k) {
+        w[k] = orc_sa_uniform(s->sa_seed, base + 3 + (unsigned long long)k);
+        W = (k == 0) ? w[k] : W + w[k];
+    }
+    if (!(W > 0.0)) return 0;
+    double klb = s->sa_kmax * us;
+    double A = 0.0;
+    for (int k = 0; k < 2 * n; ++k) {
+        a[k] = ((klb * w[k]) / W) * nu;
+        A = (k == 0) ? a[k] : A + a[k];
+    }
+    double T = s->sa_t0;
+    for (int c = 0; c < it / s->sa_period; ++c) T = T * s->sa_cool;
+    if (!(ua <= orc_sa_exp(-(A / T)))) return 0;
+    for (int i = 0; i < n; ++i)
+        for (int p = 0; p < n; ++p) s->X[IX2(n, i, p)] = (s->X[IX2(n, i, p)] + a[i]) + a[n + p];
+    s->LB = nu - A;
+    s->sa_accepted += 1;
+    return 1;
+}
+
 static void orc_trace_push(orc_da *s, double lb)
 {
     if (s->trace_len == s->trace_cap) {
@@ -648,6 +770,8 @@ static void orc_trace_push(orc_da *s, double lb)
     }
     s->trace[s->trace_len++] = lb;
 }
+
+int orc_da_proven(const orc_da *s);
 
 /* Two-phase variant F2 (Section 3.4): after the Z-LAPs, in every orbit
  * {(i,p),(j,q),(k,r)} with i < j < k and distinct p, q, r the six members
@@ -719,6 +843,10 @@ void orc_da_iterate(orc_da *s)
     orc_da_xphase(s);
     orc_trace_push(s, s->LB);
     s->t += 1;
+    /* Type 4 after every iteration t >= 1 unless this one stops the run */
+    if (s->sa_on && s->t >= 2 && !orc_da_proven(s) &&
+        !(s->min_gap > 0.0 && s->UB < HUGE_VAL && s->UB != 0.0 && (s->UB - s->LB) / fabs(s->UB) < s->min_gap))
+        orc_da_type4(s, s->t - 1);
 }
 
 /* Optimality certificate (feasibility check, Section 2.3): the X-LAP
@@ -737,6 +865,7 @@ int orc_da_proven(const orc_da *s)
 int orc_da_run(orc_da *s, int iters, double min_gap)
 {
     int done = 0;
+    s->min_gap = min_gap;
     for (int it = 0; it < iters; ++it) {
         if (s->t > 0) {
             if (orc_da_proven(s)) break;
@@ -753,6 +882,7 @@ int orc_da_run(orc_da *s, int iters, double min_gap)
 int orc_da_n(const orc_da *s) { return s->n; }
 int orc_da_t(const orc_da *s) { return s->t; }
 double orc_da_lb(const orc_da *s) { return s->LB; }
+long long orc_da_sa_accepted(const orc_da *s) { return s->sa_accepted; }
 double orc_da_ub(const orc_da *s) { return s->UB; }
 long long orc_da_steps(const orc_da *s) { return s->lap_steps; }
 int orc_da_trace(const orc_da *s, double *out, int cap)
@@ -781,7 +911,7 @@ void orc_da_export(const orc_da *s, double *X, double *Y, double *Z)
  * Both are zero-sum over an orbit / a pair.  Tracking starts at zero. */
 int orc_da_track(orc_da *s)
 {
-    if (s->half || s->two_phase) return -1;  /* tracking follows the F1 FULL transfers */
+    if (s->half || s->two_phase || s->sa_on) return -1;  /* tracking follows the F1 FULL transfers */
     size_t n2 = (size_t)s->n * s->n, n4 = n2 * n2;
     if (!s->Vt) s->Vt = calloc(n4 * n2, sizeof(double));
     if (!s->Ut) s->Ut = calloc(n4, sizeof(double));

@@ -562,3 +562,110 @@ def test_f2_refuses_half_and_tracking():
     da = O.DualAscent(F, D, B, two_phase=True)
     with pytest.raises(Exception):
         da.track()
+
+
+# ---- Type 4 ascent with simulated annealing (Section 2.3, schedule of Section 5) ----
+
+def test_splitmix64_published_outputs():
+    """SplitMix64 seeded with 0: its first three outputs as published with
+    the generator (Steele, Lea and Flood 2014); uniforms are the top 53 bits."""
+    assert [O.splitmix64(0, c) for c in (1, 2, 3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                                       0x06C45D188009454F]
+    assert O.sa_uniform(0, 1) == (0xE220A8397B1DCDAF >> 11) / 2.0 ** 53
+    u = [O.sa_uniform(7, c) for c in range(1, 20001)]
+    assert min(u) >= 0.0 and max(u) < 1.0 and abs(np.mean(u) - 0.5) < 0.01
+
+
+def test_sa_exp_matches_libm():
+    import math
+    xs = np.concatenate([np.linspace(-60.0, 0.0, 30001), -np.logspace(-12, 2.8, 2000)])
+    for x in xs:
+        e = math.exp(x)
+        assert abs(O.sa_exp(x) - e) <= 4.5e-16 * e, x
+    assert O.sa_exp(0.0) == 1.0 and O.sa_exp(-800.0) == 0.0
+
+
+def _sa_state(inst, iters=3):
+    F, D, B = inst.arrays()
+    da = O.DualAscent(F, D, B)
+    da.run(iters)
+    return F, D, B, da
+
+
+@pytest.mark.parametrize("inst", [I.random_instance(6, 21), I.grid_instance(6, 2, 3, 0.4, 1, 9, 5)],
+                         ids=lambda x: x.name)
+def test_type4_step_keeps_the_identity_and_moves_at_most_kappa_max(inst):
+    """A taken Type 4 step (huge temperature) lowers LB by the amount it adds
+    to the x slacks (each row i and column p uniformly), at most
+    kappa_max * LB; every permutation's cost still equals LB + reduced costs
+    and slacks stay >= 0.  A tiny temperature takes no step."""
+    F, D, B, da = _sa_state(inst)
+    n = inst.n
+    perms = [np.array(p, dtype=np.int32) for p in itertools.permutations(range(n))]
+    X0 = da.export()[0].copy()
+    lb0 = da.LB
+    da.set_annealing(1e30, kappa_max=0.25, seed=3)
+    assert da.type4(5)
+    X1 = da.export()[0]
+    drop = lb0 - da.LB
+    assert 0.0 < drop <= 0.25 * lb0 * (1 + 1e-12)
+    inc = X1 - X0
+    # row + column structure: inc[i,p] = a_i + b_p
+    a = inc[:, 0] - inc[0, 0]
+    b = inc[0, :]
+    assert np.allclose(inc, a[:, None] + b[None, :], rtol=0, atol=1e-9 * lb0)
+    assert abs(inc.trace() - drop) <= 1e-9 * lb0  # identity permutation meets each row/column once
+    _check_identity(da, F, D, B, perms)
+    F, D, B, db = _sa_state(inst)
+    db.set_annealing(1e-300, seed=3)
+    X0 = db.export()[0].copy()
+    lb0 = db.LB
+    assert not db.type4(5)
+    assert db.LB == lb0 and np.array_equal(db.export()[0], X0)
+
+
+@pytest.mark.parametrize("inst", [I.random_instance(8, 3), I.random_instance(9, 11)], ids=lambda x: x.name)
+def test_annealed_ascent_bounds_stay_valid(inst):
+    """With a temperature that takes nearly every step (each gives away up
+    to a quarter of the bound), every iteration's bound stays <= the
+    brute-force optimum and the final state keeps the identity."""
+    F, D, B = inst.arrays()
+    n = inst.n
+    opt = brute_opt(F, D, B)
+    da = O.DualAscent(F, D, B)
+    da.run(2)
+    da.set_annealing(10.0 * opt, seed=11)
+    da.run(60)
+    tr = da.trace()
+    assert da.sa_accepted >= 0.5 * (da.t - 2) >= 4
+    assert tr.max() <= opt + 1e-9 * max(1.0, opt)
+    rng = np.random.default_rng(1)
+    perms = [rng.permutation(n).astype(np.int32) for _ in range(200)]
+    _check_identity(da, F, D, B, perms)
+
+
+def test_annealing_schedule_and_refusals():
+    """Section 5's schedule: at 4 % of the optimum a few steps are taken in
+    300 iterations and the best bound is no worse than F1's; t0 <= 0 is F1
+    exactly; bad parameters and tracking are refused."""
+    inst = I.grid_instance(10, 2, 5, 0.4, 1, 9, 6)
+    F, D, B = inst.arrays()
+    f1 = O.DualAscent(F, D, B)
+    f1.run(300)
+    sa = O.DualAscent(F, D, B)
+    sa.run(2)
+    sa.set_annealing(0.04 * f1.UB, seed=1)
+    sa.run(298)
+    assert 1 <= sa.sa_accepted <= 50
+    assert sa.trace().max() >= f1.LB
+    off = O.DualAscent(F, D, B)
+    off.set_annealing(0.0)
+    off.run(40)
+    assert np.array_equal(off.trace(), f1.trace()[:40])
+    for bad in [dict(kappa_max=1.5), dict(cool=0.0), dict(period=0)]:
+        with pytest.raises(ValueError):
+            O.DualAscent(F, D, B).set_annealing(100.0, **bad)
+    tr = O.DualAscent(F, D, B)
+    tr.track()
+    with pytest.raises(ValueError):
+        tr.set_annealing(100.0)
