@@ -109,11 +109,13 @@ typedef struct qap_params {
 typedef struct qap_da_stats {
     int iterations_done;   /* iterations run by this call */
     int t;                 /* iterations run since init */
-    double lb;             /* best lower bound (F1 bounds are monotone) */
+    double lb;             /* the state's bound: the last X-LAP bound, less what a
+                              Type 4 step after it gave away (without annealing
+                              the bounds never fall, so this is also the best) */
     double ub;             /* best X-LAP permutation cost (+inf if none) */
-    double gap;            /* (ub - lb)/|ub| */
+    double gap;            /* (ub - max(lb, best_lb))/|ub| */
     int proven;            /* 1 when lb certifies ub optimal (feasibility check) */
-    int pad;
+    int sa_steps;          /* Type 4 steps taken since init (qap_set_annealing) */
     long long laps;        /* LAPs solved by this call: iters*(T + n^2 + 1), T/2 for
                               HALF, 2T at t >= 1 for F2 */
     long long dijkstra_steps; /* Dijkstra steps of all LAPs of this call */
@@ -121,7 +123,8 @@ typedef struct qap_da_stats {
     double ms_sweep;       /* with params.timing: summed device milliseconds of */
     double ms_zlap;        /* the ascent sweep (+x/y scaling), the Z-LAP kernel, */
     double ms_ylap;        /* the Y-LAP kernel and the X-LAP kernel over the call */
-    double ms_xlap;
+    double ms_xlap;        /* (with annealing, the X phase includes the Type 4 step) */
+    double best_lb;        /* best bound of any iteration since init (-inf before any) */
 } qap_da_stats;
 
 typedef struct qap_bnb_params {
@@ -215,12 +218,41 @@ int qap_destroy(qap_handle h);
  * NULL.  Errors: QAP_EINVAL (h NULL). */
 int qap_zlap_mapping(qap_handle h, int *lanes, int *cols, double *tuned_us);
 
-/* Run `iters` more F1 iterations (Algorithm 1 steps 2-5): ascent sweep of the
- * Type 1-3 rules (t >= 1), Z-LAPs, y-pair rule (t >= 1), Y-LAPs, X-LAP,
- * bound and incumbent update.  Stops early once the bound proves the
- * incumbent optimal or the gap falls below min_gap.  Writes the best lower
- * bound to *lb_out and the X-LAP duals alpha (rows, n) and beta (columns, n)
- * of the last iteration to alpha_out/beta_out (host, nullable); st nullable.
+/* Type 4 ascent with simulated annealing (Section 2.3's last ascent rule,
+ * Section 5's schedule).  After the X-LAP of every iteration t >= 1 whose
+ * bound nu is positive and does not stop the run, a random fraction
+ * kappa^lb = kappa_max * u of nu is split over one fraction per facility and
+ * one per location (in proportion to random weights); facility i's share is
+ * added to every x slack of row i, location p's to every slack of column p,
+ * so every permutation's cost = LB + slacks still holds.  The offer A is
+ * taken when u' <= exp(-A / T), T = t0 * cool^floor(t / period), and LB then
+ * drops by A; the trace keeps each iteration's X-LAP bound and best_lb the
+ * best of them.  Random numbers: SplitMix64 (Steele, Lea and Flood 2014)
+ * seeded with `seed`, its outputs t*(2n+2) + 1 ... + 2n+2 for iteration t,
+ * so a run is reproducible.  Section 5 uses t0 = 4 % of the best known UB,
+ * kappa_max = 0.25, cool = 0.99, period = 100. */
+typedef struct qap_sa_params {
+    double t0;             /* initial temperature (cost units); <= 0: annealing off */
+    double kappa_max;      /* largest fraction of the bound offered per step, [0, 1] */
+    double cool;           /* temperature factor per period, (0, 1] */
+    int period;            /* iterations per cooling step, >= 1 */
+    int pad;
+    uint64_t seed;
+} qap_sa_params;
+
+/* Turn annealing on (p->t0 > 0) or off (p NULL or t0 <= 0) for the next
+ * iterations of h.  Errors: QAP_EINVAL (parameters), QAP_EUNSUPPORTED (h
+ * tracks multipliers).  A handle with annealing on refuses tracking, child
+ * folds, batched and B&B ascent (QAP_EUNSUPPORTED). */
+int qap_set_annealing(qap_handle h, const qap_sa_params *p);
+
+/* Run `iters` more iterations (Algorithm 1 steps 2-5): ascent sweep of the
+ * Type 1-3 rules (t >= 1), Z-LAPs (twice with pooling under F2), y-pair rule
+ * (t >= 1), Y-LAPs, X-LAP, bound and incumbent update, and a Type 4 step if
+ * annealing is on.  Stops early once the bound proves the incumbent optimal
+ * or the gap falls below min_gap.  Writes the state's bound (qap_da_stats.lb)
+ * to *lb_out and the X-LAP duals alpha (rows, n) and beta (columns, n) of
+ * the last iteration to alpha_out/beta_out (host, nullable); st nullable.
  * Errors: QAP_EINVAL (iters < 0), QAP_EDEVICE. */
 int qap_dual_ascent(qap_handle h, int iters, double *lb_out, double *alpha_out,
                     double *beta_out, qap_da_stats *st);

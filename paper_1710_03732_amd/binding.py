@@ -37,10 +37,15 @@ SCHEME_HALF = 1
 
 class QapDaStats(C.Structure):
     _fields_ = [("iterations_done", C.c_int), ("t", C.c_int), ("lb", C.c_double),
-                ("ub", C.c_double), ("gap", C.c_double), ("proven", C.c_int), ("pad", C.c_int),
+                ("ub", C.c_double), ("gap", C.c_double), ("proven", C.c_int), ("sa_steps", C.c_int),
                 ("laps", C.c_longlong), ("dijkstra_steps", C.c_longlong), ("seconds", C.c_double),
                 ("ms_sweep", C.c_double), ("ms_zlap", C.c_double), ("ms_ylap", C.c_double),
-                ("ms_xlap", C.c_double)]
+                ("ms_xlap", C.c_double), ("best_lb", C.c_double)]
+
+
+class QapSaParams(C.Structure):
+    _fields_ = [("t0", C.c_double), ("kappa_max", C.c_double), ("cool", C.c_double),
+                ("period", C.c_int), ("pad", C.c_int), ("seed", C.c_uint64)]
 
 
 class QapBnbParams(C.Structure):
@@ -96,7 +101,8 @@ EXPORTED = ("qap_version", "qap_default_params", "qap_workspace_bytes", "qap_rlt
             "qap_orbit_count", "qap_multiplier_scale", "qap_orbit_features", "qap_orbit_targets",
             "qap_warm_start_outputs", "qap_mlp_create", "qap_mlp_destroy", "qap_mlp_set_stream",
             "qap_mlp_get_params", "qap_mlp_forward", "qap_mlp_gradients", "qap_mlp_train_step",
-            "qap_orbit_outputs", "qap_warm_start", "qap_set_allocator", "qap_zlap_mapping")
+            "qap_orbit_outputs", "qap_warm_start", "qap_set_allocator", "qap_zlap_mapping",
+            "qap_set_annealing")
 
 
 def lib():
@@ -112,6 +118,7 @@ def lib():
         L.qap_workspace_bytes.restype = C.c_size_t
         L.qap_rlt2_init.argtypes = [_dp, _dp, _dp, C.c_int, C.POINTER(QapParams), C.POINTER(C.c_void_p)]
         L.qap_destroy.argtypes = [C.c_void_p]
+        L.qap_set_annealing.argtypes = [C.c_void_p, C.c_void_p]
         L.qap_zlap_mapping.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                        C.POINTER(C.c_double)]
         L.qap_dual_ascent.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, C.POINTER(QapDaStats)]
@@ -266,7 +273,14 @@ class DualAscent:
                 "t": st.t, "ub": st.ub, "gap": st.gap, "proven": bool(st.proven), "laps": st.laps,
                 "dijkstra_steps": st.dijkstra_steps, "seconds": st.seconds,
                 "ms_sweep": st.ms_sweep, "ms_zlap": st.ms_zlap, "ms_ylap": st.ms_ylap,
-                "ms_xlap": st.ms_xlap}
+                "ms_xlap": st.ms_xlap, "best_lb": st.best_lb, "sa_steps": st.sa_steps}
+
+    def set_annealing(self, t0: float, kappa_max: float = 0.25, cool: float = 0.99, period: int = 100,
+                      seed: int = 0):
+        """Type 4 steps with annealing after every iteration t >= 1 (Section 5's
+        schedule by default); t0 <= 0 turns them off."""
+        p = QapSaParams(float(t0), float(kappa_max), float(cool), int(period), 0, int(seed))
+        _check(lib().qap_set_annealing(self.h, C.byref(p)), self.h)
 
     def trace(self):
         n = C.c_int(0)

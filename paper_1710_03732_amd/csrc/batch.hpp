@@ -398,6 +398,7 @@ __global__ __launch_bounds__(64) void k_bxlap(const BNode *__restrict__ nodes, B
             S->ub = ub;
         }
         S->steps += (unsigned long long)st;
+        S->best = fmax(S->best, lb);
         const int t = S->t;
         if (t < N.trace_cap) N.trace[t] = lb;
         S->t = t + 1;

@@ -76,6 +76,7 @@ int qap_fold_child(qap_handle h, int l, int s, qap_handle *child)
     if (!h || !child) return QAP_EINVAL;
     if (h->half) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound children are FULL-scheme only");
     if (h->prm.two_phase) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound children are F1 only");
+    if (h->sa_on) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound children run without annealing");
     const int n = h->n, n1 = n - 1;
     if (n1 < 3) return fail(h, QAP_EUNSUPPORTED, "a child needs n >= 4");
     if (l < 0 || l >= n || s < 0 || s >= n) return fail(h, QAP_EINVAL, "facility/location out of range");
@@ -139,6 +140,7 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
         if (hs[b]->Vt) return fail(h0, QAP_ESTATE, "a batched handle tracks multipliers");
         if (hs[b]->half) return fail(h0, QAP_EUNSUPPORTED, "batched dual ascent is FULL-scheme only");
         if (hs[b]->prm.two_phase) return fail(h0, QAP_EUNSUPPORTED, "batched dual ascent is F1 only");
+        if (hs[b]->sa_on) return fail(h0, QAP_EUNSUPPORTED, "batched dual ascent runs without annealing");
     }
     auto t0 = std::chrono::steady_clock::now();
     HIPCHK(h0, hipSetDevice(h0->prm.device));
@@ -363,6 +365,7 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
     if (!h || !perm_out || !obj_out) return QAP_EINVAL;
     if (h->half) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound is FULL-scheme only");
     if (h->prm.two_phase) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound is F1 only");
+    if (h->sa_on) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound runs without annealing");
     qap_bnb_params P{};
     if (p) {
         P = *p;

@@ -54,6 +54,8 @@ struct qap_ctx {
     int zlap_waves = 1;  // waves per Z-LAP block
     bool zl_auto = false;     // mapping left to the autotuner (zlap_lanes = 0)
     bool half = false;        // HALF scheme: only the tiles with i < j are solved
+    bool sa_on = false;       // Type 4 steps with annealing after each X-LAP
+    SaConsts sa{};
     bool zl_tuned = false;    // the autotuner has chosen it
     double zl_tune_us = -1.0; // its time over the tuner's synthetic tiles (< 0: rule-based)
     double offset = 0.0; // constant added to every permutation cost (B&B nodes)
@@ -277,13 +279,21 @@ hipError_t launch_xlap(qap_ctx *h)
     return hipGetLastError();
 }
 
+hipError_t launch_type4(qap_ctx *h)
+{
+    if (!h->sa_on) return hipSuccess;
+    hipLaunchKernelGGL(k_type4, dim3(1), dim3(64), 0, h->stream, h->Px, h->S, h->n, h->sa);
+    return hipGetLastError();
+}
+
 hipError_t launch_iteration(qap_ctx *h, int t)
 {
     hipError_t e;
     if (t >= 1 && (e = launch_sweep(h)) != hipSuccess) return e;
     if ((e = launch_zphase(h, t)) != hipSuccess) return e;
     if ((e = launch_ylap(h, t >= 1 ? 1 : 0)) != hipSuccess) return e;
-    return launch_xlap(h);
+    if ((e = launch_xlap(h)) != hipSuccess) return e;
+    return launch_type4(h);
 }
 
 // Same launches with HIP events between the phases (on the handle's stream).
@@ -298,6 +308,7 @@ hipError_t launch_iteration_timed(qap_ctx *h, int t, hipEvent_t *ev)
     if ((e = launch_ylap(h, t >= 1 ? 1 : 0)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev[3], h->stream)) != hipSuccess) return e;
     if ((e = launch_xlap(h)) != hipSuccess) return e;
+    if ((e = launch_type4(h)) != hipSuccess) return e;
     return hipEventRecord(ev[4], h->stream);
 }
 
@@ -376,6 +387,7 @@ int upload_scalars(qap_ctx *h, double lb)
     s.integer_data = h->integer_data ? 1 : 0;
     s.stopped = 0;
     s.steps = 0;
+    s.best = -HUGE_VAL;
     HIPCHK(h, hipMemcpyAsync(h->S, &s, sizeof(s), hipMemcpyHostToDevice, h->stream));
     std::vector<int> ident(n);
     for (int i = 0; i < n; ++i) ident[i] = i;
@@ -534,6 +546,26 @@ int create_ctx(int n, const double *F, const double *D, const double *B, const q
 extern "C" {
 
 const char *qap_version(void) { return "qap-rlt2-mi355x 0.1 (gfx950, F1 and F2; FULL and HALF)"; }
+
+int qap_set_annealing(qap_handle h, const qap_sa_params *p)
+{
+    if (!h) return QAP_EINVAL;
+    const bool on = p && p->t0 > 0.0;
+    if (on) {
+        if (!std::isfinite(p->t0) || !(p->kappa_max >= 0.0 && p->kappa_max <= 1.0) ||
+            !(p->cool > 0.0 && p->cool <= 1.0) || p->period < 1)
+            return fail(h, QAP_EINVAL, "annealing needs t0 > 0 finite, kappa_max in [0,1], cool in (0,1], period >= 1");
+        if (h->Vt) return fail(h, QAP_EUNSUPPORTED, "annealing does not combine with multiplier tracking");
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->sa_on = on;
+    if (on) h->sa = SaConsts{p->t0, p->kappa_max, p->cool, p->seed, p->period};
+    if (h->graph) {  // the next replay captures the iteration with (or without) the step
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    return QAP_OK;
+}
 
 int qap_zlap_mapping(qap_handle h, int *lanes, int *cols, double *tuned_us)
 {
@@ -702,8 +734,11 @@ int qap_dual_ascent(qap_handle h, int iters, double *lb_out, double *alpha_out, 
         st->iterations_done = after.t - before.t;
         st->t = after.t;
         st->lb = after.lb;
+        st->best_lb = after.best;
+        st->sa_steps = after.sa_steps;
         st->ub = after.ub;
-        st->gap = (after.ub < HUGE_VAL && after.ub != 0.0) ? (after.ub - after.lb) / std::fabs(after.ub) : HUGE_VAL;
+        const double bl = std::max(after.lb, after.best);
+        st->gap = (after.ub < HUGE_VAL && after.ub != 0.0) ? (after.ub - bl) / std::fabs(after.ub) : HUGE_VAL;
         st->proven = after.proven;
         const long long zlaps = h->half ? h->T / 2 : h->T;  // HALF: tiles with i < j
         st->laps = (long long)st->iterations_done * (zlaps + (long long)h->n * h->n + 1);
@@ -838,6 +873,7 @@ int qap_import_state(qap_handle h, const qap_state_header *hdr, const double *x,
     s.t = hdr->t;
     s.proven = 0;
     s.stopped = 0;
+    s.best = hdr->t > 0 ? hdr->lb : -HUGE_VAL;
     HIPCHK(h, hipMemcpyAsync(h->S, &s, sizeof(s), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->t_host = hdr->t;

@@ -34,8 +34,9 @@ struct DevScalars {
     int integer_data;
     int stopped;       // set once the bound proves optimality or gap < min_gap
     int reason;        // why a batched node stopped (1 fathomed, 2 window rule, 3 gap)
-    int pad;
+    int sa_steps;      // Type 4 steps taken
     unsigned long long steps;
+    double best;       // best bound of any iteration (a Type 4 step lowers lb)
 };
 
 struct SweepConsts {
@@ -672,6 +673,7 @@ __global__ __launch_bounds__(64) void k_xlap(const double *__restrict__ Xc, doub
             S->ub = ub;
         }
         S->steps += (unsigned long long)st;  // X-LAP steps stay in the scalar block
+        S->best = fmax(S->best, lb);
         trace[S->t] = lb;
         S->t = S->t + 1;
         int proven = 0;
@@ -691,6 +693,106 @@ __global__ __launch_bounds__(64) void k_xlap(const double *__restrict__ Xc, doub
         xperm[l] = sig[l];
         if (better) bestperm[l] = sig[l];
     }
+}
+
+// ------------------------------------------------- Type 4 with annealing --
+// Section 2.3's Type 4 rule under Section 5's annealing schedule, after the
+// X-LAP of iteration it >= 1 (bound nu): a random fraction kappa^lb <=
+// kappa_max of nu, split over one fraction per facility and per location in
+// proportion to random weights, is offered to the x slacks (row i and
+// column p grow uniformly, so every permutation's cost = LB + slacks still
+// holds and the bound stays valid); the offer A is taken when
+// u <= exp(-A / T), T = t0 * cool^floor(it / period), and LB drops by A.
+// Draws: SplitMix64 outputs it*(2n+2) + 1 (size), + 2 (acceptance),
+// + 3 ... + 2n+2 (weights, facilities then locations).
+struct SaConsts {
+    double t0, kmax, cool;
+    unsigned long long seed;
+    int period;
+};
+
+// c-th output (c >= 1) of SplitMix64 seeded with `seed` (Steele, Lea and
+// Flood 2014: Weyl increment 0x9e3779b97f4a7c15 and its published
+// finaliser), as a uniform double in [0, 1) from the top 53 bits.
+__device__ __forceinline__ double sa_uniform(unsigned long long seed, unsigned long long c)
+{
+    unsigned long long z = seed + c * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// exp(x), x <= 0, in plain IEEE operations so that every platform computes
+// the same bits: x = k ln2 + r (Cody-Waite with a 32-bit high part, k * high
+// exact), degree-13 Taylor polynomial in Horner form, scaled by 2^k.
+__device__ __forceinline__ double sa_exp(double x)
+{
+    const double ln2_hi = 6.93147180369123816490e-01;
+    const double ln2_lo = 1.90821492927058770002e-10;
+    const double log2e = 1.44269504088896338700e+00;
+    if (x < -745.0) return 0.0;
+    const double k = floor(x * log2e + 0.5);
+    const double r = (x - k * ln2_hi) - k * ln2_lo;
+    double p = 1.0 / 6227020800.0;
+    p = p * r + 1.0 / 479001600.0;
+    p = p * r + 1.0 / 39916800.0;
+    p = p * r + 1.0 / 3628800.0;
+    p = p * r + 1.0 / 362880.0;
+    p = p * r + 1.0 / 40320.0;
+    p = p * r + 1.0 / 5040.0;
+    p = p * r + 1.0 / 720.0;
+    p = p * r + 1.0 / 120.0;
+    p = p * r + 1.0 / 24.0;
+    p = p * r + 1.0 / 6.0;
+    p = p * r + 0.5;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    return ldexp(p, (int)k);
+}
+
+// One wave; lane 0 draws and decides (2n <= 128 sequential terms, the
+// summation order of the definition), all lanes then update pi_x.
+__global__ __launch_bounds__(64) void k_type4(double *__restrict__ Px, DevScalars *__restrict__ S, int n,
+                                              SaConsts K)
+{
+    if (S->stopped) return;
+    __shared__ double w[128], a[128];
+    __shared__ int take;
+    const int l = threadIdx.x;
+    if (l == 0) {
+        take = 0;
+        const int it = S->t - 1;  // the iteration whose X-LAP just ran
+        const double nu = S->lb;
+        if (it >= 1 && nu > 0.0) {
+            const unsigned long long base = (unsigned long long)it * (unsigned long long)(2 * n + 2);
+            const double us = sa_uniform(K.seed, base + 1);
+            const double ua = sa_uniform(K.seed, base + 2);
+            double W = 0.0;
+            for (int k = 0; k < 2 * n; ++k) {
+                w[k] = sa_uniform(K.seed, base + 3 + (unsigned long long)k);
+                W = (k == 0) ? w[k] : W + w[k];
+            }
+            if (W > 0.0) {
+                const double klb = K.kmax * us;
+                double A = 0.0;
+                for (int k = 0; k < 2 * n; ++k) {
+                    a[k] = ((klb * w[k]) / W) * nu;
+                    A = (k == 0) ? a[k] : A + a[k];
+                }
+                double T = K.t0;
+                for (int c = 0; c < it / K.period; ++c) T = T * K.cool;
+                if (ua <= sa_exp(-(A / T))) {
+                    take = 1;
+                    S->lb = nu - A;
+                    S->sa_steps = S->sa_steps + 1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (take)
+        for (int e = l; e < n * n; e += 64) Px[e] = (Px[e] + a[e / n]) + a[n + e % n];
 }
 
 // -------------------------------------------------------------- LAP batch --

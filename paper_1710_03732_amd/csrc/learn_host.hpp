@@ -281,6 +281,7 @@ int qap_track(qap_handle h, int on)
     if (!h) return QAP_EINVAL;
     if (h->half) return fail(h, QAP_EUNSUPPORTED, "multiplier tracking follows the FULL shares");
     if (h->prm.two_phase) return fail(h, QAP_EUNSUPPORTED, "multiplier tracking does not follow the F2 pooling");
+    if (h->sa_on && on) return fail(h, QAP_EUNSUPPORTED, "multiplier tracking does not follow Type 4 steps");
     HIPCHK(h, hipStreamSynchronize(h->stream));
     if (!on) {
         dev_free(h, h->Vt);
