@@ -18,7 +18,8 @@ time; its `achieved` is algorithmic bytes per launch / average launch time.
 device copy measured in the same run (after the timed region).
 `variants` runs the HALF scheme (Section 5: only the Z-LAPs of tiles with
 i < j) and the two-phase F2 (Section 3.4) on the same workload and times
-each to the F1 bound of 100 iterations.
+each to the F1 bound of 100 iterations; `variants.annealing` compares 300
+iterations of F1 and F2 with and without Type 4 annealing steps.
 `time_to_bound` compares 100 cold iterations with the learned warm start
 (trained weights from train_warm.py) reaching the same bound; its
 `mlp_roofline` gives the inference kernel's TFLOP/s against the bf16 MFMA
@@ -203,6 +204,30 @@ def variant_leg(inst, label: str, make_params, z_laps: int, ab: dict, steps: int
     return out
 
 
+def annealing_leg(inst, iters: int = 300, seed: int = 1):
+    """Type 4 steps with Section 5's schedule (t0 = 4 % of the incumbent
+    after two iterations, kappa_max 0.25, cooling 0.99 per 100 iterations)
+    against plain runs: best bound after `iters` iterations and wall time,
+    for F1 and for F2 (the paper's strongest combination)."""
+    from paper_1710_03732_amd import binding
+
+    F, D, B = inst.arrays()
+    out = {"iterations": iters, "seed": seed}
+    for label, kw in (("f1", {}), ("f2", {"two_phase": 1})):
+        for sa in (False, True):
+            h = binding.DualAscent(F, D, B, **kw)
+            t0 = time.perf_counter()
+            r = h.run(2)
+            if sa:
+                h.set_annealing(0.04 * r["ub"], seed=seed)
+            r = h.run(iters - 2)
+            el = time.perf_counter() - t0
+            h.close()
+            out[label + ("_sa" if sa else "")] = {"best_lb": r["best_lb"], "ub": r["ub"], "seconds": el,
+                                                  "type4_steps": r["sa_steps"]}
+    return out
+
+
 def variant_legs(inst, steps: int, warmup: int, full_trace, cold_iters: int, stream):
     """HALF (Section 5: only the Z-LAPs of tiles with i < j) and the
     two-phase F2 (Section 3.4: solve, pool each orbit's slacks, solve)."""
@@ -218,6 +243,7 @@ def variant_legs(inst, steps: int, warmup: int, full_trace, cold_iters: int, str
                             warmup, full_trace, cold_iters, stream),
         "f2": variant_leg(inst, "f2", lambda **kw: binding.default_params(two_phase=1, **kw), 2 * T, f2_bytes,
                           steps, warmup, full_trace, cold_iters, stream),
+        "annealing": annealing_leg(inst),
     }
 
 
