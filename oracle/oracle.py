@@ -72,6 +72,7 @@ def lib():
         L.orc_da_set_half.argtypes = [C.c_void_p]
         L.orc_da_set_two_phase.argtypes = [C.c_void_p]
         L.orc_da_pool.argtypes = [C.c_void_p]
+        L.orc_da_set_slow.argtypes = [C.c_void_p]
         L.orc_splitmix64.argtypes = [C.c_ulonglong, C.c_ulonglong]
         L.orc_splitmix64.restype = C.c_ulonglong
         L.orc_sa_uniform.argtypes = [C.c_ulonglong, C.c_ulonglong]
@@ -167,7 +168,7 @@ def rule3_order(F):
 class DualAscent:
     """The F1 RLT2 dual ascent on dense reduced-cost arrays."""
 
-    def __init__(self, F, D, B=None, params=FULL, _handle=None, two_phase=False):
+    def __init__(self, F, D, B=None, params=FULL, _handle=None, two_phase=False, slow=False):
         F, D = _f64(F), _f64(D)
         self.n = F.shape[0]
         B = np.zeros_like(F) if B is None else _f64(B)
@@ -184,6 +185,9 @@ class DualAscent:
         self.two_phase = bool(two_phase)
         if self.two_phase and lib().orc_da_set_two_phase(self.h) != 0:
             raise ValueError("oracle: F2 is not combined with HALF or tracking")
+        self.slow = bool(slow)
+        if self.slow and lib().orc_da_set_slow(self.h) != 0:
+            raise ValueError("oracle: S1 needs a fresh FULL state without F2 or annealing")
 
     @classmethod
     def from_arrays(cls, F, D, B, params, LB, X, Y, Z):

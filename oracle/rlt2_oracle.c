@@ -317,6 +317,7 @@ typedef struct orc_da {
     double sa_t0, sa_kmax, sa_cool;
     unsigned long long sa_seed;
     long long sa_accepted;  /* Type 4 steps taken */
+    int slow;               /* S1: LAPs on the full costs each iteration (orc_da_set_slow) */
 } orc_da;
 
 static void orc_da_derive(orc_da *s)
@@ -706,7 +707,7 @@ double orc_sa_exp(double x)
 int orc_da_set_annealing(orc_da *s, double t0, double kappa_max, double cool, int period,
                          unsigned long long seed)
 {
-    if (!s || s->Vt) return -1;
+    if (!s || s->Vt || s->slow) return -1;
     if (!(t0 > 0.0)) { s->sa_on = 0; return 0; }
     if (!(kappa_max >= 0.0 && kappa_max <= 1.0) || !(cool > 0.0 && cool <= 1.0) || period < 1) return -1;
     s->sa_on = 1;
@@ -823,14 +824,55 @@ void orc_da_pool(orc_da *s)
  * (the pooling moves multipliers the tracker does not follow); 0 or -1. */
 int orc_da_set_two_phase(orc_da *s)
 {
-    if (!s || s->half || s->Vt) return -1;
+    if (!s || s->half || s->Vt || s->slow) return -1;
     s->two_phase = 1;
+    return 0;
+}
+
+/* Slow variant S1 (Section 3.4): the LAPs of every iteration are solved on
+ * the full costs b', C', D' - v (the left-hand side of Eq. ch4:proof:4)
+ * rather than on the slacks.  The z multipliers follow F1's rule (tracked:
+ * v moves by the sweep's g_e - phi * sum, Eq. ch4:proof:2, from the slacks
+ * of the last full solve), and after the sweep the state is rebuilt from
+ * them: x costs b + f_ii d_pp, y costs f_ij d_pq, z costs -v (D = 0),
+ * LB = 0, so the X-LAP value is the whole bound nu(LRLT2(v)).  The y
+ * multipliers stay 0 (the y-pair rule is not applied): that is the setting
+ * of Theorem 1, under which these bounds never fall. */
+static void orc_da_rebuild(orc_da *s)
+{
+    int n = s->n;
+    size_t n2 = (size_t)n * n, n4 = n2 * n2;
+    for (size_t e = 0; e < n4 * n2; ++e) s->Z[e] = -s->Vt[e];
+    for (int i = 0; i < n; ++i)
+        for (int p = 0; p < n; ++p)
+            s->X[IX2(n, i, p)] = s->B[IX2(n, i, p)] + s->F[IX2(n, i, i)] * s->D[IX2(n, p, p)];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            for (int p = 0; p < n; ++p)
+                for (int q = 0; q < n; ++q) {
+                    if (q == p) continue;
+                    s->Y[IX4(n, i, j, p, q)] = s->F[IX2(n, i, j)] * s->D[IX2(n, p, q)];
+                }
+        }
+    s->LB = 0.0;
+}
+
+/* Switch a fresh state (t = 0) to S1: turns tracking on (the multipliers are
+ * its state).  Not with HALF, F2 or annealing.  0 or -1. */
+int orc_da_track(orc_da *s);
+int orc_da_set_slow(orc_da *s)
+{
+    if (!s || s->t != 0 || s->half || s->two_phase || s->sa_on) return -1;
+    if (orc_da_track(s) != 0) return -1;
+    s->slow = 1;
     return 0;
 }
 
 void orc_da_iterate(orc_da *s)
 {
     if (s->t >= 1) orc_da_sweep(s);
+    if (s->t >= 1 && s->slow) orc_da_rebuild(s);
     orc_da_zphase(s);
     if (s->two_phase && s->t >= 1) {
         /* F2: pool within the orbits, then re-solve the Z-LAPs on the pooled
@@ -838,7 +880,7 @@ void orc_da_iterate(orc_da *s)
         orc_da_pool(s);
         orc_da_zphase(s);
     }
-    if (s->t >= 1) orc_da_yequal(s);
+    if (s->t >= 1 && !s->slow) orc_da_yequal(s);  /* S1 keeps u = 0 */
     orc_da_yphase(s);
     orc_da_xphase(s);
     orc_trace_push(s, s->LB);

@@ -669,3 +669,66 @@ def test_annealing_schedule_and_refusals():
     tr.track()
     with pytest.raises(ValueError):
         tr.set_annealing(100.0)
+
+
+# ---- slow variant S1 (Section 3.4): LAPs on the full costs every iteration ----
+
+@pytest.mark.parametrize("inst", [I.random_instance(8, 3), I.grid_instance(9, 3, 3, 0.4, 1, 10, 2),
+                                  I.random_instance(9, 11)], ids=lambda x: x.name)
+def test_s1_bound_never_falls_and_stays_valid(inst):
+    """Theorem 1 (fixed u): the S1 bounds, each recomputed from scratch on
+    the full costs, never fall (to rounding) and stay below the brute-force
+    optimum."""
+    F, D, B = inst.arrays()
+    opt = brute_opt(F, D, B)
+    da = O.DualAscent(F, D, B, slow=True)
+    da.run(30)
+    tr = da.trace()
+    assert np.all(np.diff(tr) >= -1e-9 * abs(tr[-1]))
+    assert tr.max() <= opt + 1e-9 * max(1.0, opt)
+
+
+def test_s1_state_is_the_s_form_of_its_multipliers():
+    """After an S1 iteration the z level is -v for the tracked v (zero-sum
+    over every orbit), the y multipliers are 0, and the bound of that
+    iteration equals a fresh S-form start from v run for one iteration (the
+    LAPs on b, C, -v) -- the left-hand side of Eq. ch4:proof:4."""
+    inst = I.grid_instance(7, 2, 4, 0.4, 1, 9, 1)
+    F, D, B = inst.arrays()
+    n = inst.n
+    da = O.DualAscent(F, D, B, slow=True)
+    da.run(6)
+    V, U = da.multipliers()
+    assert not U.any()
+    for (i, j, k) in itertools.combinations(range(n), 3):
+        for (p, q, r) in [(0, 1, 2), (n - 1, 0, 3), (2, n - 2, 1)]:
+            assert abs(sum(V[m] for m in _orbit_members(i, j, k, p, q, r))) <= 1e-9 * max(1.0, np.abs(V).max())
+    # one more S1 iteration = sweep (v update), rebuild, LAPs
+    da.run(1)
+    V1, _ = da.multipliers()
+    fresh = O.DualAscent.from_multipliers(F, D, B, O.FULL, V1, None)
+    fresh.run(1)
+    assert fresh.trace()[0] == da.trace()[-1]
+
+
+@pytest.mark.parametrize("inst", [I.random_instance(5, 3), I.grid_instance(6, 2, 3, 0.4, 1, 9, 4)],
+                         ids=lambda x: x.name)
+def test_s1_identity_every_iteration(inst):
+    F, D, B = inst.arrays()
+    n = F.shape[0]
+    perms = [np.array(p, dtype=np.int32) for p in itertools.permutations(range(n))]
+    da = O.DualAscent(F, D, B, slow=True)
+    for _ in range(5):
+        da.run(1)
+        _check_identity(da, F, D, B, perms)
+
+
+def test_s1_refuses_other_variants():
+    F, D, B = I.random_instance(5, 2).arrays()
+    with pytest.raises(ValueError):
+        O.DualAscent(F, D, B, O.HALF, slow=True)
+    with pytest.raises(ValueError):
+        O.DualAscent(F, D, B, two_phase=True, slow=True)
+    da = O.DualAscent(F, D, B, slow=True)
+    with pytest.raises(ValueError):
+        da.set_annealing(100.0)
