@@ -49,7 +49,7 @@ extern "C" {
 #define QAP_ENOMEM (-2)       /* device arena larger than free memory (checked first) */
 #define QAP_EDEVICE (-3)      /* HIP runtime error (text in qap_last_error) */
 #define QAP_ESTATE (-4)       /* call out of order, or bad checksum on import */
-#define QAP_EUNSUPPORTED (-5) /* n outside 3..64, or a call a HALF or F2 handle refuses */
+#define QAP_EUNSUPPORTED (-5) /* n outside 3..64, or a call a HALF, F2, S1 or annealing handle refuses */
 
 typedef struct qap_ctx *qap_handle;
 
@@ -101,6 +101,17 @@ typedef struct qap_params {
                               the y costs as well.  FULL scheme only; tracking,
                               child folds, batched and B&B ascent refuse an F2
                               handle (QAP_EUNSUPPORTED) */
+    int slow;              /* 0: fast (F-form); 1: S1, the slow variant of Section 3.4:
+                              the z multipliers v move by F1's sweep rule (Eq.
+                              ch4:proof:2) and each iteration solves the LAPs on
+                              the full costs b + f_ii d_pp, f_ij d_pq and -v, so
+                              every X-LAP value is a whole bound (the left-hand
+                              side of Eq. ch4:proof:4).  The y multipliers stay 0
+                              (Theorem 1's setting; the y-pair rule is not
+                              applied).  v lives in the tracking array
+                              (qap_get_multipliers).  FULL, not with F2 or
+                              annealing; import, multiplier setting, warm starts,
+                              folds, batched and B&B ascent refuse S1 handles */
     qap_alloc_fn alloc;    /* optional device allocator */
     qap_free_fn free_fn;
     void *alloc_ctx;

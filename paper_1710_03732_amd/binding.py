@@ -27,7 +27,8 @@ class QapParams(C.Structure):
     _fields_ = [("kappa_z", C.c_double), ("kappa_y", C.c_double), ("kappa_x", C.c_double),
                 ("phi_z", C.c_double), ("phi_y", C.c_double), ("min_gap", C.c_double),
                 ("device", C.c_int), ("zlap_lanes", C.c_int), ("zlap_cols", C.c_int),
-                ("timing", C.c_int), ("scheme", C.c_int), ("two_phase", C.c_int), ("alloc", _alloc_fn),
+                ("timing", C.c_int), ("scheme", C.c_int), ("two_phase", C.c_int), ("slow", C.c_int),
+                ("alloc", _alloc_fn),
                 ("free_fn", _free_fn), ("alloc_ctx", C.c_void_p)]
 
 

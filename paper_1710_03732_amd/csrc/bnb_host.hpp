@@ -77,6 +77,7 @@ int qap_fold_child(qap_handle h, int l, int s, qap_handle *child)
     if (h->half) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound children are FULL-scheme only");
     if (h->prm.two_phase) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound children are F1 only");
     if (h->sa_on) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound children run without annealing");
+    if (h->prm.slow) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound children are F1 only");
     const int n = h->n, n1 = n - 1;
     if (n1 < 3) return fail(h, QAP_EUNSUPPORTED, "a child needs n >= 4");
     if (l < 0 || l >= n || s < 0 || s >= n) return fail(h, QAP_EINVAL, "facility/location out of range");
@@ -137,6 +138,7 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
     for (int b = 0; b < count; ++b) {
         if (!hs[b] || hs[b]->prm.device != h0->prm.device) return fail(h0, QAP_EINVAL, "handles on one device");
         if (hs[b]->n > 64) return fail(h0, QAP_EUNSUPPORTED, "n > 64 in a batch");
+        if (hs[b]->prm.slow) return fail(h0, QAP_EUNSUPPORTED, "batched dual ascent is F1 only");
         if (hs[b]->Vt) return fail(h0, QAP_ESTATE, "a batched handle tracks multipliers");
         if (hs[b]->half) return fail(h0, QAP_EUNSUPPORTED, "batched dual ascent is FULL-scheme only");
         if (hs[b]->prm.two_phase) return fail(h0, QAP_EUNSUPPORTED, "batched dual ascent is F1 only");
@@ -366,6 +368,7 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
     if (h->half) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound is FULL-scheme only");
     if (h->prm.two_phase) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound is F1 only");
     if (h->sa_on) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound runs without annealing");
+    if (h->prm.slow) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound is F1 only");
     qap_bnb_params P{};
     if (p) {
         P = *p;

@@ -132,7 +132,8 @@ bool params_ok(const qap_params &p)
     // each member shares among its partners: five under FULL, two upper ones under HALF
     const double partners = p.scheme == QAP_SCHEME_HALF ? 2.0 : 5.0;
     const bool mapping = p.scheme != QAP_SCHEME_HALF || p.zlap_lanes == 0 || p.zlap_lanes == -1;
-    const bool variant = p.two_phase == 0 || (p.two_phase == 1 && p.scheme == QAP_SCHEME_FULL);
+    const bool variant = (p.two_phase == 0 || (p.two_phase == 1 && p.scheme == QAP_SCHEME_FULL)) &&
+                         (p.slow == 0 || (p.slow == 1 && p.scheme == QAP_SCHEME_FULL && p.two_phase == 0));
     return (p.scheme == QAP_SCHEME_FULL || p.scheme == QAP_SCHEME_HALF) && mapping && variant && in01(p.kappa_z) &&
            in01(p.kappa_y) && in01(p.kappa_x) && in01(p.phi_z) && in01(p.phi_y) &&
            std::fabs(partners * p.phi_z - 1.0) < 1e-12 && std::isfinite(p.min_gap) && p.min_gap >= 0.0;
@@ -229,6 +230,16 @@ hipError_t launch_sweep(qap_ctx *h)
         const unsigned groups8 = (unsigned)((h->ntriples + 7) / 8);
         const int nb = (h->n + SB - 1) / SB;
         const unsigned blocks = groups8 * 8u * (unsigned)(nb * nb * nb);
+        if (h->prm.slow) {
+            hipLaunchKernelGGL((k_sweep<true, false, false, true>), dim3(blocks), dim3(256), 0, h->stream, h->Z,
+                               h->Py, h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, h->Vt);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            const long long work = std::max<long long>(h->T, (long long)h->n * h->n);
+            const unsigned sb = (unsigned)std::min<long long>((work + 255) / 256, 65535);
+            hipLaunchKernelGGL(k_slow_reset, dim3(sb), dim3(256), 0, h->stream, h->F, h->D, h->B, h->Xc, h->Yc,
+                               h->n, h->S);
+            return hipGetLastError();
+        }
         if (h->half)
             hipLaunchKernelGGL((k_sweep<false, true>), dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py,
                                h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, (double *)nullptr);
@@ -291,7 +302,7 @@ hipError_t launch_iteration(qap_ctx *h, int t)
     hipError_t e;
     if (t >= 1 && (e = launch_sweep(h)) != hipSuccess) return e;
     if ((e = launch_zphase(h, t)) != hipSuccess) return e;
-    if ((e = launch_ylap(h, t >= 1 ? 1 : 0)) != hipSuccess) return e;
+    if ((e = launch_ylap(h, (t >= 1 && !h->prm.slow) ? 1 : 0)) != hipSuccess) return e;  // S1: u stays 0
     if ((e = launch_xlap(h)) != hipSuccess) return e;
     return launch_type4(h);
 }
@@ -305,7 +316,7 @@ hipError_t launch_iteration_timed(qap_ctx *h, int t, hipEvent_t *ev)
     if ((e = hipEventRecord(ev[1], h->stream)) != hipSuccess) return e;
     if ((e = launch_zphase(h, t)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev[2], h->stream)) != hipSuccess) return e;
-    if ((e = launch_ylap(h, t >= 1 ? 1 : 0)) != hipSuccess) return e;
+    if ((e = launch_ylap(h, (t >= 1 && !h->prm.slow) ? 1 : 0)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev[3], h->stream)) != hipSuccess) return e;
     if ((e = launch_xlap(h)) != hipSuccess) return e;
     if ((e = launch_type4(h)) != hipSuccess) return e;
@@ -545,7 +556,7 @@ int create_ctx(int n, const double *F, const double *D, const double *B, const q
 
 extern "C" {
 
-const char *qap_version(void) { return "qap-rlt2-mi355x 0.1 (gfx950, F1 and F2; FULL and HALF)"; }
+const char *qap_version(void) { return "qap-rlt2-mi355x 0.1 (gfx950, F1, F2 and S1; FULL and HALF; Type 4)"; }
 
 int qap_set_annealing(qap_handle h, const qap_sa_params *p)
 {
@@ -555,7 +566,7 @@ int qap_set_annealing(qap_handle h, const qap_sa_params *p)
         if (!std::isfinite(p->t0) || !(p->kappa_max >= 0.0 && p->kappa_max <= 1.0) ||
             !(p->cool > 0.0 && p->cool <= 1.0) || p->period < 1)
             return fail(h, QAP_EINVAL, "annealing needs t0 > 0 finite, kappa_max in [0,1], cool in (0,1], period >= 1");
-        if (h->Vt) return fail(h, QAP_EUNSUPPORTED, "annealing does not combine with multiplier tracking");
+        if (h->Vt || h->prm.slow) return fail(h, QAP_EUNSUPPORTED, "annealing does not combine with multiplier tracking or S1");
     }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->sa_on = on;
@@ -659,6 +670,11 @@ int qap_dual_ascent(qap_handle h, int iters, double *lb_out, double *alpha_out, 
     if (!h) return QAP_EINVAL;
     if (iters < 0) return fail(h, QAP_EINVAL, "iters < 0");
     HIPCHK(h, hipSetDevice(h->prm.device));
+    if (h->prm.slow && !h->Vt && iters > 0) {
+        // S1 keeps its z multipliers in the tracking array from the start
+        const int rc = qap_track(h, 1);
+        if (rc != QAP_OK) return rc;
+    }
     if (h->zl_auto && !h->zl_tuned && iters > 0) {
         // pick the Z-LAP mapping by measurement before anything is captured
         HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -848,6 +864,7 @@ int qap_import_state(qap_handle h, const qap_state_header *hdr, const double *x,
     cs = fnv1a(cs, y, sizeof(double) * h->T);
     cs = fnv1a(cs, z, sizeof(double) * h->Vz);
     if (cs != hdr->checksum) return fail(h, QAP_ESTATE, "state checksum mismatch");
+    if (h->prm.slow) return fail(h, QAP_EUNSUPPORTED, "an S1 state lives in its multipliers, not in the costs");
     if (h->half) {
         // tiles (i,p,j',q') with j < i, i.e. j' < i, must hold zeros
         const int n = h->n;

@@ -169,7 +169,11 @@ __device__ __forceinline__ int cube_idx(int pl, int ql, int rl) { return pl * SB
 // slacks into S_N (> 0) and S_B (<= 0); when both are non-empty the S_N
 // members become 0 and each S_B member gains (left fold of the S_N slacks,
 // canonical order) / |S_B|.  No y or x duals are involved.
-template <bool TRACK, bool HALF, bool POOL = false>
+//
+// SLOW (with TRACK) is the slow variant's sweep: the tracked multiplier
+// moves as above and z is rebuilt as its S-form cost, -v (D = 0), for LAPs
+// on the full costs.
+template <bool TRACK, bool HALF, bool POOL = false, bool SLOW = false>
 __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const double *__restrict__ Py,
                                                const double *__restrict__ Px,
                                                const int *__restrict__ triples, int ntriples, int n,
@@ -332,17 +336,45 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
                 // POOL leaves most orbits as they are (no zero slack among
                 // the six): store only entries whose bits changed
                 if (POOL && __double_as_longlong(share) == __double_as_longlong(pz[e][w])) continue;
-                Z[za[e][w]] = POOL ? share : K.okz * pz[e][w] + share;
+                if (!SLOW) Z[za[e][w]] = POOL ? share : K.okz * pz[e][w] + share;
                 if (TRACK) {
                     const int u = threadIdx.x + 256 * w;
                     const int a2 = (u / SB) % SB, a1 = u / (SB * SB);
                     const double y = pys[(e * SB + a1) * SB + a2];
                     const double x = pxs[X1[e] * SB + a1];
                     const double g = (K.kz * pz[e][w] + K.ky2 * y) + K.kx3 * x;
-                    Vt[za[e][w]] = Vt[za[e][w]] + (g - share);
+                    const double vnew = Vt[za[e][w]] + (g - share);
+                    Vt[za[e][w]] = vnew;
+                    if (SLOW) Z[za[e][w]] = -vnew;
                 }
             }
     }
+}
+
+// Slow variant: after its sweep the x and y levels restart from the full
+// costs, b + f_ii d_pp and f_ij d_pq (the y multipliers stay 0), and the
+// bound from 0, so the X-LAP gives the whole bound of the new multipliers.
+__global__ void k_slow_reset(const double *__restrict__ F, const double *__restrict__ D,
+                             const double *__restrict__ B, double *__restrict__ Xc, double *__restrict__ Yc,
+                             int n, DevScalars *__restrict__ S)
+{
+    if (S->stopped) return;
+    const long long T = (long long)n * n * (n - 1) * (n - 1);
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < T; e += stride) {
+        const int m1 = n - 1;
+        const int qp = (int)(e % m1);
+        const int jp = (int)((e / m1) % m1);
+        const int ip = (int)(e / ((long long)m1 * m1));
+        const int i = ip / n, p = ip % n;
+        const int j = jp + (jp >= i), q = qp + (qp >= p);
+        Yc[e] = F[i * n + j] * D[p * n + q];
+    }
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < (long long)n * n; e += stride) {
+        const int i = (int)(e / n), p = (int)(e % n);
+        Xc[e] = B[e] + F[i * n + i] * D[p * n + p];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) S->lb = 0.0;
 }
 
 // R_y <- (1-ky) pi_y, R_x <- (1-kx) pi_x (after the sweep has read them).

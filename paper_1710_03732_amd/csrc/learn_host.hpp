@@ -282,6 +282,7 @@ int qap_track(qap_handle h, int on)
     if (h->half) return fail(h, QAP_EUNSUPPORTED, "multiplier tracking follows the FULL shares");
     if (h->prm.two_phase) return fail(h, QAP_EUNSUPPORTED, "multiplier tracking does not follow the F2 pooling");
     if (h->sa_on && on) return fail(h, QAP_EUNSUPPORTED, "multiplier tracking does not follow Type 4 steps");
+    if (h->prm.slow && !on) return fail(h, QAP_EUNSUPPORTED, "an S1 handle keeps its multipliers tracked");
     HIPCHK(h, hipStreamSynchronize(h->stream));
     if (!on) {
         dev_free(h, h->Vt);
@@ -332,6 +333,7 @@ int qap_set_multipliers(qap_handle h, const double *v, const double *u)
 {
     if (!h) return QAP_EINVAL;
     if (h->half) return fail(h, QAP_EUNSUPPORTED, "z multipliers are FULL-scheme only");
+    if (h->prm.slow) return fail(h, QAP_EUNSUPPORTED, "an S1 handle sets its own multipliers");
     const int n = h->n;
     // zero sums: every orbit of v, every y pair of u
     if (v) {
@@ -452,6 +454,7 @@ int qap_warm_start_outputs(qap_handle h, const float *y, double scale)
 {
     if (!h || !y || !(scale > 0.0) || !std::isfinite(scale)) return QAP_EINVAL;
     if (h->half) return fail(h, QAP_EUNSUPPORTED, "warm starts are FULL-scheme only");
+    if (h->prm.slow) return fail(h, QAP_EUNSUPPORTED, "warm starts are F-form only");
     const int nb = (h->n + SB - 1) / SB;
     const unsigned groups8 = (unsigned)((h->ntriples + 7) / 8);
     const unsigned blocks = groups8 * 8u * (unsigned)(nb * nb * nb);
@@ -619,6 +622,7 @@ int qap_warm_start(qap_handle h, qap_mlp_handle p, double gain, qap_warm_stats *
 {
     if (!h || !p) return QAP_EINVAL;
     if (h->half) return fail(h, QAP_EUNSUPPORTED, "warm starts are FULL-scheme only");
+    if (h->prm.slow) return fail(h, QAP_EUNSUPPORTED, "warm starts are F-form only");
     if (!(gain > 0.0) || !std::isfinite(gain)) return fail(h, QAP_EINVAL, "gain must be positive and finite");
     auto t0 = std::chrono::steady_clock::now();
     const long long count = orbit_count_of(h->n);
