@@ -17,8 +17,8 @@ time; its `achieved` is algorithmic bytes per launch / average launch time.
 `frac` is against the 8 TB/s peak and `frac_of_copy` against a plain 2 GiB
 device copy measured in the same run (after the timed region).
 `variants` runs the HALF scheme (Section 5: only the Z-LAPs of tiles with
-i < j) and the two-phase F2 (Section 3.4) on the same workload and times
-each to the F1 bound of 100 iterations; `variants.annealing` compares 300
+i < j), the two-phase F2 and the slow S1 (Section 3.4) on the same workload
+and times each to the F1 bound of 100 iterations; `variants.annealing` compares 300
 iterations of F1 and F2 with and without Type 4 annealing steps.
 `time_to_bound` compares 100 cold iterations with the learned warm start
 (trained weights from train_warm.py) reaching the same bound; its
@@ -238,10 +238,14 @@ def variant_legs(inst, steps: int, warmup: int, full_trace, cold_iters: int, str
     V = T * (n - 2) * (n - 2)
     f1 = algorithmic_bytes(n)
     f2_bytes = dict(f1, zlap=2 * f1["zlap"] + 8 * 2 * V)  # two solves and the pooling pass
+    # S1's sweep also reads and writes the multipliers v; its reset writes the x/y costs
+    s1_bytes = dict(f1, sweep=8 * (4 * V + T + n * n) + 8 * (T + 2 * n * n))
     return {
         "half": variant_leg(inst, "half", binding.half_params, T // 2, algorithmic_bytes_half(n), steps,
                             warmup, full_trace, cold_iters, stream),
         "f2": variant_leg(inst, "f2", lambda **kw: binding.default_params(two_phase=1, **kw), 2 * T, f2_bytes,
+                          steps, warmup, full_trace, cold_iters, stream),
+        "s1": variant_leg(inst, "s1", lambda **kw: binding.default_params(slow=1, **kw), T, s1_bytes,
                           steps, warmup, full_trace, cold_iters, stream),
         "annealing": annealing_leg(inst),
     }
