@@ -187,7 +187,7 @@ class DualAscent:
             raise ValueError("oracle: F2 is not combined with HALF or tracking")
         self.slow = bool(slow)
         if self.slow and lib().orc_da_set_slow(self.h) != 0:
-            raise ValueError("oracle: S1 needs a fresh FULL state without F2 or annealing")
+            raise ValueError("oracle: S1 needs a fresh FULL state without annealing")
 
     @classmethod
     def from_arrays(cls, F, D, B, params, LB, X, Y, Z):

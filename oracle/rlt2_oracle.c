@@ -815,16 +815,22 @@ void orc_da_pool(orc_da *s)
                             }
                             if (nbasic == 0 || nbasic == 6) continue;
                             double share = slack / (double)nbasic;
-                            for (int e = 0; e < 6; ++e) Z[zi[e]] = pi[e] > 0.0 ? 0.0 : pi[e] + share;
+                            for (int e = 0; e < 6; ++e) {
+                                double nv = pi[e] > 0.0 ? 0.0 : pi[e] + share;
+                                Z[zi[e]] = nv;
+                                /* S2: the cost change is a multiplier move, v += old - new */
+                                if (s->slow) s->Vt[zi[e]] = s->Vt[zi[e]] + (pi[e] - nv);
+                            }
                         }
                     }
 }
 
-/* Switch a state to the two-phase variant F2.  Not with HALF or tracking
- * (the pooling moves multipliers the tracker does not follow); 0 or -1. */
+/* Switch a state to the two-phase variant (F2, or S2 with the slow
+ * variant, whose tracked multipliers the pooling then moves too).  Not with
+ * HALF, nor with tracking outside S1; 0 or -1. */
 int orc_da_set_two_phase(orc_da *s)
 {
-    if (!s || s->half || s->Vt || s->slow) return -1;
+    if (!s || s->half || (s->Vt && !s->slow)) return -1;
     s->two_phase = 1;
     return 0;
 }
@@ -858,14 +864,15 @@ static void orc_da_rebuild(orc_da *s)
     s->LB = 0.0;
 }
 
-/* Switch a fresh state (t = 0) to S1: turns tracking on (the multipliers are
- * its state).  Not with HALF, F2 or annealing.  0 or -1. */
+/* Switch a fresh state (t = 0) to S1 (S2 with the two-phase flag): turns
+ * tracking on (the multipliers are its state).  Not with HALF or
+ * annealing.  0 or -1. */
 int orc_da_track(orc_da *s);
 int orc_da_set_slow(orc_da *s)
 {
-    if (!s || s->t != 0 || s->half || s->two_phase || s->sa_on) return -1;
-    if (orc_da_track(s) != 0) return -1;
+    if (!s || s->t != 0 || s->half || s->sa_on) return -1;
     s->slow = 1;
+    if (orc_da_track(s) != 0) { s->slow = 0; return -1; }
     return 0;
 }
 
@@ -953,7 +960,7 @@ void orc_da_export(const orc_da *s, double *X, double *Y, double *Z)
  * Both are zero-sum over an orbit / a pair.  Tracking starts at zero. */
 int orc_da_track(orc_da *s)
 {
-    if (s->half || s->two_phase || s->sa_on) return -1;  /* tracking follows the F1 FULL transfers */
+    if (s->half || (s->two_phase && !s->slow) || s->sa_on) return -1;  /* tracking follows the FULL transfers */
     size_t n2 = (size_t)s->n * s->n, n4 = n2 * n2;
     if (!s->Vt) s->Vt = calloc(n4 * n2, sizeof(double));
     if (!s->Ut) s->Ut = calloc(n4, sizeof(double));
