@@ -17,7 +17,7 @@ time; its `achieved` is algorithmic bytes per launch / average launch time.
 `frac` is against the 8 TB/s peak and `frac_of_copy` against a plain 2 GiB
 device copy measured in the same run (after the timed region).
 `variants` runs the HALF scheme (Section 5: only the Z-LAPs of tiles with
-i < j), the two-phase F2 and the slow S1 (Section 3.4) on the same workload
+i < j), the two-phase F2 and the slow S1 and S2 (Section 3.4) on the same workload
 and times each to the F1 bound of 100 iterations; `variants.annealing` compares 300
 iterations of F1 and F2 with and without Type 4 annealing steps.
 `time_to_bound` compares 100 cold iterations with the learned warm start
@@ -247,6 +247,9 @@ def variant_legs(inst, steps: int, warmup: int, full_trace, cold_iters: int, str
                           steps, warmup, full_trace, cold_iters, stream),
         "s1": variant_leg(inst, "s1", lambda **kw: binding.default_params(slow=1, **kw), T, s1_bytes,
                           steps, warmup, full_trace, cold_iters, stream),
+        "s2": variant_leg(inst, "s2", lambda **kw: binding.default_params(slow=1, two_phase=1, **kw), 2 * T,
+                          dict(s1_bytes, zlap=f2_bytes["zlap"] + 8 * 2 * V), steps, warmup, full_trace, cold_iters,
+                          stream),
         "annealing": annealing_leg(inst),
     }
 

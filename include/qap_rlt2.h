@@ -98,9 +98,9 @@ typedef struct qap_params {
                               to 0, their total is shared equally by those with
                               slack <= 0; unchanged if either set is empty) and
                               the Z-LAPs are solved again, their values adding to
-                              the y costs as well.  FULL scheme only; tracking,
-                              child folds, batched and B&B ascent refuse an F2
-                              handle (QAP_EUNSUPPORTED) */
+                              the y costs as well.  FULL scheme only; tracking
+                              (outside S2), child folds, batched and B&B ascent
+                              refuse an F2 handle (QAP_EUNSUPPORTED) */
     int slow;              /* 0: fast (F-form); 1: S1, the slow variant of Section 3.4:
                               the z multipliers v move by F1's sweep rule (Eq.
                               ch4:proof:2) and each iteration solves the LAPs on
@@ -109,9 +109,11 @@ typedef struct qap_params {
                               side of Eq. ch4:proof:4).  The y multipliers stay 0
                               (Theorem 1's setting; the y-pair rule is not
                               applied).  v lives in the tracking array
-                              (qap_get_multipliers).  FULL, not with F2 or
+                              (qap_get_multipliers).  With two_phase = 1 this is
+                              S2: the pooling also moves each pooled member's v by
+                              its old slack minus its new one.  FULL, not with
                               annealing; import, multiplier setting, warm starts,
-                              folds, batched and B&B ascent refuse S1 handles */
+                              folds, batched and B&B ascent refuse S1/S2 handles */
     qap_alloc_fn alloc;    /* optional device allocator */
     qap_free_fn free_fn;
     void *alloc_ctx;

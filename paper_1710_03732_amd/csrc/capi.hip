@@ -133,7 +133,7 @@ bool params_ok(const qap_params &p)
     const double partners = p.scheme == QAP_SCHEME_HALF ? 2.0 : 5.0;
     const bool mapping = p.scheme != QAP_SCHEME_HALF || p.zlap_lanes == 0 || p.zlap_lanes == -1;
     const bool variant = (p.two_phase == 0 || (p.two_phase == 1 && p.scheme == QAP_SCHEME_FULL)) &&
-                         (p.slow == 0 || (p.slow == 1 && p.scheme == QAP_SCHEME_FULL && p.two_phase == 0));
+                         (p.slow == 0 || (p.slow == 1 && p.scheme == QAP_SCHEME_FULL));
     return (p.scheme == QAP_SCHEME_FULL || p.scheme == QAP_SCHEME_HALF) && mapping && variant && in01(p.kappa_z) &&
            in01(p.kappa_y) && in01(p.kappa_x) && in01(p.phi_z) && in01(p.phi_y) &&
            std::fabs(partners * p.phi_z - 1.0) < 1e-12 && std::isfinite(p.min_gap) && p.min_gap >= 0.0;
@@ -266,8 +266,12 @@ hipError_t launch_pool(qap_ctx *h)
     const unsigned groups8 = (unsigned)((h->ntriples + 7) / 8);
     const int nb = (h->n + SB - 1) / SB;
     const unsigned blocks = groups8 * 8u * (unsigned)(nb * nb * nb);
-    hipLaunchKernelGGL((k_sweep<false, false, true>), dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py, h->Px,
-                       h->triples, h->ntriples, h->n, nb, K, h->S, (double *)nullptr);
+    if (h->prm.slow)  // S2: the pooling moves the tracked multipliers too
+        hipLaunchKernelGGL((k_sweep<true, false, true>), dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py, h->Px,
+                           h->triples, h->ntriples, h->n, nb, K, h->S, h->Vt);
+    else
+        hipLaunchKernelGGL((k_sweep<false, false, true>), dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py,
+                           h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, (double *)nullptr);
     return hipGetLastError();
 }
 

@@ -172,7 +172,8 @@ __device__ __forceinline__ int cube_idx(int pl, int ql, int rl) { return pl * SB
 //
 // SLOW (with TRACK) is the slow variant's sweep: the tracked multiplier
 // moves as above and z is rebuilt as its S-form cost, -v (D = 0), for LAPs
-// on the full costs.
+// on the full costs.  POOL with TRACK is S2's pooling: a changed entry's
+// multiplier moves by its old slack minus its new one.
 template <bool TRACK, bool HALF, bool POOL = false, bool SLOW = false>
 __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const double *__restrict__ Py,
                                                const double *__restrict__ Px,
@@ -337,7 +338,9 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
                 // the six): store only entries whose bits changed
                 if (POOL && __double_as_longlong(share) == __double_as_longlong(pz[e][w])) continue;
                 if (!SLOW) Z[za[e][w]] = POOL ? share : K.okz * pz[e][w] + share;
-                if (TRACK) {
+                if (TRACK && POOL) {
+                    Vt[za[e][w]] = Vt[za[e][w]] + (pz[e][w] - share);
+                } else if (TRACK) {
                     const int u = threadIdx.x + 256 * w;
                     const int a2 = (u / SB) % SB, a1 = u / (SB * SB);
                     const double y = pys[(e * SB + a1) * SB + a2];

@@ -280,7 +280,8 @@ int qap_track(qap_handle h, int on)
 {
     if (!h) return QAP_EINVAL;
     if (h->half) return fail(h, QAP_EUNSUPPORTED, "multiplier tracking follows the FULL shares");
-    if (h->prm.two_phase) return fail(h, QAP_EUNSUPPORTED, "multiplier tracking does not follow the F2 pooling");
+    if (h->prm.two_phase && !h->prm.slow)
+        return fail(h, QAP_EUNSUPPORTED, "multiplier tracking does not follow the F2 pooling");
     if (h->sa_on && on) return fail(h, QAP_EUNSUPPORTED, "multiplier tracking does not follow Type 4 steps");
     if (h->prm.slow && !on) return fail(h, QAP_EUNSUPPORTED, "an S1 handle keeps its multipliers tracked");
     HIPCHK(h, hipStreamSynchronize(h->stream));

@@ -1,5 +1,7 @@
-"""GPU parity of the slow variant S1 (Section 3.4): the z multipliers move
-by F1's sweep rule and every iteration solves the LAPs on the full costs.
+"""GPU parity of the slow variants (Section 3.4): S1, where the z
+multipliers move by F1's sweep rule and every iteration solves the LAPs on
+the full costs, and S2, S1 with the two-phase pooling (which then moves the
+multipliers too).
 The HIP library through its C ABI against the CPU oracle's S1, bit for bit
 (np.array_equal): bounds, the rebuilt cost arrays and the multipliers."""
 import numpy as np
@@ -85,7 +87,7 @@ def test_s1_refusals():
             call()
         assert e.value.code == -5
     h.run(1)
-    for bad in [B.half_params(slow=1), B.default_params(slow=1, two_phase=1)]:
+    for bad in [B.half_params(slow=1)]:
         with pytest.raises(B.QapError) as e:
             B.DualAscent(F, D, Bm, params=bad)
         assert e.value.code == -1
@@ -104,3 +106,19 @@ def test_s1_full_size_n30_dense():
     T = 30 * 30 * 29 * 29
     got = s1.export_tiles([int(t) for t in np.random.default_rng(8).integers(0, T, 32)])
     assert got.min() >= -1e-9 * F.max() * D.max()
+
+
+@pytest.mark.parametrize("inst", [I.grid_n8(), I.random_instance(5, 3, lo=-5, hi=5), I.dense_instance(9, 5),
+                                  I.random_instance(12, 7, lo=0, hi=50), I.dense_instance(17, 11)],
+                         ids=lambda x: x.name)
+def test_s2_parity(inst):
+    F, D, Bm = inst.arrays()
+    n = inst.n
+    gpu = B.DualAscent(F, D, Bm, slow=1, two_phase=1)
+    cpu = O.DualAscent(F, D, Bm, slow=True, two_phase=True)
+    for chunk in ((1, 1, 2, 8) if n < 15 else (1, 4)):
+        g = gpu.run(chunk)
+        c = cpu.run(chunk)
+        assert g["iterations_done"] == c
+        _compare_state(gpu, cpu, n)
+    assert np.array_equal(gpu.trace(), cpu.trace())
