@@ -156,6 +156,12 @@ typedef struct qap_bnb_params {
                               cold from their restricted QAP, so no parent
                               state is kept for them (Section 4's depth limit
                               d; 0 = no cap, the default) */
+    int symmetry;          /* 1: symmetry elimination (Section 4, used there on
+                              grid instances): with the location automorphisms
+                              of D and B (qap_location_automorphisms), a child
+                              is not built when an automorphism that keeps every
+                              placed facility's location maps its location to a
+                              lower one; 0 (default): off */
 } qap_bnb_params;
 
 typedef struct qap_bnb_stats {
@@ -164,7 +170,19 @@ typedef struct qap_bnb_stats {
     long long batches;     /* batched launches */
     long long enumerated;  /* leaves evaluated by enumeration */
     double seconds;
+    long long symmetric_skipped; /* children not built by the symmetry elimination */
+    long long automorphisms;     /* location automorphisms used, identity included */
 } qap_bnb_stats;
+
+/* Location automorphisms of a QAP (host only, no device work): the
+ * permutations sigma of the locations with D[sigma p][sigma q] = D[p][q] for
+ * all p, q and B[i][sigma p] = B[i][p] for all i, p (B may be NULL: zero),
+ * under which every assignment keeps its cost.  D, B: host, n*n row-major.
+ * out: host, cap*n int32, permutation a at out[a*n .. a*n+n-1] (location p
+ * goes to out[a*n+p]); *count gets how many were written, the identity
+ * first.  A search budget and cap bound the work; every permutation written
+ * is exact even when the list is not the whole group.  Errors: QAP_EINVAL. */
+int qap_location_automorphisms(int n, const double *D, const double *B, int cap, int32_t *out, int *count);
 
 /* Node rules of qap_batch_dual_ascent (branch-and-bound control, Section 4
  * and the early termination of Section 5.4).  Each handle runs at most

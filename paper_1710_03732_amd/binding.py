@@ -52,12 +52,13 @@ class QapSaParams(C.Structure):
 class QapBnbParams(C.Structure):
     _fields_ = [("batch", C.c_int), ("node_iters", C.c_int), ("window", C.c_int),
                 ("root_iters", C.c_int), ("min_improve", C.c_double), ("ub0", C.c_double),
-                ("enum_below", C.c_int), ("rule", C.c_int), ("depth_cap", C.c_int)]
+                ("enum_below", C.c_int), ("rule", C.c_int), ("depth_cap", C.c_int), ("symmetry", C.c_int)]
 
 
 class QapBnbStats(C.Structure):
     _fields_ = [("nodes", C.c_longlong), ("da_iters", C.c_longlong), ("batches", C.c_longlong),
-                ("enumerated", C.c_longlong), ("seconds", C.c_double)]
+                ("enumerated", C.c_longlong), ("seconds", C.c_double), ("symmetric_skipped", C.c_longlong),
+                ("automorphisms", C.c_longlong)]
 
 
 class QapBatchParams(C.Structure):
@@ -103,7 +104,7 @@ EXPORTED = ("qap_version", "qap_default_params", "qap_workspace_bytes", "qap_rlt
             "qap_warm_start_outputs", "qap_mlp_create", "qap_mlp_destroy", "qap_mlp_set_stream",
             "qap_mlp_get_params", "qap_mlp_forward", "qap_mlp_gradients", "qap_mlp_train_step",
             "qap_orbit_outputs", "qap_warm_start", "qap_set_allocator", "qap_zlap_mapping",
-            "qap_set_annealing")
+            "qap_set_annealing", "qap_location_automorphisms")
 
 
 def lib():
@@ -120,6 +121,7 @@ def lib():
         L.qap_rlt2_init.argtypes = [_dp, _dp, _dp, C.c_int, C.POINTER(QapParams), C.POINTER(C.c_void_p)]
         L.qap_destroy.argtypes = [C.c_void_p]
         L.qap_set_annealing.argtypes = [C.c_void_p, C.c_void_p]
+        L.qap_location_automorphisms.argtypes = [C.c_int, _dp, _dp, C.c_int, C.c_void_p, C.POINTER(C.c_int)]
         L.qap_zlap_mapping.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                        C.POINTER(C.c_double)]
         L.qap_dual_ascent.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, C.POINTER(QapDaStats)]
@@ -339,9 +341,9 @@ class DualAscent:
         _check(lib().qap_set_stream(self.h, C.c_void_p(stream_handle)), self.h)
 
     def bnb_solve(self, batch=256, node_iters=100, window=25, root_iters=0, min_improve=2e-4,
-                  ub0=float("inf"), enum_below=3, rule=3, depth_cap=0):
+                  ub0=float("inf"), enum_below=3, rule=3, depth_cap=0, symmetry=0):
         p = QapBnbParams(batch, node_iters, window, root_iters, min_improve, ub0, enum_below, rule,
-                         depth_cap)
+                         depth_cap, symmetry)
         perm = np.zeros(self.n, dtype=np.int32)
         obj = C.c_double(0.0)
         st = QapBnbStats()
@@ -349,7 +351,8 @@ class DualAscent:
                                    C.byref(st)), self.h)
         return obj.value, perm, {"nodes": st.nodes, "da_iters": st.da_iters,
                                  "batches": st.batches, "enumerated": st.enumerated,
-                                 "seconds": st.seconds}
+                                 "seconds": st.seconds, "symmetric_skipped": st.symmetric_skipped,
+                                 "automorphisms": st.automorphisms}
 
 
     # ---- multipliers and the learned warm start ---------------------------
@@ -565,3 +568,16 @@ def tile_index(n: int, i: int, p: int, j: int, q: int) -> int:
     jp = j - (j > i)
     qp = q - (q > p)
     return ((i * n + p) * (n - 1) + jp) * (n - 1) + qp
+
+
+def location_automorphisms(D, B=None, cap: int = 4096) -> np.ndarray:
+    """Location permutations keeping D (and B's columns): rows of the result,
+    identity first (host computation in the library)."""
+    D = _f64(D)
+    n = D.shape[0]
+    Bp = None if B is None else _f64(B)
+    out = np.zeros((cap, n), dtype=np.int32)
+    cnt = C.c_int(0)
+    _check(lib().qap_location_automorphisms(n, _dptr(D), None if Bp is None else _dptr(Bp), int(cap),
+                                            C.c_void_p(out.ctypes.data), C.byref(cnt)))
+    return out[:cnt.value].copy()

@@ -67,9 +67,92 @@ std::vector<int> rule3_order(int n, const double *F)
     return order;
 }
 
+// Location automorphisms for the symmetry elimination of Section 4 (grid
+// instances): permutations sigma of the locations with D[sigma p][sigma q] =
+// D[p][q] for all p, q and B[i][sigma p] = B[i][p] for all i, p, so that
+// placing every facility at sigma of its location keeps the cost.  Depth-
+// first over p = 0, 1, ... with candidates of equal sorted row, sorted column
+// and B column; each permutation found satisfies the equalities exactly.
+// Stops after `cap` permutations or a step budget, so on a highly symmetric
+// D it may return a subset (the identity first): any subset of exact
+// automorphisms keeps the elimination exact.
+std::vector<std::vector<int>> location_automorphisms(int n, const double *D, const double *B, int cap)
+{
+    std::vector<std::vector<double>> sig(n);
+    for (int p = 0; p < n; ++p) {
+        std::vector<double> row(D + (size_t)p * n, D + (size_t)p * n + n), col(n), bc(n);
+        for (int q = 0; q < n; ++q) col[q] = D[(size_t)q * n + p];
+        for (int i = 0; i < n; ++i) bc[i] = B ? B[(size_t)i * n + p] : 0.0;
+        std::sort(row.begin(), row.end());
+        std::sort(col.begin(), col.end());
+        sig[p].push_back(D[(size_t)p * n + p]);
+        sig[p].insert(sig[p].end(), row.begin(), row.end());
+        sig[p].insert(sig[p].end(), col.begin(), col.end());
+        sig[p].insert(sig[p].end(), bc.begin(), bc.end());  // B column exactly, not sorted
+    }
+    std::vector<std::vector<int>> cand(n);
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q)
+            if (sig[q] == sig[p]) cand[p].push_back(q);
+    std::vector<std::vector<int>> out;
+    std::vector<int> sigma(n, -1), used(n, 0);
+    long long steps = 0;
+    const long long budget = 4000000;
+    // iterative depth-first search: pos[k] = next candidate index for p = k
+    std::vector<int> pos(n + 1, 0);
+    int k = 0;
+    while (k >= 0 && (int)out.size() < cap && steps < budget) {
+        if (k == n) {
+            out.push_back(sigma);
+            --k;
+            used[sigma[k]] = 0;
+            sigma[k] = -1;
+            continue;
+        }
+        bool placed = false;
+        while (pos[k] < (int)cand[k].size()) {
+            const int q = cand[k][pos[k]++];
+            ++steps;
+            if (used[q]) continue;
+            bool ok = D[(size_t)q * n + q] == D[(size_t)k * n + k];
+            for (int t = 0; ok && t < k; ++t)
+                ok = D[(size_t)q * n + sigma[t]] == D[(size_t)k * n + t] &&
+                     D[(size_t)sigma[t] * n + q] == D[(size_t)t * n + k];
+            if (!ok) continue;
+            sigma[k] = q;
+            used[q] = 1;
+            placed = true;
+            break;
+        }
+        if (placed) {
+            ++k;
+            if (k < n) pos[k] = 0;
+        } else {
+            pos[k] = 0;
+            --k;
+            if (k >= 0) {
+                used[sigma[k]] = 0;
+                sigma[k] = -1;
+            }
+        }
+    }
+    return out;
+}
+
 }  // namespace
 
 extern "C" {
+
+int qap_location_automorphisms(int n, const double *D, const double *B, int cap, int32_t *out, int *count)
+{
+    if (n < 1 || n > 64 || !D || cap < 1 || !out || !count) return fail(nullptr, QAP_EINVAL, "bad arguments");
+    const auto g = location_automorphisms(n, D, B, cap);
+    for (size_t a = 0; a < g.size(); ++a)
+        for (int p = 0; p < n; ++p) out[a * n + p] = g[a][p];
+    *count = (int)g.size();
+    return QAP_OK;
+}
+
 
 int qap_fold_child(qap_handle h, int l, int s, qap_handle *child)
 {
@@ -382,15 +465,23 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
         P.enum_below = 3;
         P.rule = 3;
         P.depth_cap = 0;
+        P.symmetry = 0;
     }
     if (P.batch < 1 || P.node_iters < 1 || P.window < 0 || P.window > 1000 || P.enum_below < 3 ||
-        !(P.min_improve >= 0.0) || P.rule != 3 || P.depth_cap < 0)
+        !(P.min_improve >= 0.0) || P.rule != 3 || P.depth_cap < 0 || P.symmetry < 0 || P.symmetry > 1)
         return fail(h, QAP_EINVAL, "bad branch-and-bound parameters");
     if (P.root_iters <= 0) P.root_iters = P.node_iters;
     const int n = h->n;
     if (n > 24) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound supports n <= 24");
     auto t0 = std::chrono::steady_clock::now();
     const std::vector<int> order = rule3_order(n, h->hF.data());
+    // symmetry elimination: the non-identity location automorphisms
+    std::vector<std::vector<int>> autos;
+    if (P.symmetry) {
+        autos = location_automorphisms(n, h->hD.data(), h->hB.data(), 4096);
+        if (!autos.empty()) autos.erase(autos.begin());  // the identity
+    }
+    long long sym_skipped = 0;
     const bool integer_data = h->integer_data;
     double UB = P.ub0;
     std::vector<int> best(n, -1);
@@ -526,8 +617,25 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
                 rc = fail(h, QAP_EDEVICE, "reading pi_x failed");
                 break;
             }
+            // automorphisms that keep every placed facility where it is: a
+            // child whose location one of them maps lower is equivalent to
+            // that lower child (same costs below it) and is not built
+            std::vector<const std::vector<int> *> stab;
+            for (const auto &a : autos) {
+                bool fixes = true;
+                for (int i = 0; fixes && i < n; ++i)
+                    if (nd.fixed[i] >= 0 && a[nd.fixed[i]] != nd.fixed[i]) fixes = false;
+                if (fixes) stab.push_back(&a);
+            }
             std::vector<Node> kids;
             for (int s = 0; s < nl; ++s) {
+                bool dominated = false;
+                for (const auto *a : stab)
+                    if ((*a)[nd.loc[s]] < nd.loc[s]) dominated = true;
+                if (dominated) {
+                    ++sym_skipped;
+                    continue;
+                }
                 const double lbc = sv[b].lb + pxr[s];
                 if (fathomed_host(lbc, UB, integer_data)) continue;
                 Node k;
@@ -565,6 +673,8 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
         st->batches = batches;
         st->enumerated = enumerated;
         st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        st->symmetric_skipped = sym_skipped;
+        st->automorphisms = (long long)autos.size() + 1;
     }
     return QAP_OK;
 }

@@ -187,3 +187,31 @@ def test_batched_lane_counts_are_tuned(tmp_path, monkeypatch):
         m = int(k.split("/m")[1].split("/")[0])
         assert cols == 1 and us > 0.0
         assert (lanes == -1 and m <= 32) or (lanes in (8, 16, 32, 64) and lanes >= m)
+
+
+@pytest.mark.parametrize("inst", [I.grid_n8(), I.grid_instance(9, 3, 3, 0.4, 1, 10, 2)], ids=lambda x: x.name)
+def test_bnb_symmetry_elimination_keeps_the_optimum(inst):
+    """Grid instances (Section 4's symmetry elimination): with forced
+    branching the optimum equals brute force with and without the
+    elimination, and the elimination builds fewer nodes."""
+    F, D, Bm = inst.arrays()
+    opt, _ = O.bruteforce(F, D, Bm)
+    h = B.DualAscent(F, D, Bm)
+    res = {}
+    for sym in (0, 1):
+        obj, perm, st = h.bnb_solve(node_iters=2, window=0, symmetry=sym)
+        assert obj == opt and O.qap_cost(F, D, Bm, perm) == opt
+        res[sym] = st
+    assert res[1]["automorphisms"] >= 4 and res[1]["symmetric_skipped"] > 0
+    assert res[0]["symmetric_skipped"] == 0
+    assert res[1]["nodes"] + res[1]["enumerated"] < res[0]["nodes"] + res[0]["enumerated"]
+
+
+def test_bnb_symmetry_elimination_grid_n12():
+    F, D, Bm = I.grid_instance(12, 3, 4, 0.4, 1, 9, 5).arrays()
+    h = B.DualAscent(F, D, Bm)
+    a = h.bnb_solve(node_iters=4)
+    b = h.bnb_solve(node_iters=4, symmetry=1)
+    assert a[0] == b[0]
+    assert O.qap_cost(F, D, Bm, b[1]) == b[0]
+    assert b[2]["nodes"] <= a[2]["nodes"]
