@@ -23,7 +23,8 @@ iterations of F1 and F2 with and without Type 4 annealing steps.
 `time_to_bound` compares 100 cold iterations with the learned warm start
 (trained weights from train_warm.py) reaching the same bound; its
 `mlp_roofline` gives the inference kernel's TFLOP/s against the bf16 MFMA
-peak.  `bnb` times branch-and-bound at n = 14 and 18.  `cpu_baseline` times
+peak.  `bnb` times branch-and-bound at n = 14 and 18 (dense) and on a 4x4 grid
+(n = 16) with and without symmetry elimination.  `cpu_baseline` times
 the CPU oracle (all OpenMP threads) on a
 bounded sample (about 10 s of iterations) of the same workload.
 """
@@ -257,14 +258,17 @@ def variant_legs(inst, steps: int, warmup: int, full_trace, cold_iters: int, str
 def bnb_leg():
     """Branch-and-bound: the n = 14 dense instance with forced branching (4
     iterations per node, batches of up to 256 nodes of mixed depth) and with
-    the default settings (the root bound closes it), and the n = 18 dense
-    instance (seed 0) with the default settings."""
+    the default settings (the root bound closes it), the n = 18 dense
+    instance (seed 0) with the default settings, and a 4x4 grid instance
+    (n = 16) with and without Section 4's symmetry elimination."""
     from paper_1710_03732_amd import binding, instances as insts
 
     out = {}
     runs = (("dense_n14_branching", insts.dense_n14(), dict(batch=256, node_iters=4, window=25)),
             ("dense_n14_default", insts.dense_n14(), {}),
-            ("dense_n18_default", insts.dense_instance(18, 0), {}))
+            ("dense_n18_default", insts.dense_instance(18, 0), {}),
+            ("grid4x4_n16_default", insts.grid_instance(16, 4, 4, 0.4, 1, 9, 1), {}),
+            ("grid4x4_n16_symmetry", insts.grid_instance(16, 4, 4, 0.4, 1, 9, 1), dict(symmetry=1)))
     for label, inst, kw in runs:
         F, D, B = inst.arrays()
         h = binding.DualAscent(F, D, B)
@@ -274,7 +278,8 @@ def bnb_leg():
         h.close()
         out[label] = {"optimum": obj, "seconds": el, "nodes": st["nodes"], "batches": st["batches"],
                       "da_iterations": st["da_iters"], "nodes_per_s": st["nodes"] / el,
-                      "node_iterations_per_s": st["da_iters"] / el, **kw}
+                      "node_iterations_per_s": st["da_iters"] / el,
+                      "symmetric_skipped": st["symmetric_skipped"], **kw}
     return out
 
 
