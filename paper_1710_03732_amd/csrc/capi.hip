@@ -231,7 +231,7 @@ hipError_t launch_sweep(qap_ctx *h)
         const int nb = (h->n + SB - 1) / SB;
         const unsigned blocks = groups8 * 8u * (unsigned)(nb * nb * nb);
         if (h->prm.slow) {
-            hipLaunchKernelGGL((k_sweep<true, false, false, true>), dim3(blocks), dim3(256), 0, h->stream, h->Z,
+            hipLaunchKernelGGL((k_sweep<true, false, false, true>), dim3(blocks), dim3(kSweepThreads), 0, h->stream, h->Z,
                                h->Py, h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, h->Vt);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             const long long work = std::max<long long>(h->T, (long long)h->n * h->n);
@@ -241,13 +241,13 @@ hipError_t launch_sweep(qap_ctx *h)
             return hipGetLastError();
         }
         if (h->half)
-            hipLaunchKernelGGL((k_sweep<false, true>), dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py,
+            hipLaunchKernelGGL((k_sweep<false, true>), dim3(blocks), dim3(kSweepThreads), 0, h->stream, h->Z, h->Py,
                                h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, (double *)nullptr);
         else if (h->Vt)
-            hipLaunchKernelGGL((k_sweep<true, false>), dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py,
+            hipLaunchKernelGGL((k_sweep<true, false>), dim3(blocks), dim3(kSweepThreads), 0, h->stream, h->Z, h->Py,
                                h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, h->Vt);
         else
-            hipLaunchKernelGGL((k_sweep<false, false>), dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py,
+            hipLaunchKernelGGL((k_sweep<false, false>), dim3(blocks), dim3(kSweepThreads), 0, h->stream, h->Z, h->Py,
                                h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, (double *)nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const long long work = std::max<long long>(h->T, (long long)h->n * h->n);  // x/y scaling
@@ -267,10 +267,10 @@ hipError_t launch_pool(qap_ctx *h)
     const int nb = (h->n + SB - 1) / SB;
     const unsigned blocks = groups8 * 8u * (unsigned)(nb * nb * nb);
     if (h->prm.slow)  // S2: the pooling moves the tracked multipliers too
-        hipLaunchKernelGGL((k_sweep<true, false, true>), dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py, h->Px,
+        hipLaunchKernelGGL((k_sweep<true, false, true>), dim3(blocks), dim3(kSweepThreads), 0, h->stream, h->Z, h->Py, h->Px,
                            h->triples, h->ntriples, h->n, nb, K, h->S, h->Vt);
     else
-        hipLaunchKernelGGL((k_sweep<false, false, true>), dim3(blocks), dim3(256), 0, h->stream, h->Z, h->Py,
+        hipLaunchKernelGGL((k_sweep<false, false, true>), dim3(blocks), dim3(kSweepThreads), 0, h->stream, h->Z, h->Py,
                            h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, (double *)nullptr);
     return hipGetLastError();
 }

@@ -148,6 +148,7 @@ constexpr int SB = 8;                       // cube edge
 constexpr int SB_Q = SB + 1;                // padded q pitch
 constexpr int SB_P = SB * SB_Q + 1;         // padded p pitch
 constexpr int SB_CUBE = SB * SB_P;          // doubles per staged member
+constexpr int kSweepThreads = 512;          // threads per sweep block
 
 __device__ __forceinline__ int cube_idx(int pl, int ql, int rl) { return pl * SB_P + ql * SB_Q + rl; }
 
@@ -175,7 +176,7 @@ __device__ __forceinline__ int cube_idx(int pl, int ql, int rl) { return pl * SB
 // on the full costs.  POOL with TRACK is S2's pooling: a changed entry's
 // multiplier moves by its old slack minus its new one.
 template <bool TRACK, bool HALF, bool POOL = false, bool SLOW = false>
-__global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const double *__restrict__ Py,
+__global__ __launch_bounds__(kSweepThreads) void k_sweep(double *__restrict__ Z, const double *__restrict__ Py,
                                                const double *__restrict__ Px,
                                                const int *__restrict__ triples, int ntriples, int n,
                                                int nb, SweepConsts K, const DevScalars *__restrict__ S,
@@ -201,7 +202,8 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
     const int X1[6] = {0, 0, 1, 1, 2, 2};
     const int X2[6] = {1, 2, 0, 2, 0, 1};
     const int X3[6] = {2, 1, 2, 0, 1, 0};
-    constexpr int PER = (SB * SB * SB) / 256;  // member elements per thread and member
+    constexpr int NT = kSweepThreads;
+    constexpr int PER = (SB * SB * SB) / NT;  // member elements per thread and member
     // pi_y of the block's tiles and pi_x of its (facility, location) pairs,
     // read once per block: member e's tile is fixed by its first two cube
     // coordinates (a1 along axis X1[e], a2 along X2[e]), its x parent by the
@@ -209,8 +211,8 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
     __shared__ double pys[6 * SB * SB];
     __shared__ double pxs[3 * SB];
 #pragma unroll
-    for (int rep = 0; rep < (POOL ? 0 : (6 * SB * SB + 255) / 256); ++rep) {
-        const int a = threadIdx.x + 256 * rep;
+    for (int rep = 0; rep < (POOL ? 0 : (6 * SB * SB + NT - 1) / NT); ++rep) {
+        const int a = threadIdx.x + NT * rep;
         if (a < 6 * SB * SB) {
             const int e = a / (SB * SB), a1 = (a / SB) % SB, a2 = a % SB;
             const int x1 = e >> 1, x2 = (0x102021 >> (4 * e)) & 0xf;  // X1[e], X2[e]
@@ -231,8 +233,8 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
     double pz[6][PER];
     // this thread's member-major elements (runs along each member's own last
     // location axis); pi_z goes to the cube for the orbit phase.  Element
-    // (a1, a2, a3) of thread u = tid + 256 w has a1 = tid/64 + 4 w, the same
-    // for the whole wave, so the tile row (f1, l1, f2) and the z row are a
+    // (a1, a2, a3) of thread u = tid + NT w has a1 = tid/64 + (NT/64) w, the
+    // same for the whole wave, so the tile row (f1, l1, f2) and the z row are a
     // scalar offset; only l2' * m^2 + col varies across the lanes (a 24-bit
     // product instead of 64-bit tile arithmetic per element).
     const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -242,7 +244,7 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
         if (HALF && (e == 2 || e == 4 || e == 5)) continue;
 #pragma unroll
         for (int w = 0; w < PER; ++w) {
-            const int a1 = wid + (256 / (SB * SB)) * w;
+            const int a1 = wid + (NT / (SB * SB)) * w;
             int loc[3];
             loc[X1[e]] = base[X1[e]] + a1;
             loc[X2[e]] = base[X2[e]] + a2;
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
     // partners' g), canonical order
 #pragma unroll
     for (int w = 0; w < PER; ++w) {
-        const int u = threadIdx.x + 256 * w;
+        const int u = threadIdx.x + NT * w;
         const int rl = u % SB, ql = (u / SB) % SB, pl = u / (SB * SB);
         const int p = base[0] + pl, q = base[1] + ql, r = base[2] + rl;
         if (p < n && q < n && r < n && p != q && p != r && q != r) {
@@ -341,7 +343,7 @@ __global__ __launch_bounds__(256) void k_sweep(double *__restrict__ Z, const dou
                 if (TRACK && POOL) {
                     Vt[za[e][w]] = Vt[za[e][w]] + (pz[e][w] - share);
                 } else if (TRACK) {
-                    const int u = threadIdx.x + 256 * w;
+                    const int u = threadIdx.x + NT * w;
                     const int a2 = (u / SB) % SB, a1 = u / (SB * SB);
                     const double y = pys[(e * SB + a1) * SB + a2];
                     const double x = pxs[X1[e] * SB + a1];
