@@ -284,6 +284,7 @@ int qap_track(qap_handle h, int on)
         return fail(h, QAP_EUNSUPPORTED, "multiplier tracking does not follow the F2 pooling");
     if (h->sa_on && on) return fail(h, QAP_EUNSUPPORTED, "multiplier tracking does not follow Type 4 steps");
     if (h->prm.slow && !on) return fail(h, QAP_EUNSUPPORTED, "an S1 handle keeps its multipliers tracked");
+    if (h->prm.slow && h->Vt) return QAP_OK;  // already on: its multipliers are the S1 state, keep them
     HIPCHK(h, hipStreamSynchronize(h->stream));
     if (!on) {
         dev_free(h, h->Vt);

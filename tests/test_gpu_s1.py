@@ -87,6 +87,9 @@ def test_s1_refusals():
             call()
         assert e.value.code == -5
     h.run(1)
+    v0, _ = h.multipliers()
+    h.track(True)  # a no-op on an S1 handle: its multipliers are its state
+    assert np.array_equal(h.multipliers()[0], v0)
     for bad in [B.half_params(slow=1)]:
         with pytest.raises(B.QapError) as e:
             B.DualAscent(F, D, Bm, params=bad)
