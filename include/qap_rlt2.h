@@ -395,8 +395,11 @@ const char *qap_last_error(qap_handle h);
 /* Start (on != 0: allocate, zero) or stop (0: free) tracking the multipliers
  * of the single-handle dual ascent.  Tracking costs T*m*m + T doubles of
  * device memory and one more read and write of that array per sweep.
- * Tracked handles are rejected by qap_batch_dual_ascent (QAP_ESTATE).
- * Errors: QAP_ENOMEM, QAP_EDEVICE. */
+ * Tracked handles are rejected by qap_batch_dual_ascent (QAP_ESTATE).  An
+ * S1/S2 handle tracks from its first iteration on (its multipliers are its
+ * state): on is then a no-op and off is refused.  HALF, F2 and annealing
+ * handles refuse tracking.  Errors: QAP_ENOMEM, QAP_EDEVICE,
+ * QAP_EUNSUPPORTED. */
 int qap_track(qap_handle h, int on);
 
 /* Device allocator for this handle's later allocations: tracking arrays
