@@ -54,6 +54,7 @@ struct qap_ctx {
     int zlap_waves = 1;  // waves per Z-LAP block
     bool zl_auto = false;     // mapping left to the autotuner (zlap_lanes = 0)
     bool half = false;        // HALF scheme: only the tiles with i < j are solved
+    int sweep_cb = 8;         // cube edge of the ascent sweep (sweep_cube)
     bool sa_on = false;       // Type 4 steps with annealing after each X-LAP
     SaConsts sa{};
     bool zl_tuned = false;    // the autotuner has chosen it
@@ -222,57 +223,68 @@ hipError_t launch_ylap(qap_ctx *h, int equalize)
     return launch_ylap_t<16, 4>(h, equalize);
 }
 
+// Cube edge of the sweep for size n: 10 when its cubes cover the n^3
+// locations with fewer slots left over than 8's (n = 9, 10, 17-20, 25-30,
+// 49, 50, 57-60), else 8.  A smaller edge (7 at n = 42) wastes no slots there
+// but measured slower: shorter runs per cache line and fewer waves per CU.
+int sweep_cube(int n)
+{
+    auto slots = [n](int cb) {
+        const long long c = (long long)((n + cb - 1) / cb) * cb;
+        return c * c * c;
+    };
+    return slots(10) < slots(8) ? 10 : 8;
+}
+
+template <int CB, bool TRACK, bool HALF, bool POOL, bool SLOW>
+hipError_t launch_sweep_cb(qap_ctx *h, const SweepConsts &K, double *Vt)
+{
+    const unsigned groups8 = (unsigned)((h->ntriples + 7) / 8);
+    const int nb = (h->n + CB - 1) / CB;
+    const unsigned blocks = groups8 * 8u * (unsigned)(nb * nb * nb);
+    hipLaunchKernelGGL((k_sweep<CB, TRACK, HALF, POOL, SLOW>), dim3(blocks), dim3(Cube<CB>::NT), 0, h->stream,
+                       h->Z, h->Py, h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, Vt);
+    return hipGetLastError();
+}
+
+template <bool TRACK, bool HALF, bool POOL, bool SLOW>
+hipError_t launch_sweep_k(qap_ctx *h, const SweepConsts &K, double *Vt)
+{
+    if (h->sweep_cb == 10) return launch_sweep_cb<10, TRACK, HALF, POOL, SLOW>(h, K, Vt);
+    return launch_sweep_cb<8, TRACK, HALF, POOL, SLOW>(h, K, Vt);
+}
+
 hipError_t launch_sweep(qap_ctx *h)
 {
     hipError_t e;
-    {
-        SweepConsts K{h->kz, h->okz, h->ky2, h->kx3, h->phi, 1.0 / 3.0};
-        const unsigned groups8 = (unsigned)((h->ntriples + 7) / 8);
-        const int nb = (h->n + SB - 1) / SB;
-        const unsigned blocks = groups8 * 8u * (unsigned)(nb * nb * nb);
-        if (h->prm.slow) {
-            hipLaunchKernelGGL((k_sweep<true, false, false, true>), dim3(blocks), dim3(kSweepThreads), 0, h->stream, h->Z,
-                               h->Py, h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, h->Vt);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            const long long work = std::max<long long>(h->T, (long long)h->n * h->n);
-            const unsigned sb = (unsigned)std::min<long long>((work + 255) / 256, 65535);
-            hipLaunchKernelGGL(k_slow_reset, dim3(sb), dim3(256), 0, h->stream, h->F, h->D, h->B, h->Xc, h->Yc,
-                               h->n, h->S);
-            return hipGetLastError();
-        }
-        if (h->half)
-            hipLaunchKernelGGL((k_sweep<false, true>), dim3(blocks), dim3(kSweepThreads), 0, h->stream, h->Z, h->Py,
-                               h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, (double *)nullptr);
-        else if (h->Vt)
-            hipLaunchKernelGGL((k_sweep<true, false>), dim3(blocks), dim3(kSweepThreads), 0, h->stream, h->Z, h->Py,
-                               h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, h->Vt);
-        else
-            hipLaunchKernelGGL((k_sweep<false, false>), dim3(blocks), dim3(kSweepThreads), 0, h->stream, h->Z, h->Py,
-                               h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, (double *)nullptr);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        const long long work = std::max<long long>(h->T, (long long)h->n * h->n);  // x/y scaling
-        const unsigned sb = (unsigned)std::min<long long>((work + 255) / 256, 65535);
-        hipLaunchKernelGGL(k_scale_xy, dim3(sb), dim3(256), 0, h->stream, h->Yc, h->Py, h->Xc, h->Px,
-                           h->T, h->n * h->n, h->oky, h->okx, h->S);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+    const SweepConsts K{h->kz, h->okz, h->ky2, h->kx3, h->phi, 1.0 / 3.0};
+    const long long work = std::max<long long>(h->T, (long long)h->n * h->n);
+    const unsigned sb = (unsigned)std::min<long long>((work + 255) / 256, 65535);
+    if (h->prm.slow) {
+        if ((e = launch_sweep_k<true, false, false, true>(h, K, h->Vt)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_slow_reset, dim3(sb), dim3(256), 0, h->stream, h->F, h->D, h->B, h->Xc, h->Yc, h->n,
+                           h->S);
+        return hipGetLastError();
     }
-    return hipSuccess;
+    if (h->half)
+        e = launch_sweep_k<false, true, false, false>(h, K, nullptr);
+    else if (h->Vt)
+        e = launch_sweep_k<true, false, false, false>(h, K, h->Vt);
+    else
+        e = launch_sweep_k<false, false, false, false>(h, K, nullptr);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scale_xy, dim3(sb), dim3(256), 0, h->stream, h->Yc, h->Py, h->Xc, h->Px, h->T, h->n * h->n,
+                       h->oky, h->okx, h->S);
+    return hipGetLastError();
 }
 
 // F2 pooling between the two Z-LAP solves (the sweep's transpose, POOL mode).
 hipError_t launch_pool(qap_ctx *h)
 {
-    SweepConsts K{h->kz, h->okz, h->ky2, h->kx3, h->phi, 1.0 / 3.0};
-    const unsigned groups8 = (unsigned)((h->ntriples + 7) / 8);
-    const int nb = (h->n + SB - 1) / SB;
-    const unsigned blocks = groups8 * 8u * (unsigned)(nb * nb * nb);
+    const SweepConsts K{h->kz, h->okz, h->ky2, h->kx3, h->phi, 1.0 / 3.0};
     if (h->prm.slow)  // S2: the pooling moves the tracked multipliers too
-        hipLaunchKernelGGL((k_sweep<true, false, true>), dim3(blocks), dim3(kSweepThreads), 0, h->stream, h->Z, h->Py, h->Px,
-                           h->triples, h->ntriples, h->n, nb, K, h->S, h->Vt);
-    else
-        hipLaunchKernelGGL((k_sweep<false, false, true>), dim3(blocks), dim3(kSweepThreads), 0, h->stream, h->Z, h->Py,
-                           h->Px, h->triples, h->ntriples, h->n, nb, K, h->S, (double *)nullptr);
-    return hipGetLastError();
+        return launch_sweep_k<true, false, true, false>(h, K, h->Vt);
+    return launch_sweep_k<false, false, true, false>(h, K, nullptr);
 }
 
 // Z-LAP phase: one solve (F1), or solve, pool, solve (F2 from t = 1 on).
@@ -473,6 +485,7 @@ int create_ctx(int n, const double *F, const double *D, const double *B, const q
     h->integer_data = integer_all(F, n) && integer_all(D, n) && integer_all(h->hB.data(), n) &&
                       std::fabs(offset) < 9.0e15 && offset == std::floor(offset);
     derive_constants(h);
+    h->sweep_cb = sweep_cube(n);
     h->half = prm.scheme == QAP_SCHEME_HALF;
     // HALF solves the upper tiles with the scalar solver (one LAP per wave)
     pick_zlap(h->m, h->half ? -1 : prm.zlap_lanes, prm.zlap_cols, h->zl, h->zc);

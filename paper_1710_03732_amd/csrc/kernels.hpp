@@ -136,21 +136,33 @@ __global__ void k_init_xy(const double *__restrict__ F, const double *__restrict
 //
 // For one facility triple the six members form six axis-permuted copies of a
 // 3-D array over the locations (p,q,r): member e is contiguous along its
-// third location.  A block takes one triple and one SB^3 cube of locations
-// and transposes through LDS: load phase (each member read as runs of SB
+// third location.  A block takes one triple and one CB^3 cube of locations
+// and transposes through LDS: load phase (each member read as runs of CB
 // contiguous doubles along its own last axis, pi_z staged in a padded
 // [p][q][r] layout, pi_y / pi_x of the block's tiles and pairs read once),
 // orbit phase (one thread per orbit forms the six g and the shares), store
 // phase (runs again).  Block numbering keeps all cubes of one triple on one
 // XCD, back to back, so the partial cache lines at run ends merge in that
 // XCD's L2.
-constexpr int SB = 8;                       // cube edge
+constexpr int SB = 8;                       // cube edge of the warm-start writer and batched sweep
 constexpr int SB_Q = SB + 1;                // padded q pitch
 constexpr int SB_P = SB * SB_Q + 1;         // padded p pitch
 constexpr int SB_CUBE = SB * SB_P;          // doubles per staged member
-constexpr int kSweepThreads = 512;          // threads per sweep block
 
 __device__ __forceinline__ int cube_idx(int pl, int ql, int rl) { return pl * SB_P + ql * SB_Q + rl; }
+
+// The ascent sweep's cube, edge CB chosen per n (8, or 10 where its cubes
+// leave fewer slots outside the instance): padded LDS pitches, one thread
+// per orbit, whole waves.
+template <int CB>
+struct Cube {
+    static constexpr int Q = CB + 1;                 // padded q pitch
+    static constexpr int P = CB * Q + 1;             // padded p pitch
+    static constexpr int SIZE = CB * P;              // doubles per staged member
+    static constexpr int ORB = CB * CB * CB;         // orbits per block
+    static constexpr int NT = (ORB + 63) / 64 * 64;  // threads per block
+    __device__ static __forceinline__ int idx(int pl, int ql, int rl) { return pl * P + ql * Q + rl; }
+};
 
 //
 // With TRACK the sweep also accumulates each entry's Lagrange multiplier
@@ -175,8 +187,8 @@ __device__ __forceinline__ int cube_idx(int pl, int ql, int rl) { return pl * SB
 // moves as above and z is rebuilt as its S-form cost, -v (D = 0), for LAPs
 // on the full costs.  POOL with TRACK is S2's pooling: a changed entry's
 // multiplier moves by its old slack minus its new one.
-template <bool TRACK, bool HALF, bool POOL = false, bool SLOW = false>
-__global__ __launch_bounds__(kSweepThreads) void k_sweep(double *__restrict__ Z, const double *__restrict__ Py,
+template <int CB, bool TRACK, bool HALF, bool POOL = false, bool SLOW = false>
+__global__ __launch_bounds__(Cube<CB>::NT) void k_sweep(double *__restrict__ Z, const double *__restrict__ Py,
                                                const double *__restrict__ Px,
                                                const int *__restrict__ triples, int ntriples, int n,
                                                int nb, SweepConsts K, const DevScalars *__restrict__ S,
@@ -184,14 +196,15 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(double *__restrict__ Z,
 {
     if (S->stopped) return;
     // g_e staged per orbit position; the orbit phase overwrites it with phi*sum
-    __shared__ double gs[6 * SB_CUBE];
+    using C = Cube<CB>;
+    __shared__ double gs[6 * C::SIZE];
     const unsigned b = blockIdx.x;
     const unsigned xcd = b & 7u, s = b >> 3;
     const unsigned nb3 = (unsigned)(nb * nb * nb);
     const int tri = (int)((s / nb3) * 8u + xcd);
     if (tri >= ntriples) return;
     const int sub = (int)(s % nb3);
-    const int base[3] = {(sub / (nb * nb)) * SB, ((sub / nb) % nb) * SB, (sub % nb) * SB};
+    const int base[3] = {(sub / (nb * nb)) * CB, ((sub / nb) % nb) * CB, (sub % nb) * CB};
     const int packed = triples[tri];
     const int fi = packed & 0xff, fj = (packed >> 8) & 0xff, fk = (packed >> 16) & 0xff;
     const int m = n - 2;
@@ -202,19 +215,18 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(double *__restrict__ Z,
     const int X1[6] = {0, 0, 1, 1, 2, 2};
     const int X2[6] = {1, 2, 0, 2, 0, 1};
     const int X3[6] = {2, 1, 2, 0, 1, 0};
-    constexpr int NT = kSweepThreads;
-    constexpr int PER = (SB * SB * SB) / NT;  // member elements per thread and member
+    constexpr int NT = C::NT;
     // pi_y of the block's tiles and pi_x of its (facility, location) pairs,
     // read once per block: member e's tile is fixed by its first two cube
     // coordinates (a1 along axis X1[e], a2 along X2[e]), its x parent by the
     // first.  Entries outside the instance hold 0 and are never used.
-    __shared__ double pys[6 * SB * SB];
-    __shared__ double pxs[3 * SB];
+    __shared__ double pys[6 * CB * CB];
+    __shared__ double pxs[3 * CB];
 #pragma unroll
-    for (int rep = 0; rep < (POOL ? 0 : (6 * SB * SB + NT - 1) / NT); ++rep) {
+    for (int rep = 0; rep < (POOL ? 0 : (6 * CB * CB + NT - 1) / NT); ++rep) {
         const int a = threadIdx.x + NT * rep;
-        if (a < 6 * SB * SB) {
-            const int e = a / (SB * SB), a1 = (a / SB) % SB, a2 = a % SB;
+        if (a < 6 * CB * CB) {
+            const int e = a / (CB * CB), a1 = (a / CB) % CB, a2 = a % CB;
             const int x1 = e >> 1, x2 = (0x102021 >> (4 * e)) & 0xf;  // X1[e], X2[e]
             const int f1 = x1 == 0 ? fi : (x1 == 1 ? fj : fk), f2 = x2 == 0 ? fi : (x2 == 1 ? fj : fk);
             const int l1 = (x1 == 0 ? base[0] : (x1 == 1 ? base[1] : base[2])) + a1;
@@ -222,35 +234,38 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(double *__restrict__ Z,
             pys[a] = (l1 < n && l2 < n && l1 != l2) ? Py[tile_of(n, f1, l1, f2, l2)] : 0.0;
         }
     }
-    if (!POOL && threadIdx.x < 3 * SB) {
-        const int x = threadIdx.x / SB, l = (x == 0 ? base[0] : (x == 1 ? base[1] : base[2])) + threadIdx.x % SB;
+    if (!POOL && threadIdx.x < 3 * CB) {
+        const int x = threadIdx.x / CB, l = (x == 0 ? base[0] : (x == 1 ? base[1] : base[2])) + threadIdx.x % CB;
         const int f = x == 0 ? fi : (x == 1 ? fj : fk);
         pxs[threadIdx.x] = l < n ? Px[f * n + l] : 0.0;
     }
+    constexpr int PER = 1;  // one orbit per thread
     long long za[6][PER];
     int li[6][PER];
     bool ok[6][PER];
     double pz[6][PER];
     // this thread's member-major elements (runs along each member's own last
-    // location axis); pi_z goes to the cube for the orbit phase.  Element
-    // (a1, a2, a3) of thread u = tid + NT w has a1 = tid/64 + (NT/64) w, the
-    // same for the whole wave, so the tile row (f1, l1, f2) and the z row are a
-    // scalar offset; only l2' * m^2 + col varies across the lanes (a 24-bit
-    // product instead of 64-bit tile arithmetic per element).
-    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int a2 = (int)(threadIdx.x >> 3) & (SB - 1), a3 = (int)threadIdx.x & (SB - 1);
+    // location axis); pi_z goes to the cube for the orbit phase.  Thread
+    // tid < CB^3 takes cube coordinates (a1, a2, a3) = (tid / CB^2,
+    // tid / CB % CB, tid % CB); with CB = 8 a1 is the same for the whole
+    // wave, so the tile row (f1, l1, f2) and the z row are a scalar offset.
+    // Only l2' * m^2 + col always varies across the lanes (a 24-bit product).
+    const bool live = (int)threadIdx.x < C::ORB;
+    const int a1w = (CB * CB == 64) ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))
+                                    : (int)threadIdx.x / (CB * CB);
+    const int a2 = ((int)threadIdx.x / CB) % CB, a3 = (int)threadIdx.x % CB;
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
         if (HALF && (e == 2 || e == 4 || e == 5)) continue;
 #pragma unroll
         for (int w = 0; w < PER; ++w) {
-            const int a1 = wid + (NT / (SB * SB)) * w;
+            const int a1 = a1w;
             int loc[3];
             loc[X1[e]] = base[X1[e]] + a1;
             loc[X2[e]] = base[X2[e]] + a2;
             loc[X3[e]] = base[X3[e]] + a3;
             const int l1 = loc[X1[e]], l2 = loc[X2[e]], l3 = loc[X3[e]];
-            const bool v = l1 < n && l2 < n && l3 < n && l1 != l2 && l1 != l3 && l2 != l3;
+            const bool v = live && l1 < n && l2 < n && l3 < n && l1 != l2 && l1 != l3 && l2 != l3;
             const int f1 = F1[e], f2 = F2[e], f3 = F3[e];
             const int f2p = f2 - (f2 > f1);
             const int row = f3 - (f3 > f1) - (f3 > f2);
@@ -259,7 +274,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(double *__restrict__ Z,
             const int col = l3 - (l3 > l1) - (l3 > l2);
             ok[e][w] = v;
             za[e][w] = v ? zrow + (long long)(__umul24((unsigned)l2p, (unsigned)mm) + col) : 0;
-            li[e][w] = cube_idx(loc[0] - base[0], loc[1] - base[1], loc[2] - base[2]);
+            li[e][w] = C::idx(loc[0] - base[0], loc[1] - base[1], loc[2] - base[2]);
             pz[e][w] = Z[za[e][w]];
         }
     }
@@ -268,7 +283,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(double *__restrict__ Z,
         if (HALF && (e == 2 || e == 4 || e == 5)) continue;
 #pragma unroll
         for (int w = 0; w < PER; ++w)
-            if (ok[e][w]) gs[e * SB_CUBE + li[e][w]] = pz[e][w];
+            if (ok[e][w]) gs[e * C::SIZE + li[e][w]] = pz[e][w];
     }
     __syncthreads();
     // orbit phase: g of the six members, then phi * (left fold of the
@@ -276,17 +291,17 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(double *__restrict__ Z,
 #pragma unroll
     for (int w = 0; w < PER; ++w) {
         const int u = threadIdx.x + NT * w;
-        const int rl = u % SB, ql = (u / SB) % SB, pl = u / (SB * SB);
+        const int rl = u % CB, ql = (u / CB) % CB, pl = u / (CB * CB);
         const int p = base[0] + pl, q = base[1] + ql, r = base[2] + rl;
-        if (p < n && q < n && r < n && p != q && p != r && q != r) {
-            const int c = cube_idx(pl, ql, rl);
+        if (u < C::ORB && p < n && q < n && r < n && p != q && p != r && q != r) {
+            const int c = C::idx(pl, ql, rl);
             if (POOL) {
                 double v[6], slack = 0.0;
                 int nbasic = 0;
                 bool first = true;
 #pragma unroll
                 for (int e = 0; e < 6; ++e) {
-                    v[e] = gs[e * SB_CUBE + c];
+                    v[e] = gs[e * C::SIZE + c];
                     if (v[e] > 0.0) {
                         slack = first ? v[e] : slack + v[e];
                         first = false;
@@ -297,7 +312,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(double *__restrict__ Z,
                 if (nbasic != 0 && nbasic != 6) {
                     const double share = slack / (double)nbasic;
 #pragma unroll
-                    for (int e = 0; e < 6; ++e) gs[e * SB_CUBE + c] = v[e] > 0.0 ? 0.0 : v[e] + share;
+                    for (int e = 0; e < 6; ++e) gs[e * C::SIZE + c] = v[e] > 0.0 ? 0.0 : v[e] + share;
                 }
                 continue;
             }
@@ -305,26 +320,26 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(double *__restrict__ Z,
             double g[6];
 #pragma unroll
             for (int e = 0; e < 6; ++e) {
-                const double y = pys[(e * SB + lc[X1[e]]) * SB + lc[X2[e]]];
-                const double x = pxs[X1[e] * SB + lc[X1[e]]];
+                const double y = pys[(e * CB + lc[X1[e]]) * CB + lc[X2[e]]];
+                const double x = pxs[X1[e] * CB + lc[X1[e]]];
                 if (HALF && (e == 2 || e == 4 || e == 5))
                     g[e] = (1.0 * 0.0 + K.ky2 * y) + K.kx3 * x;
                 else
-                    g[e] = (K.kz * gs[e * SB_CUBE + c] + K.ky2 * y) + K.kx3 * x;
+                    g[e] = (K.kz * gs[e * C::SIZE + c] + K.ky2 * y) + K.kx3 * x;
             }
             if (HALF) {
                 const double low = K.phil * ((g[2] + g[4]) + g[5]);
-                gs[0 * SB_CUBE + c] = K.phi * (g[1] + g[3]) + low;
-                gs[1 * SB_CUBE + c] = K.phi * (g[0] + g[3]) + low;
-                gs[3 * SB_CUBE + c] = K.phi * (g[0] + g[1]) + low;
+                gs[0 * C::SIZE + c] = K.phi * (g[1] + g[3]) + low;
+                gs[1 * C::SIZE + c] = K.phi * (g[0] + g[3]) + low;
+                gs[3 * C::SIZE + c] = K.phi * (g[0] + g[1]) + low;
                 continue;
             }
-            gs[0 * SB_CUBE + c] = K.phi * ((((g[1] + g[2]) + g[3]) + g[4]) + g[5]);
-            gs[1 * SB_CUBE + c] = K.phi * ((((g[0] + g[2]) + g[3]) + g[4]) + g[5]);
-            gs[2 * SB_CUBE + c] = K.phi * ((((g[0] + g[1]) + g[3]) + g[4]) + g[5]);
-            gs[3 * SB_CUBE + c] = K.phi * ((((g[0] + g[1]) + g[2]) + g[4]) + g[5]);
-            gs[4 * SB_CUBE + c] = K.phi * ((((g[0] + g[1]) + g[2]) + g[3]) + g[5]);
-            gs[5 * SB_CUBE + c] = K.phi * ((((g[0] + g[1]) + g[2]) + g[3]) + g[4]);
+            gs[0 * C::SIZE + c] = K.phi * ((((g[1] + g[2]) + g[3]) + g[4]) + g[5]);
+            gs[1 * C::SIZE + c] = K.phi * ((((g[0] + g[2]) + g[3]) + g[4]) + g[5]);
+            gs[2 * C::SIZE + c] = K.phi * ((((g[0] + g[1]) + g[3]) + g[4]) + g[5]);
+            gs[3 * C::SIZE + c] = K.phi * ((((g[0] + g[1]) + g[2]) + g[4]) + g[5]);
+            gs[4 * C::SIZE + c] = K.phi * ((((g[0] + g[1]) + g[2]) + g[3]) + g[5]);
+            gs[5 * C::SIZE + c] = K.phi * ((((g[0] + g[1]) + g[2]) + g[3]) + g[4]);
         }
     }
     __syncthreads();
@@ -335,7 +350,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(double *__restrict__ Z,
 #pragma unroll
         for (int w = 0; w < PER; ++w)
             if (ok[e][w]) {
-                const double share = gs[e * SB_CUBE + li[e][w]];
+                const double share = gs[e * C::SIZE + li[e][w]];
                 // POOL leaves most orbits as they are (no zero slack among
                 // the six): store only entries whose bits changed
                 if (POOL && __double_as_longlong(share) == __double_as_longlong(pz[e][w])) continue;
@@ -344,9 +359,9 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(double *__restrict__ Z,
                     Vt[za[e][w]] = Vt[za[e][w]] + (pz[e][w] - share);
                 } else if (TRACK) {
                     const int u = threadIdx.x + NT * w;
-                    const int a2 = (u / SB) % SB, a1 = u / (SB * SB);
-                    const double y = pys[(e * SB + a1) * SB + a2];
-                    const double x = pxs[X1[e] * SB + a1];
+                    const int a2 = (u / CB) % CB, a1 = u / (CB * CB);
+                    const double y = pys[(e * CB + a1) * CB + a2];
+                    const double x = pxs[X1[e] * CB + a1];
                     const double g = (K.kz * pz[e][w] + K.ky2 * y) + K.kx3 * x;
                     const double vnew = Vt[za[e][w]] + (g - share);
                     Vt[za[e][w]] = vnew;
