@@ -175,7 +175,10 @@ template <int H>
 hipError_t launch_zlap_s(qap_ctx *h)
 {
     const int m = h->m;
-    const size_t per = ((size_t)m * m + 2 * m) * sizeof(double) * H;
+    // one LAP: tile, row potentials and one int per column (the solver's
+    // proposal and matching slots share it); two LAPs: also v for the epilogue
+    const size_t per = H == 1 ? ((size_t)m * m + m) * sizeof(double) + ((size_t)m * sizeof(int) + 7) / 8 * 8
+                              : ((size_t)m * m + 2 * m) * sizeof(double) * H;
     // HALF: one block per tile with i < j (half of them; H = 1 only)
     const int half = (H == 1 && h->half) ? 1 : 0;
     const long long blocks = half ? h->T / 2 : (h->T + H - 1) / H;

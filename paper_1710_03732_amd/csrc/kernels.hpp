@@ -507,8 +507,10 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
         lap_solve_scalar2(lds, toff, soff, m, nt, u, v, p, th, st);
     }
     __builtin_amdgcn_wave_barrier();
-    // v to the scratch after the potentials (matching and links are done)
-    if (l < m && h < nt) scr[(size_t)h * 2 * m + m + l] = v;
+    // v to the scratch after the potentials (matching and links are done);
+    // with one LAP per wave (whose scratch has no room for v) it is fetched
+    // from its lane instead
+    if (H == 2 && l < m && h < nt) scr[(size_t)h * 2 * m + m + l] = v;
     __syncthreads();
     // slacks back in place, row by row (no index division): a lane owns one
     // column; with one LAP of m <= 32 per wave the two half-waves take
@@ -517,9 +519,10 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
         const bool two = (H == 1) && (m <= 32);
         const int sub = two ? (lane >> 5) : 0;
         const int col = (H == 1 && !two) ? lane : (lane & 31);
+        const double vcol = (H == 1) ? __shfl(v, col) : 0.0;  // every lane takes part
         if (h < nt && col < m) {
             const double *us = scr + (size_t)h * 2 * m;
-            const double vc = us[m + col];
+            const double vc = (H == 1) ? vcol : us[m + col];
             const double *tl = lds + (size_t)h * mm;
             double *dst = src + (size_t)h * mm;
             for (int r = sub; r < m; r += (two ? 2 : 1)) dst[r * m + col] = (tl[r * m + col] - us[r]) - vc;

@@ -83,7 +83,7 @@ __device__ void lap_solve_scalar1(double *lds, int toff, int soff, int m, double
     const double *M = lds + toff;
     double *mlu = lds + soff;
     int *mlp = (int *)(mlu + m);
-    int *mlw = mlp + m;
+    int *mlw = mlp;  // the rows' proposal winners share the matching's slots: read before it is written
     const unsigned long long validm = (m >= 64) ? ~0ull : ((1ull << m) - 1ull);
 
     // column reduction: lane l scans column l
@@ -112,13 +112,19 @@ __device__ void lap_solve_scalar1(double *lds, int toff, int soff, int m, double
     double th = mlu[0];
     for (int j = 1; j < m; ++j) th = th + mlu[j];
     __builtin_amdgcn_wave_barrier();
+    int wprop = kNone, wown = kNone;
     if (valid) {
-        p = (mlw[prop] == l) ? prop : -1;
+        wprop = mlw[prop];
+        wown = mlw[l];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (valid) {
+        p = (wprop == l) ? prop : -1;
         mlp[l] = p;
         mlu[l] = 0.0;
     }
-    unsigned long long unm = __builtin_amdgcn_ballot_w64(valid && mlw[l] == kNone);  // rows to insert
-    unsigned long long freem = __builtin_amdgcn_ballot_w64(valid && p < 0);         // unmatched columns
+    unsigned long long unm = __builtin_amdgcn_ballot_w64(valid && wown == kNone);  // rows to insert
+    unsigned long long freem = __builtin_amdgcn_ballot_w64(valid && p < 0);       // unmatched columns
     __builtin_amdgcn_wave_barrier();
     int st = 0;
     if (unm) {
