@@ -396,7 +396,7 @@ class DualAscent:
         """ids: int64 CUDA tensor; returns a float32 CUDA tensor (count, 32)."""
         import torch
 
-        ids = ids.contiguous()
+        ids = _device_tensor(ids, torch.int64, "ids")
         x = torch.empty((ids.numel(), 32), dtype=torch.float32, device=ids.device)
         _check(lib().qap_orbit_features(self.h, C.c_void_p(ids.data_ptr()), ids.numel(),
                                         C.c_void_p(x.data_ptr())), self.h)
@@ -405,9 +405,13 @@ class DualAscent:
     def orbit_targets(self, ids, scale: float, out=None):
         import torch
 
-        ids = ids.contiguous()
-        t = out if out is not None else torch.empty((ids.numel(), 6), dtype=torch.float32,
-                                                    device=ids.device)
+        ids = _device_tensor(ids, torch.int64, "ids")
+        if out is not None:
+            t = _device_tensor(out, torch.float32, "out", need=ids.numel() * 6)
+            if t.data_ptr() != out.data_ptr():
+                raise ValueError("out must be a contiguous float32 CUDA tensor")
+        else:
+            t = torch.empty((ids.numel(), 6), dtype=torch.float32, device=ids.device)
         _check(lib().qap_orbit_targets(self.h, C.c_void_p(ids.data_ptr()), ids.numel(),
                                        float(scale), C.c_void_p(t.data_ptr())), self.h)
         return t
@@ -420,7 +424,10 @@ class DualAscent:
         return y
 
     def warm_start_outputs(self, y, scale: float):
-        y = y.contiguous()
+        """y: float32 CUDA tensor of orbit_count(n) x 6 outputs in orbit-id order."""
+        import torch
+
+        y = _device_tensor(y, torch.float32, "y", need=orbit_count(self.n) * 6)
         _check(lib().qap_warm_start_outputs(self.h, C.c_void_p(y.data_ptr()), float(scale)), self.h)
 
     def warm_start(self, mlp: "Mlp", gain: float | None = None):
@@ -430,6 +437,32 @@ class DualAscent:
         _check(lib().qap_warm_start(self.h, mlp.h, g, C.byref(st)), self.h)
         return {"orbits": st.orbits, "scale": st.scale, "gain": st.gain, "ms_mlp": st.ms_mlp,
                 "ms_write": st.ms_write, "seconds": st.seconds, "mlp_flops": st.mlp_flops}
+
+
+def _device_tensor(t, dtype, name: str, need: int | None = None):
+    """The learned calls hand raw device pointers to kernels: refuse, before
+    any launch, a tensor that is not a CUDA tensor of the given dtype or, when
+    `need` is given, does not hold exactly that many elements."""
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, not {t.dtype}")
+    if need is not None and t.numel() != need:
+        raise ValueError(f"{name} must hold {need} elements, not {t.numel()}")
+    return t.contiguous()
+
+
+def _samples(t, cols: int, name: str, rows: int | None = None):
+    """A (rows, cols) float32 CUDA tensor of perceptron samples, checked."""
+    import torch
+
+    t = _device_tensor(t, torch.float32, name)
+    if t.dim() != 2 or t.shape[1] != cols or (rows is not None and t.shape[0] != rows):
+        want = f"({'count' if rows is None else rows}, {cols})"
+        raise ValueError(f"{name} must have shape {want}, not {tuple(t.shape)}")
+    return t
 
 
 def orbit_count(n: int) -> int:
@@ -503,14 +536,15 @@ class Mlp:
     def forward(self, x):
         import torch
 
-        x = x.contiguous()
+        x = _samples(x, 32, "x")
         y = torch.empty((x.shape[0], 6), dtype=torch.float32, device=x.device)
         _check(lib().qap_mlp_forward(self.h, C.c_void_p(x.data_ptr()), x.shape[0],
                                      C.c_void_p(y.data_ptr())))
         return y
 
     def gradients(self, x, t):
-        x, t = x.contiguous(), t.contiguous()
+        x = _samples(x, 32, "x")
+        t = _samples(t, 6, "t", rows=x.shape[0])
         g = np.zeros(MLP_PARAMS, dtype=np.float32)
         loss = C.c_double(0.0)
         _check(lib().qap_mlp_gradients(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
@@ -519,6 +553,8 @@ class Mlp:
         return g, loss.value
 
     def train_step(self, x, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8) -> float:
+        x = _samples(x, 32, "x")
+        t = _samples(t, 6, "t", rows=x.shape[0])
         opt = QapAdamParams(float(lr), float(beta1), float(beta2), float(eps))
         loss = C.c_double(0.0)
         _check(lib().qap_mlp_train_step(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),

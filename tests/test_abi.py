@@ -139,3 +139,60 @@ def test_missing_library_fails_loudly(monkeypatch):
         B.lib()
     with pytest.raises(RuntimeError):
         B.DualAscent(np.ones((5, 5)), np.ones((5, 5)))
+
+
+def test_learned_calls_refuse_bad_tensors_before_any_launch():
+    """The learned calls pass raw device pointers to kernels, so the binding
+    refuses host tensors, wrong dtypes and wrong sizes with ValueError before
+    the library is called (the handles here are never created on a device)."""
+    import torch
+
+    da = B.DualAscent.__new__(B.DualAscent)  # no device state: validation comes first
+    da.h, da.n, da.m, da.T = None, 8, 6, B.tile_count(8)
+    ids_cpu = torch.arange(10, dtype=torch.int64)
+    with pytest.raises(ValueError, match="CUDA"):
+        da.orbit_features(ids_cpu)
+    with pytest.raises(ValueError, match="CUDA"):
+        da.orbit_targets(ids_cpu, 1.0)
+    y = torch.zeros((B.orbit_count(8), 6), dtype=torch.float32)
+    with pytest.raises(ValueError, match="CUDA"):
+        da.warm_start_outputs(y, 1.0)
+    mlp = B.Mlp.__new__(B.Mlp)
+    mlp.h = None
+    x = torch.zeros((4, 32), dtype=torch.float32)
+    with pytest.raises(ValueError, match="CUDA"):
+        mlp.forward(x)
+    with pytest.raises(ValueError, match="CUDA"):
+        mlp.gradients(x, torch.zeros((4, 6)))
+    with pytest.raises(ValueError, match="CUDA"):
+        mlp.train_step(x, torch.zeros((4, 6)))
+    with pytest.raises(ValueError):
+        da.orbit_features([1, 2, 3])
+
+
+def test_tensor_checks_of_the_learned_calls():
+    """dtype, element-count and shape rules of the checks themselves, on
+    tensors that claim to be on a device (is_cuda patched): int32 ids, a
+    short or float64 y, samples with the wrong width or row count."""
+    import torch
+
+    class Fake(torch.Tensor):
+        @property
+        def is_cuda(self):
+            return True
+
+    def fake(t):
+        return t.as_subclass(Fake)
+
+    B._device_tensor(fake(torch.zeros(5, dtype=torch.int64)), torch.int64, "ids")
+    with pytest.raises(ValueError, match="dtype"):
+        B._device_tensor(fake(torch.zeros(5, dtype=torch.int32)), torch.int64, "ids")
+    with pytest.raises(ValueError, match="elements"):
+        B._device_tensor(fake(torch.zeros((3, 6), dtype=torch.float32)), torch.float32, "y", need=24)
+    with pytest.raises(ValueError, match="dtype"):
+        B._device_tensor(fake(torch.zeros((4, 6), dtype=torch.float64)), torch.float32, "y", need=24)
+    B._samples(fake(torch.zeros((4, 32), dtype=torch.float32)), 32, "x")
+    with pytest.raises(ValueError, match="shape"):
+        B._samples(fake(torch.zeros((4, 31), dtype=torch.float32)), 32, "x")
+    with pytest.raises(ValueError, match="shape"):
+        B._samples(fake(torch.zeros((5, 6), dtype=torch.float32)), 6, "t", rows=4)
