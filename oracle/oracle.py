@@ -52,6 +52,7 @@ def lib():
         L.orc_da_trace.argtypes = [C.c_void_p, _dp, C.c_int]
         L.orc_da_perms.argtypes = [C.c_void_p, _ip, _ip]
         L.orc_da_export.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        L.orc_da_z_tiles.argtypes = [C.c_void_p, C.c_int, _ip, _dp]
         L.orc_da_identity.argtypes = [C.c_void_p, _ip]
         L.orc_da_identity.restype = C.c_double
         L.orc_da_min_entries.argtypes = [C.c_void_p, _dp]
@@ -277,13 +278,24 @@ class DualAscent:
         lib().orc_da_perms(self.h, _i(a), _i(b))
         return a, b
 
-    def export(self):
+    def export(self, with_z: bool = True):
+        """Dense X (n^2), Y (n^4) and Z (n^6, None without with_z)."""
         n = self.n
         X = np.zeros((n, n))
         Y = np.zeros((n,) * 4)
-        Z = np.zeros((n,) * 6)
-        lib().orc_da_export(self.h, _d(X), _d(Y), _d(Z))
+        Z = np.zeros((n,) * 6) if with_z else None
+        lib().orc_da_export(self.h, _d(X), _d(Y), None if Z is None else _d(Z))
         return X, Y, Z
+
+    def z_tiles(self, picks):
+        """The z reduced costs of tiles (i, j, p, q): array (len, m, m), rows
+        k and columns r over the remaining indices in ascending order."""
+        m = self.n - 2
+        ijpq = np.ascontiguousarray(np.asarray(picks, dtype=np.int32).reshape(-1, 4))
+        out = np.zeros((len(ijpq), m, m))
+        if lib().orc_da_z_tiles(self.h, len(ijpq), _i(ijpq), _d(out)) != 0:
+            raise ValueError("z_tiles: bad tile")
+        return out
 
     def identity(self, perm) -> float:
         perm = np.ascontiguousarray(perm, dtype=np.int32)

@@ -953,6 +953,29 @@ void orc_da_export(const orc_da *s, double *X, double *Y, double *Z)
     if (Z) memcpy(Z, s->Z, sizeof(double) * n4 * n2);
 }
 
+/* The z reduced costs of selected tiles, without the dense n^6 copy: for
+ * tile a, given as facilities (i, j) and locations (p, q) in ijpq[4a..4a+3],
+ * out[a*m*m + k''*m + r''] = R_z[i,j,k,p,q,r] with k and r running over the
+ * remaining facilities and locations in ascending order (m = n - 2).
+ * Returns 0, or -1 for an index out of range or repeated within a pair. */
+int orc_da_z_tiles(const orc_da *s, int count, const int *ijpq, double *out)
+{
+    int n = s->n, m = n - 2;
+    for (int a = 0; a < count; ++a) {
+        int i = ijpq[4 * a], j = ijpq[4 * a + 1], p = ijpq[4 * a + 2], q = ijpq[4 * a + 3];
+        if (i < 0 || j < 0 || p < 0 || q < 0 || i >= n || j >= n || p >= n || q >= n || i == j || p == q)
+            return -1;
+        int ks[ORC_MAXM], rs[ORC_MAXM], c = 0;
+        for (int k = 0; k < n; ++k) if (k != i && k != j) ks[c++] = k;
+        c = 0;
+        for (int r = 0; r < n; ++r) if (r != p && r != q) rs[c++] = r;
+        for (int x = 0; x < m; ++x)
+            for (int y = 0; y < m; ++y)
+                out[(size_t)a * m * m + (size_t)x * m + y] = s->Z[IX6(n, i, j, ks[x], p, q, rs[y])];
+    }
+    return 0;
+}
+
 /* Multiplier tracking.  The F1 transfers are Lagrange multiplier updates in
  * the sense of the ascent rules: per sweep, entry e's multiplier moves by
  * g_e - phi * sum_{f != e} g_f (Eq. ch4:proof:2: its own kappa-shares minus

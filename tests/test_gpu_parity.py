@@ -262,6 +262,50 @@ def test_full_size_n30_sampled(inst):
     assert got.min() >= -1e-9 * F.max() * D.max()
 
 
+@pytest.mark.parametrize("inst,timing", [(I.dense_n30(), 1), (I.grid_n30(), 0)],
+                         ids=["dense_n30-bench_launches", "grid_n30-graph_replay"])
+def test_full_size_n30_trajectory_bitwise(inst, timing):
+    """Full n = 30, default (autotuned) Z-LAP mapping, against the oracle's
+    full F1 iterations (Algorithm 1): the bound after every one of the first
+    K iterations, the Dijkstra step count, and at t = K all of pi_x and pi_y
+    plus 10,000 random pi_z tiles, bit for bit.  The dense instance runs in
+    the benchmark's launch configuration (eager launches between HIP
+    events), the 5x6 grid on the library's default path (graph replay)."""
+    K = 6
+    F, D, Bm = inst.arrays()
+    n = 30
+    print(f"n30 trajectory: {inst.name}, timing={timing}, K={K}", flush=True)
+    gpu = B.DualAscent(F, D, Bm, timing=timing)
+    cpu = O.DualAscent(F, D, Bm)
+    gsteps = 0
+    for t in range(K):
+        r = gpu.run(1)
+        gsteps += r["dijkstra_steps"]
+        cpu.run(1)
+        tg, tc = gpu.trace(), cpu.trace()
+        assert len(tg) == t + 1
+        assert np.array_equal(tg, tc), (t, tg, tc)
+        assert _rel(tg[-1], tc[-1]) <= 1e-9
+        assert r["ub"] == cpu.UB
+    assert gsteps == cpu.steps
+    hdr, x, y, _ = gpu.export_state(with_z=False)
+    X, Y, _ = cpu.export(with_z=False)
+    assert hdr.lb == cpu.LB and hdr.t == K
+    assert np.array_equal(x, X.reshape(-1))
+    assert np.array_equal(y, dense_to_compact_y(n, Y))
+    rng = np.random.default_rng(3000 + timing)
+    picks = [(0, 1, 0, 1), (29, 28, 29, 28), (0, 29, 29, 0)]
+    while len(picks) < 10000:
+        i, j = rng.choice(n, 2, replace=False)
+        p, q = rng.choice(n, 2, replace=False)
+        picks.append((int(i), int(j), int(p), int(q)))
+    got = gpu.export_tiles([tile_index(n, i, p, j, q) for (i, j, p, q) in picks])
+    ref = cpu.z_tiles(picks)
+    bad = [a for a in range(len(picks)) if not np.array_equal(got[a], ref[a])]
+    assert not bad, [picks[a] for a in bad[:5]]
+    gpu.close()
+
+
 def test_full_size_n42_iteration0_and_sampled_tiles():
     """The largest benchmark size, n = 42 (4.74 G z entries, 38 GB): iteration
     0 in full against the oracle and the Gilmore-Lawler closed form, then

@@ -765,3 +765,23 @@ def test_s2_pooling_moves_the_multipliers(inst):
     Z1 = da.export()[2]
     V1, _ = da.multipliers()
     assert np.allclose(V1 - V0, Z0 - Z1, rtol=0, atol=1e-12 * scale)
+
+
+def test_z_tiles_accessor_matches_the_dense_export():
+    """The tile accessor the full-size GPU parity test reads (rows k and
+    columns r over the remaining indices, ascending) against the dense
+    export of the same state, including a ragged tile choice."""
+    from layout import dense_to_compact_z, tile_index
+
+    inst = I.random_instance(7, 5)
+    F, D, Bm = inst.arrays()
+    da = O.DualAscent(F, D, Bm)
+    da.run(3)
+    _, _, Z = da.export()
+    comp = dense_to_compact_z(7, Z)
+    picks = [(0, 1, 0, 1), (6, 5, 6, 5), (3, 0, 2, 6), (2, 4, 5, 1)]
+    got = da.z_tiles(picks)
+    for a, (i, j, p, q) in enumerate(picks):
+        assert np.array_equal(got[a], comp[tile_index(7, i, p, j, q)])
+    with pytest.raises(ValueError):
+        da.z_tiles([(1, 1, 0, 2)])
