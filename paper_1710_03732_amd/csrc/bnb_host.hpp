@@ -368,11 +368,19 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
                 if (e2 == hipSuccess && stopped0 + ns >= count) break;
             }
             if (e2 != hipSuccess) {
+                // replays already queued still read the exec's kernel
+                // arguments: drain the stream before destroying it
+                (void)hipStreamSynchronize(stream);
                 if (ge) (void)hipGraphExecDestroy(ge);
                 return fail(h0, QAP_EDEVICE, std::string("batch replay: ") + hipGetErrorString(e2));
             }
         }
+        // the graph exec owns the kernel arguments of its nodes; replays
+        // still in the stream's queue read them when they are dispatched,
+        // so the exec is destroyed only after the stream has drained
+        const hipError_t se = hipStreamSynchronize(stream);
         if (ge) (void)hipGraphExecDestroy(ge);
+        if (se != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch sync: ") + hipGetErrorString(se));
     }
     HIPCHK(h0, hipStreamSynchronize(stream));
     if (st) {
