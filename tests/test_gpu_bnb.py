@@ -84,6 +84,55 @@ def test_batch_equals_single_runs():
     assert st["iterations"] == sum(c.t for c in cpu)
 
 
+def _mixed_depth_children(F, D, Bm, counts, root_iters=3, parent_iters=2, seed=0):
+    """Children of depth 1..len(counts) (reduced sizes n-1 .. n-len(counts))
+    of one root, built identically on the GPU and in the oracle: at depth d
+    the parent is the chain root -> fold(0, ...) -> ... with parent_iters
+    iterations behind every link, and counts[d-1] distinct fixings (l, s)
+    of that parent are folded."""
+    rng = np.random.default_rng(seed)
+    gp = B.DualAscent(F, D, Bm)
+    cp = O.DualAscent(F, D, Bm)
+    gp.run(root_iters)
+    cp.run(root_iters)
+    gpu, cpu = [], []
+    for d, cnt in enumerate(counts, start=1):
+        n1 = gp.n
+        picks = rng.choice(n1 * n1, size=cnt, replace=False)
+        for k in picks:
+            l, s = divmod(int(k), n1)
+            gpu.append(gp.fold(l, s))
+            cpu.append(cp.fold(l, s))
+        if d < len(counts):
+            s0 = d % n1
+            gp, cp = gp.fold(0, s0), cp.fold(0, s0)
+            gp.run(parent_iters)
+            cp.run(parent_iters)
+    return gpu, cpu
+
+
+def test_batch_of_mixed_depth_children_bitwise():
+    """Over 200 children of the n = 14 dense instance (the batched
+    branch-and-bound workload), of depths 1..6 (reduced sizes 13 down to 8),
+    advanced together in one batch for 5 iterations: every child's bound
+    trace and final state equal the oracle's fold and 5 iterations, bit for
+    bit.  This exercises the prefix tables and the per-node search of the
+    batched kernels over many nodes of uneven size."""
+    F, D, Bm = I.dense_n14().arrays()
+    counts = [60, 50, 40, 30, 20, 10]
+    gpu, cpu = _mixed_depth_children(F, D, Bm, counts)
+    assert len(gpu) == sum(counts) >= 200
+    assert sorted({g.n for g in gpu}) == [8, 9, 10, 11, 12, 13]
+    st = B.batch_run(gpu, iters=5)
+    for k, (g, c) in enumerate(zip(gpu, cpu)):
+        c.run(5)
+        assert np.array_equal(g.trace(), c.trace()), (k, g.n, g.trace(), c.trace())
+        _state_equal(g, c)
+    assert st["iterations"] == sum(c.t for c in cpu)
+    for g in gpu:
+        g.close()
+
+
 def test_batch_window_rule_stops_nodes():
     F, D, Bm = I.dense_instance(11, 70).arrays()
     g = B.DualAscent(F, D, Bm)
