@@ -24,9 +24,17 @@ iterations of F1 and F2 with and without Type 4 annealing steps.
 (trained weights from train_warm.py) reaching the same bound; its
 `mlp_roofline` gives the inference kernel's TFLOP/s against the bf16 MFMA
 peak.  `bnb` times branch-and-bound at n = 14 and 18 (dense) and on a 4x4 grid
-(n = 16) with and without symmetry elimination.  `cpu_baseline` times
-the CPU oracle (all OpenMP threads) on a
-bounded sample (about 10 s of iterations) of the same workload.
+(n = 16) with and without symmetry elimination.  `graph_replay` times the
+same iterations on the library's production path (one captured HIP graph
+per iteration, no events between kernels).  `n42` runs the n = 42 root
+bound: 100 plain iterations (per-phase times, HBM rates, the bound every 10
+iterations) against the learned warm start.  `iteration_hbm` relates the
+iteration time to the minimal schedule's bytes (three passes over z) and to
+the implemented schedule's (four).  `cpu_baseline` times the CPU oracle
+(all OpenMP threads, then one iteration on one thread) on a bounded sample
+(about 10 s of iterations) of the same workload, names the host CPU, and
+checks the oracle's bound against the GPU trace at the same iteration (the
+run exits with status 3 when they differ by more than 1e-9 relative).
 """
 from __future__ import annotations
 
@@ -60,6 +68,32 @@ def algorithmic_bytes(n: int) -> dict:
         "ylap": 8 * (3 * T + 2 * nn),
         "xlap": 8 * (5 * nn),
     }
+
+
+def minimal_iteration_bytes(n: int) -> int:
+    """HBM bytes of one iteration under the minimal schedule: the Z-LAPs read
+    the z array and write only their duals (u, v per tile and Theta), the
+    sweep reads the z array and the duals, forms the slacks on the fly and
+    writes the new z array: 8 (3 V + 2 T (2 m + 1)) plus the O(n^4) y and x
+    arrays.  The implemented schedule moves more (the Z-LAPs write the slacks
+    back in place and the sweep reads them: four passes over z, not three);
+    both are reported."""
+    m = n - 2
+    T = n * n * (n - 1) * (n - 1)
+    V = T * m * m
+    return 8 * (3 * V + 2 * T * (2 * m + 1))
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def algorithmic_bytes_half(n: int) -> dict:
@@ -101,10 +135,17 @@ def load_traffic(kernel: str, workload: str):
     return k.get("bytes_per_launch")
 
 
-def cpu_baseline(inst, threads: int | None, budget_s: float = 10.0):
+def cpu_baseline(inst, threads: int | None, gpu_trace, budget_s: float = 10.0):
     """The CPU oracle on the same workload: full F1 iterations (t >= 1: ascent
-    sweep and all Z/Y/X LAPs) after iteration 0, until `budget_s` seconds of
-    CPU work have been timed (at least two iterations)."""
+    sweep and all Z/Y/X LAPs) after iteration 0, on all threads until
+    `budget_s` seconds have been timed (at least two iterations); then one
+    iteration on a single thread and the next one on all threads again
+    (neighbouring iterations take about the same number of Dijkstra steps).
+    The oracle's results do not depend on the thread count, so its bound
+    after those iterations is compared with the GPU's trace at the same
+    iteration (bitwise, and within the 1e-9 relative tolerance)."""
+    import numpy as np
+
     from oracle import oracle as O
 
     if threads:
@@ -119,10 +160,33 @@ def cpu_baseline(inst, threads: int | None, budget_s: float = 10.0):
         cpu.run(1)
         el += time.perf_counter() - t0
         done += 1
+    O.set_threads(1)
+    t0 = time.perf_counter()
+    cpu.run(1)
+    one = time.perf_counter() - t0
+    O.set_threads(used)
+    t0 = time.perf_counter()
+    cpu.run(1)
+    nxt = time.perf_counter() - t0
+    O.set_threads(threads or used)
+    total = done + 3  # iterations 0 .. done + 2
+    lb = cpu.LB
+    gpu_lb = float(gpu_trace[total - 1]) if len(gpu_trace) >= total else None
+    parity = {"iterations": total, "oracle_lb": lb, "gpu_lb": gpu_lb,
+              "bitwise": gpu_lb is not None and gpu_lb == lb,
+              "within_1e-9": gpu_lb is not None and abs(gpu_lb - lb) <= 1e-9 * abs(lb),
+              "oracle_trace_equal": gpu_lb is not None
+              and bool(np.array_equal(np.asarray(gpu_trace[:total]), np.asarray(cpu.trace())))}
     return {"value": done / el, "unit": "iterations/s", "cores": used, "kind": "oracle",
             "sample": f"{done} full F1 iterations (t = 1..{done}: ascent sweep and all Z/Y/X LAPs) of the "
-                      f"{inst.name} workload after iteration 0, {el:.2f} s on {used} threads",
-            "seconds": el, "iterations": done, "lb_after": cpu.LB}
+                      f"{inst.name} workload after iteration 0, {el:.2f} s on {used} threads; then iteration "
+                      f"{done + 1} on one thread ({one:.2f} s) and iteration {done + 2} on {used} threads "
+                      f"({nxt:.2f} s)",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "seconds": el, "iterations": done,
+            "single_thread": {"iteration": done + 1, "seconds": one, "iterations_per_s": 1.0 / one,
+                              "laps_per_s": (inst.n * inst.n * (inst.n - 1) ** 2 + inst.n ** 2 + 1) / one},
+            "all_threads_next_iteration": {"iteration": done + 2, "seconds": nxt, "threads": used},
+            "lb_after": lb, "gpu_parity": parity}
 
 
 def warm_vs_cold(inst, cold_iters: int):
@@ -143,6 +207,137 @@ def warm_vs_cold(inst, cold_iters: int):
                            "ms": ms}
     mlp.close()
     return res
+
+
+def graph_replay_leg(inst, steps: int, warmup: int, timed_trace):
+    """The library's production path: a handle on its own stream, whose
+    iteration is one captured HIP graph replayed per iteration with no events
+    between the kernels.  Same workload, warmup and step count as the timed
+    run (which records events around every kernel); the bounds must agree
+    bitwise."""
+    import numpy as np
+    import torch
+
+    from paper_1710_03732_amd import binding
+
+    F, D, B = inst.arrays()
+    h = binding.DualAscent(F, D, B)
+    if warmup > 0:
+        h.run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = h.run(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tr = h.trace()
+    h.close()
+    done = r["iterations_done"]
+    n = inst.n
+    laps = n * n * (n - 1) * (n - 1) + n * n + 1
+    return {"iterations_per_s": done / el if done else None, "ms_per_step": 1e3 * el / done if done else None,
+            "laps_per_s": laps * done / el if done else None, "iterations_done": done,
+            "trace_equal_to_timed_run": bool(np.array_equal(tr, timed_trace))}
+
+
+def n42_leg(cold_iters: int = 100, every: int = 10):
+    """The n = 42 root bound (dense symmetric F, D ~ U{0..99}, seed 0; the
+    z array is 37.96 GB): `cold_iters` plain iterations with events around
+    every kernel (per-phase times, HBM rates against the minimal schedule's
+    bytes and the implemented schedule's), then the learned warm start
+    followed by the same number of iterations, and the wall time the warm
+    start (features, inference and z writer included) needs to reach the
+    plain bound.  Bounds every `every` iterations."""
+    import numpy as np
+    import torch
+
+    from paper_1710_03732_amd import binding, instances as insts, train_warm
+
+    inst = insts.dense_n42()
+    F, D, B = inst.arrays()
+    n = inst.n
+    m = n - 2
+    T = n * n * (n - 1) * (n - 1)
+    ab = algorithmic_bytes(n)
+    stream = torch.cuda.current_stream()
+    h = binding.DualAscent(F, D, B, timing=1)
+    h.set_stream(stream.cuda_stream)
+    h.run(1)  # iteration 0 and the Z-LAP mapping's tuning, untimed
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = h.run(cold_iters - 1)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    cold_tr = h.trace()
+    mapping = mapping_text(h)
+    h.close()
+    done = r["iterations_done"]
+    phase_ms = {"sweep": r["ms_sweep"] / done, "zlap": r["ms_zlap"] / done,
+                "ylap": r["ms_ylap"] / done, "xlap": r["ms_xlap"] / done}
+    per_it = el / done
+    out = {"workload": "dense_n42: QAP n=42 root dual ascent, dense symmetric F,D~U{0..99}, zero diagonals, "
+                       "seed 0; F1 FULL",
+           "z_laps_per_iter": T, "laps_per_iter": T + n * n + 1, "z_entries": T * m * m,
+           "zlap_mapping": mapping,
+           "cold": {"iterations": len(cold_tr), "timed_iterations": done, "iterations_per_s": done / el,
+                    "ms_per_step": 1e3 * per_it, "laps_per_s": (T + n * n + 1) * done / el,
+                    "phase_ms_per_iter": phase_ms,
+                    "phase_gbs": {k: ab[k] / (phase_ms[k] * 1e-3) / 1e9 for k in ("zlap", "sweep")},
+                    "dijkstra_steps_per_lap": r["dijkstra_steps"] / max(1, done * (T + n * n + 1)),
+                    "zlap_dijkstra_steps_per_s": r["dijkstra_steps"] / max(1e-12, r["ms_zlap"] * 1e-3),
+                    "iteration_hbm_minimal": {"bytes": minimal_iteration_bytes(n),
+                                              "achieved_gbs": minimal_iteration_bytes(n) / per_it / 1e9,
+                                              "frac": minimal_iteration_bytes(n) / per_it / 1e9 / HBM_PEAK_GBS},
+                    "iteration_hbm_schedule": {"bytes": sum(ab.values()),
+                                               "achieved_gbs": sum(ab.values()) / per_it / 1e9,
+                                               "frac": sum(ab.values()) / per_it / 1e9 / HBM_PEAK_GBS},
+                    "lb_every": {str(k): float(cold_tr[k - 1]) for k in range(every, len(cold_tr) + 1, every)},
+                    "lb": float(cold_tr[-1])}}
+    if not os.path.exists(train_warm.WEIGHTS):
+        out["warm"] = {"skipped": "no trained weights"}
+        return out
+    # the cold side on the production path (graph replay), for the wall time
+    # (the Z-LAP mapping chosen by the first handle is kept for the process)
+    c = binding.DualAscent(F, D, B)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.run(cold_iters)
+    cold_s = time.perf_counter() - t0
+    assert np.array_equal(c.trace(), cold_tr), "graph replay and timed run disagree"
+    c.close()
+    mlp = binding.Mlp(train_warm.load_weights(), max_batch=256)
+    w = binding.DualAscent(F, D, B)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = w.warm_start(mlp)
+    w.run(cold_iters)
+    wel = time.perf_counter() - t0
+    warm_tr = w.trace()
+    w.close()
+    best = np.maximum.accumulate(warm_tr)
+    hit = np.nonzero(best >= cold_tr[-1])[0]
+    reached = None
+    if len(hit):
+        k = int(hit[0]) + 1
+        w = binding.DualAscent(F, D, B)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        w.warm_start(mlp)
+        rr = w.run(k)
+        kel = time.perf_counter() - t0
+        w.close()
+        reached = {"iterations": k, "seconds": kel, "lb": rr["lb"]}
+    mlp.close()
+    flops = 2.0 * binding.orbit_count(n) * (32 * 256 + 256 * 256 + 256 * 6)
+    out["warm"] = {"iterations": len(warm_tr), "seconds_with_start": wel, "start_seconds": st["seconds"],
+                   "ms_mlp": st["ms_mlp"], "ms_write": st["ms_write"],
+                   "mlp_tflops": flops / (st["ms_mlp"] * 1e-3) / 1e12,
+                   "lb_t0": float(warm_tr[0]),
+                   "lb_every": {str(k): float(best[k - 1]) for k in range(every, len(best) + 1, every)},
+                   "lb": float(best[-1]), "to_cold_lb": reached}
+    out["time_to_cold_bound"] = {"cold_iterations": len(cold_tr), "cold_seconds": cold_s,
+                                 "warm_seconds": reached["seconds"] if reached else None,
+                                 "speedup": cold_s / reached["seconds"] if reached else None}
+    return out
 
 
 def variant_leg(inst, label: str, make_params, z_laps: int, ab: dict, steps: int, warmup: int,
@@ -343,6 +538,7 @@ def main(argv=None):
     ap.add_argument("--no-time-to-bound", action="store_true")
     ap.add_argument("--no-bnb", action="store_true", help="skip the branch-and-bound leg (n = 14 and 18)")
     ap.add_argument("--no-variants", action="store_true", help="skip the HALF and F2 legs")
+    ap.add_argument("--no-n42", action="store_true", help="skip the n = 42 plain vs warm leg")
     ap.add_argument("--cold-iters", type=int, default=100,
                     help="cold iterations whose bound the learned warm start must reach")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -397,6 +593,7 @@ def main(argv=None):
     achieved = ab[dom] / dom_s / 1e9
     traffic = load_traffic(dom, inst.name)
     iter_bytes = sum(ab.values())
+    min_bytes = minimal_iteration_bytes(n)
     full_trace = da.trace()
     copy_gbs = measure_copy_gbs()  # after the timed region
     steps_per_zlap = r["dijkstra_steps"] / max(1, done * laps_per_iter)
@@ -432,20 +629,30 @@ def main(argv=None):
         "ub": r["ub"],
         "gap": r["gap"],
         "dijkstra_steps_per_lap": steps_per_zlap,
-        "iteration_hbm": {"bytes": iter_bytes, "achieved_gbs": iter_bytes / (el / done) / 1e9,
+        "zlap_issue": {"dijkstra_steps_per_s": r["dijkstra_steps"] / max(1e-12, r["ms_zlap"] * 1e-3),
+                       "z_laps_per_s": T * done / max(1e-12, r["ms_zlap"] * 1e-3),
+                       "ms_per_launch": phase_ms["zlap"]},
+        "iteration_hbm": {"minimal_schedule_bytes": min_bytes,
+                          "minimal_achieved_gbs": min_bytes / (el / done) / 1e9,
+                          "minimal_frac": min_bytes / (el / done) / 1e9 / HBM_PEAK_GBS,
+                          "schedule_bytes": iter_bytes, "achieved_gbs": iter_bytes / (el / done) / 1e9,
                           "frac": iter_bytes / (el / done) / 1e9 / HBM_PEAK_GBS,
-                          "copy_gbs": copy_gbs, "frac_of_copy": iter_bytes / (el / done) / 1e9 / copy_gbs},
+                          "copy_gbs": copy_gbs, "frac_of_copy": iter_bytes / (el / done) / 1e9 / copy_gbs,
+                          "minimal_frac_of_copy": min_bytes / (el / done) / 1e9 / copy_gbs},
         "roofline": {"bound": "hbm", "kernel": {"zlap": "k_zlap", "sweep": "k_sweep+k_scale_xy"}[dom],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": ab[dom],
                      "avg_launch_ms": phase_ms[dom], "frac_of_copy": achieved / copy_gbs},
+        "graph_replay": None,
         "variants": None,
         "bnb": None,
         "time_to_bound": None,
+        "n42": None,
         "cpu_baseline": None,
     }
     da.close()
+    out["graph_replay"] = graph_replay_leg(inst, args.steps, args.warmup, full_trace)
     if not args.no_variants:
         out["variants"] = variant_legs(inst, args.steps, args.warmup, full_trace, args.cold_iters, stream)
     if not args.no_bnb and inst.name == "dense_n30":
@@ -457,10 +664,17 @@ def main(argv=None):
         if inst.name == "dense_n30":  # the headline's second instance
             ttb["grid_n30"] = warm_vs_cold(insts.grid_n30(), args.cold_iters)
         out["time_to_bound"] = ttb
+    if not args.no_n42 and inst.name == "dense_n30":
+        out["n42"] = n42_leg(args.cold_iters)
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
-        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_threads or None)
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_threads or None, full_trace)
     print(json.dumps(out), flush=True)
+    par = (out["cpu_baseline"] or {}).get("gpu_parity")
+    if par is not None and par["gpu_lb"] is not None and not par["within_1e-9"]:
+        print(f"bench.py: the GPU bound {par['gpu_lb']!r} differs from the oracle's {par['oracle_lb']!r} "
+              f"after {par['iterations']} iterations", file=sys.stderr)
+        return 3
     return 0
 
 
