@@ -219,6 +219,49 @@ def time_to_bound(inst, mlp, cold_iters: int):
             "speedup": (W / reached["seconds"]) if reached else None}
 
 
+def u_ablation(inst, mlp, tracked_iters: int, cold_iters: int):
+    """How much could predicting the y-pair multipliers u add?  From the
+    multipliers (v, u) that `tracked_iters` plain iterations with tracking
+    reach (the training targets), restart once with (v, u) and once with
+    (v, 0), and compare both with the learned start (predicted v, u = 0):
+    bound at the restart, iterations and seconds to the bound of
+    `cold_iters` cold iterations.  The tracked (v, u) is the best a
+    predictor of both could hope to reproduce; the gap between its two
+    restarts bounds what a u prediction can gain."""
+    import torch
+
+    F, D, Bm = inst.arrays()
+    cold = B.DualAscent(F, D, Bm)
+    lb_cold = cold.run(cold_iters)["lb"]
+    cold.close()
+    t = B.DualAscent(F, D, Bm)
+    t.track()
+    t.run(tracked_iters)
+    v, u = t.multipliers()
+    t.close()
+    out = {"name": inst.name, "n": inst.n, "cold_iterations": cold_iters, "cold_lb": lb_cold,
+           "tracked_iterations": tracked_iters,
+           "u_rel_size": float(np.abs(u).sum() / max(1e-300, np.abs(v).sum()))}
+    for label, uu in (("tracked_v_u", u), ("tracked_v_only", None), ("learned_v", "mlp")):
+        h = B.DualAscent(F, D, Bm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if uu == "mlp":
+            h.warm_start(mlp)
+        else:
+            h.set_multipliers(v, uu)
+        h.run(cold_iters)
+        el = time.perf_counter() - t0
+        tr = np.maximum.accumulate(h.trace())
+        h.close()
+        hit = np.nonzero(tr >= lb_cold)[0]
+        k = int(hit[0]) + 1 if len(hit) else None
+        out[label] = {"lb_t0": float(tr[0]), "lb_after": float(tr[-1]), "iterations_to_cold_lb": k,
+                      "seconds_per_iteration": el / cold_iters,
+                      "seconds_to_cold_lb_est": (el * k / cold_iters) if k else None}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--iters", type=int, default=500, help="tracked iterations per training instance")
@@ -237,6 +280,8 @@ def main(argv=None):
     ap.add_argument("--recalibrate", action="store_true",
                     help="with --eval-only: choose the gain again on the training instances and save it")
     ap.add_argument("--calib", type=int, default=16, help="training instances (the last ones) for the gain")
+    ap.add_argument("--u-ablation", default=None,
+                    help="instead of training: write the u ablation of the held-out instances to this JSON file")
     args = ap.parse_args(argv)
 
     import torch
@@ -245,6 +290,21 @@ def main(argv=None):
         print("train_warm.py: no GPU visible", file=sys.stderr)
         return 1
     t_all = time.perf_counter()
+    if args.u_ablation:
+        mlp = B.Mlp(load_weights(args.out), max_batch=args.batch)
+        rows = []
+        for idx in range(64, 64 + args.heldout):
+            res = u_ablation(I.learned_family(idx), mlp, args.iters, args.cold_iters)
+            rows.append(res)
+            log(f"{res['name']}: |u|/|v| {res['u_rel_size']:.3f}; LB0 (v,u) {res['tracked_v_u']['lb_t0']:.1f} "
+                f"(v,0) {res['tracked_v_only']['lb_t0']:.1f} learned {res['learned_v']['lb_t0']:.1f}; "
+                f"iterations to the cold bound (v,u) {res['tracked_v_u']['iterations_to_cold_lb']} "
+                f"(v,0) {res['tracked_v_only']['iterations_to_cold_lb']} "
+                f"learned {res['learned_v']['iterations_to_cold_lb']}")
+        with open(args.u_ablation, "w") as f:
+            json.dump({"rows": rows, "args": vars(args), "seconds": time.perf_counter() - t_all}, f, indent=1)
+        mlp.close()
+        return 0
     calib = list(range(max(0, args.train - args.calib), args.train))
     gain_scores = None
     if args.eval_only:
