@@ -182,8 +182,16 @@ hipError_t launch_zlap_s(qap_ctx *h)
     // HALF: one block per tile with i < j (half of them; H = 1 only)
     const int half = (H == 1 && h->half) ? 1 : 0;
     const long long blocks = half ? h->T / 2 : (h->T + H - 1) / H;
-    hipLaunchKernelGGL((k_zlap_s<H>), dim3((unsigned)blocks), dim3(64), per, h->stream, h->Z, h->Yc, m,
-                       h->T, h->S, h->bins, half);
+    // the tile sizes of the n = 30 and n = 42 workloads have kernels compiled for them
+    if (H == 1 && m == 28)
+        hipLaunchKernelGGL((k_zlap_s<1, 28>), dim3((unsigned)blocks), dim3(64), per, h->stream, h->Z, h->Yc, m,
+                           h->T, h->S, h->bins, half);
+    else if (H == 1 && m == 40)
+        hipLaunchKernelGGL((k_zlap_s<1, 40>), dim3((unsigned)blocks), dim3(64), per, h->stream, h->Z, h->Yc, m,
+                           h->T, h->S, h->bins, half);
+    else
+        hipLaunchKernelGGL((k_zlap_s<H>), dim3((unsigned)blocks), dim3(64), per, h->stream, h->Z, h->Yc, m,
+                           h->T, h->S, h->bins, half);
     return hipGetLastError();
 }
 
@@ -943,6 +951,12 @@ int qap_lap_batch(const double *cost, int count, int m, double *u, double *v, do
         const unsigned bs = (unsigned)((count + H - 1) / H);
         if (H == 2)
             hipLaunchKernelGGL((k_lap_batch_s<2>), dim3(bs), dim3(64), pers, s, cost, count, m, u, v, theta,
+                               (int *)row_of_col);
+        else if (m == 28)  // the tile sizes with kernels compiled for them (k_zlap_s)
+            hipLaunchKernelGGL((k_lap_batch_s<1, 28>), dim3(bs), dim3(64), pers, s, cost, count, m, u, v, theta,
+                               (int *)row_of_col);
+        else if (m == 40)
+            hipLaunchKernelGGL((k_lap_batch_s<1, 40>), dim3(bs), dim3(64), pers, s, cost, count, m, u, v, theta,
                                (int *)row_of_col);
         else
             hipLaunchKernelGGL((k_lap_batch_s<1>), dim3(bs), dim3(64), pers, s, cost, count, m, u, v, theta,

@@ -468,22 +468,27 @@ __global__ __launch_bounds__(256) void k_zlap(double *__restrict__ Z, double *__
 
 // Z-LAPs with the scalar-controlled solver: one wavefront per block holding
 // H tiles (H = 2: two 32-lane LAPs, m <= 32; H = 1: one 64-lane LAP).
-template <int H>
-__global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *__restrict__ Yc, int m,
+// MC > 0 compiles the kernel for tiles of size MC (m must equal it): the
+// tile copy, the column reduction and the write-back then run with constant
+// trip counts and immediate offsets.  Same arithmetic in the same order.
+template <int H, int MC = 0>
+__global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *__restrict__ Yc, int m_in,
                                                long long T, DevScalars *__restrict__ S,
                                                unsigned long long *__restrict__ bins, int half)
 {
     if (S->stopped) return;
     extern __shared__ double lds[];
     constexpr int W = 64 / H;
-    const int lane = threadIdx.x;
+    const int m = MC > 0 ? MC : m_in;
+    const int lane = (int)(threadIdx.x & 63);  // (the mask tells the compiler lane < 64)
     const int h = (H == 1) ? 0 : (lane >> 5);
     const int l = lane & (W - 1);
     // HALF (H = 1): block b solves the b-th tile with i < j
     const long long t0 = (H == 1 && half) ? upper_tile(blockIdx.x, m + 2) : (long long)blockIdx.x * H;
     const int mm = m * m;
     const long long left = T - t0;
-    const int nt = (int)(left < H ? left : H);
+    // (one tile per block: every block of the grid has its tile)
+    const int nt = (H == 1) ? 1 : (int)(left < H ? left : H);
     double *src = Z + t0 * mm;
     copy_to_lds(lds, src, nt * mm, lane, 64);
     const double yc0 = (h < nt) ? Yc[t0 + h] : 0.0;  // read now, added to after the solve
@@ -525,7 +530,12 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
             const double vc = (H == 1) ? vcol : us[m + col];
             const double *tl = lds + (size_t)h * mm;
             double *dst = src + (size_t)h * mm;
-            for (int r = sub; r < m; r += (two ? 2 : 1)) dst[r * m + col] = (tl[r * m + col] - us[r]) - vc;
+            const int step = two ? 2 : 1;
+            // a constant trip count (rows past m skipped) lets a fixed m unroll it
+            for (int k = 0; k < (m + step - 1) / step; ++k) {
+                const int r = k * step + sub;
+                if (r < m) dst[r * m + col] = (tl[r * m + col] - us[r]) - vc;
+            }
         }
     }
     if (l == 0 && h < nt) Yc[t0 + h] = yc0 + th;
@@ -534,15 +544,17 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
     if (lane == 0) atomicAdd(&bins[blockIdx.x & (kStepBins - 1)], (unsigned long long)stt);
 }
 
-// LAP batch with the scalar-controlled solver (validation entry point).
-template <int H>
-__global__ __launch_bounds__(64) void k_lap_batch_s(const double *__restrict__ cost, int count, int m,
+// LAP batch with the scalar-controlled solver (validation entry point);
+// MC > 0 as for k_zlap_s.
+template <int H, int MC = 0>
+__global__ __launch_bounds__(64) void k_lap_batch_s(const double *__restrict__ cost, int count, int m_in,
                                                     double *__restrict__ uo, double *__restrict__ vo,
                                                     double *__restrict__ tho, int *__restrict__ rco)
 {
     extern __shared__ double lds[];
     constexpr int W = 64 / H;
-    const int lane = threadIdx.x;
+    const int m = MC > 0 ? MC : m_in;
+    const int lane = (int)(threadIdx.x & 63);
     const int h = (H == 1) ? 0 : (lane >> 5);
     const int l = lane & (W - 1);
     const long long t0 = (long long)blockIdx.x * H;
