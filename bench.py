@@ -474,6 +474,9 @@ def bnb_leg():
         out[label] = {"optimum": obj, "seconds": el, "nodes": st["nodes"], "batches": st["batches"],
                       "da_iterations": st["da_iters"], "nodes_per_s": st["nodes"] / el,
                       "node_iterations_per_s": st["da_iters"] / el,
+                      "node_iteration_bytes": st["node_bytes"],
+                      "bytes_per_node_iteration": st["node_bytes"] / max(1, st["da_iters"]),
+                      "algorithmic_gbs_over_wall_time": st["node_bytes"] / el / 1e9,
                       "symmetric_skipped": st["symmetric_skipped"], **kw}
     return out
 

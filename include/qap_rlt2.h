@@ -172,6 +172,12 @@ typedef struct qap_bnb_stats {
     double seconds;
     long long symmetric_skipped; /* children not built by the symmetry elimination */
     long long automorphisms;     /* location automorphisms used, identity included */
+    double node_bytes;           /* algorithmic HBM bytes of all node iterations: per
+                                    iteration of a node of size n', m' = n' - 2,
+                                    T' = n'^2 (n'-1)^2, V' = T' m'^2:
+                                    8 (4 V' + 8 T' + 10 n'^2) (the sweep and the
+                                    Z-LAPs read and write the z array once each,
+                                    plus the y and x arrays) */
 } qap_bnb_stats;
 
 /* Location automorphisms of a QAP (host only, no device work): the

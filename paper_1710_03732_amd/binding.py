@@ -58,7 +58,7 @@ class QapBnbParams(C.Structure):
 class QapBnbStats(C.Structure):
     _fields_ = [("nodes", C.c_longlong), ("da_iters", C.c_longlong), ("batches", C.c_longlong),
                 ("enumerated", C.c_longlong), ("seconds", C.c_double), ("symmetric_skipped", C.c_longlong),
-                ("automorphisms", C.c_longlong)]
+                ("automorphisms", C.c_longlong), ("node_bytes", C.c_double)]
 
 
 class QapBatchParams(C.Structure):
@@ -352,7 +352,7 @@ class DualAscent:
         return obj.value, perm, {"nodes": st.nodes, "da_iters": st.da_iters,
                                  "batches": st.batches, "enumerated": st.enumerated,
                                  "seconds": st.seconds, "symmetric_skipped": st.symmetric_skipped,
-                                 "automorphisms": st.automorphisms}
+                                 "automorphisms": st.automorphisms, "node_bytes": st.node_bytes}
 
 
     # ---- multipliers and the learned warm start ---------------------------

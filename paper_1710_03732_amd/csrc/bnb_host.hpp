@@ -494,6 +494,7 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
     double UB = P.ub0;
     std::vector<int> best(n, -1);
     long long nodes_done = 0, da_iters = 0, batches = 0, enumerated = 0;
+    double node_bytes = 0.0;
 
     struct Node {
         std::shared_ptr<qap_ctx> parent;  // materialised parent state (shared by siblings)
@@ -597,6 +598,10 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
                 break;
             }
             da_iters += sv[b].t;
+            {
+                const double nn = c->n, T1 = nn * nn * (nn - 1) * (nn - 1), V1 = T1 * (nn - 2) * (nn - 2);
+                node_bytes += sv[b].t * 8.0 * (4.0 * V1 + 8.0 * T1 + 10.0 * nn * nn);
+            }
             std::vector<int> lp(c->n);
             if (hipMemcpy(lp.data(), c->bestperm, sizeof(int) * c->n, hipMemcpyDeviceToHost) != hipSuccess) {
                 rc = fail(h, QAP_EDEVICE, "reading node assignment failed");
@@ -683,6 +688,7 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
         st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         st->symmetric_skipped = sym_skipped;
         st->automorphisms = (long long)autos.size() + 1;
+        st->node_bytes = node_bytes;
     }
     return QAP_OK;
 }

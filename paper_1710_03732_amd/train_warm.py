@@ -242,11 +242,11 @@ def u_ablation(inst, mlp, tracked_iters: int, cold_iters: int):
     out = {"name": inst.name, "n": inst.n, "cold_iterations": cold_iters, "cold_lb": lb_cold,
            "tracked_iterations": tracked_iters,
            "u_rel_size": float(np.abs(u).sum() / max(1e-300, np.abs(v).sum()))}
-    for label, uu in (("tracked_v_u", u), ("tracked_v_only", None), ("learned_v", "mlp")):
+    for label, uu in (("tracked_v_u", u), ("tracked_v_only", None), ("learned_v", None)):
         h = B.DualAscent(F, D, Bm)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if uu == "mlp":
+        if label == "learned_v":
             h.warm_start(mlp)
         else:
             h.set_multipliers(v, uu)
