@@ -358,6 +358,27 @@ int qap_fold_child(qap_handle h, int l, int s, qap_handle *child);
  * handles; st nullable. */
 int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_stats *st);
 
+/* qap_batch_dual_ascent for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments and the same results, bitwise; it allocates
+ * nothing.  Its node table, prefix tables and stop counter live in a
+ * file-scope device array of QAP_BATCH_STATIC_BYTES per GPU (held by each GPU
+ * the library runs on until the process ends), set up on the first call on
+ * a device; the iterations are launched one by one (no graph is captured or
+ * instantiated), and the batched Z-LAP mapping is the one the autotuner
+ * already chose in this process or the QAP_TUNE_CACHE file holds, else the
+ * smallest lane group that holds the tiles (every mapping computes the same
+ * LAPs).  Every call on a GPU shares that GPU's array and starts by
+ * rewriting what it uses (the stop counter is cleared by a kernel): calls
+ * that overlap on one GPU race and must be serialised by the caller.
+ * Errors: QAP_EINVAL (count outside 0..QAP_BATCH_STATIC_MAX_NODES, tables
+ * larger than the array), QAP_ESTATE (a handle's bound trace, 1024 entries
+ * from init and grown only by the allocating calls, has no room for the
+ * iterations), and those of qap_batch_dual_ascent. */
+#define QAP_BATCH_STATIC_BYTES 131072
+#define QAP_BATCH_STATIC_MAX_NODES 256
+int qap_batch_dual_ascent_static(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_stats *st);
+
 /* Scalars of a handle: iterations run, bound, incumbent, stop flag and the
  * batch rule that stopped it (0 none, 1 certificate/fathomed, 2 window,
  * 3 min_gap).  Pointers nullable. */

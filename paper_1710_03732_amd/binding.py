@@ -99,6 +99,7 @@ EXPORTED = ("qap_version", "qap_default_params", "qap_workspace_bytes", "qap_rlt
             "qap_destroy", "qap_dual_ascent", "qap_get_trace", "qap_get_assignment",
             "qap_export_state", "qap_export_z_tiles", "qap_import_state", "qap_set_stream", "qap_bnb_solve",
             "qap_lap_batch", "qap_last_error", "qap_fold_child", "qap_batch_dual_ascent",
+            "qap_batch_dual_ascent_static",
             "qap_node_status", "qap_track", "qap_get_multipliers", "qap_set_multipliers",
             "qap_orbit_count", "qap_multiplier_scale", "qap_orbit_features", "qap_orbit_targets",
             "qap_warm_start_outputs", "qap_mlp_create", "qap_mlp_destroy", "qap_mlp_set_stream",
@@ -138,6 +139,8 @@ def lib():
         L.qap_fold_child.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_void_p)]
         L.qap_batch_dual_ascent.argtypes = [C.POINTER(C.c_void_p), C.c_int,
                                             C.POINTER(QapBatchParams), C.POINTER(QapBatchStats)]
+        L.qap_batch_dual_ascent_static.argtypes = [C.POINTER(C.c_void_p), C.c_int,
+                                                   C.POINTER(QapBatchParams), C.POINTER(QapBatchStats)]
         L.qap_node_status.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double), C.POINTER(C.c_int),
                                       C.POINTER(C.c_int)]
@@ -563,12 +566,15 @@ class Mlp:
 
 
 def batch_run(handles, iters: int, window: int = 0, min_improve: float = 0.0,
-              ub_cut: float = float("inf")):
-    """Advance several DualAscent handles (any sizes) with the batched kernels."""
+              ub_cut: float = float("inf"), static: bool = False):
+    """Advance several DualAscent handles (any sizes) with the batched kernels;
+    static=True calls the entry point that allocates nothing
+    (qap_batch_dual_ascent_static)."""
     arr = (C.c_void_p * len(handles))(*[hd.h.value for hd in handles])
     bp = QapBatchParams(int(iters), int(window), float(min_improve), float(ub_cut))
     st = QapBatchStats()
-    code = lib().qap_batch_dual_ascent(arr, len(handles), C.byref(bp), C.byref(st))
+    fn = lib().qap_batch_dual_ascent_static if static else lib().qap_batch_dual_ascent
+    code = fn(arr, len(handles), C.byref(bp), C.byref(st))
     _check(code, handles[0].h if handles else None)
     return {"iterations": st.iterations, "stopped": st.stopped, "fathomed": st.fathomed,
             "window_stops": st.window_stops, "seconds": st.seconds}

@@ -4,6 +4,7 @@
 #pragma once
 #include <algorithm>
 #include <memory>
+#include <mutex>
 
 #include "batch.hpp"
 
@@ -139,6 +140,35 @@ std::vector<std::vector<int>> location_automorphisms(int n, const double *D, con
     return out;
 }
 
+// Workspace of qap_batch_dual_ascent_static: the batch's node table,
+// prefix tables and stop counter.  Each GPU holds its own copy of the array
+// until the process ends; in host code its name is only a stand-in, so the
+// device address is taken once per device (hipGetSymbolAddress, with that
+// device current) and used everywhere host code needs the memory.
+static __device__ __align__(256) char scratch[QAP_BATCH_STATIC_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on h's device (set-up on the first call
+// on that device).
+int static_workspace(qap_ctx *h, char **ws)
+{
+    const int dev = h->prm.device;
+    if (dev < 0 || dev >= kMaxDevices) return fail(h, QAP_EUNSUPPORTED, "device ordinal beyond the static workspace table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        HIPCHK(h, hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(h, QAP_EDEVICE, std::string("static workspace: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (char *)p;
+    }
+    *ws = g_scratch_ptr[dev];
+    return QAP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -210,7 +240,20 @@ int qap_fold_child(qap_handle h, int l, int s, qap_handle *child)
     return QAP_OK;
 }
 
-int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_stats *st)
+}  // extern "C"
+
+namespace {
+
+// The batched dual ascent shared by qap_batch_dual_ascent and
+// qap_batch_dual_ascent_static.  With no_alloc the node table, prefix tables
+// and stop counter go to the per-device static array (ws, ws_bytes), the
+// iterations are launched directly (no captured graph: instantiating one
+// allocates), the batched Z-LAP mapping is the tuned one if this process or
+// the tune cache already holds it (else the rule-based one; every mapping
+// gives the same results), and a handle whose trace has no room for the
+// iterations is refused instead of grown.
+int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_stats *st, bool no_alloc,
+               char *ws, size_t ws_bytes)
 {
     if (count < 0 || (count > 0 && (!hs || !bp))) return fail(nullptr, QAP_EINVAL, "bad batch arguments");
     if (count == 0) return QAP_OK;
@@ -239,8 +282,14 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
         DevScalars s{};
         HIPCHK(h0, hipMemcpy(&s, h->S, sizeof(s), hipMemcpyDeviceToHost));
         stopped0 += s.stopped ? 1 : 0;
-        int rc = ensure_trace(h, s.t + bp->iters + 1);
-        if (rc != QAP_OK) return rc;
+        if (no_alloc) {
+            if (s.t + bp->iters + 1 > h->trace_cap)
+                return fail(h0, QAP_ESTATE, "a handle's bound trace has no room for the iterations (the "
+                                            "allocating entry points grow it)");
+        } else {
+            int rc = ensure_trace(h, s.t + bp->iters + 1);
+            if (rc != QAP_OK) return rc;
+        }
         BNode &N = nodes[b];
         N.Z = h->Z;
         N.Yc = h->Yc;
@@ -285,9 +334,17 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
     }
     // device copies (one allocation): node table, prefix tables, stop counter
     const size_t nb_bytes = round_up(sizeof(BNode) * count), pf_bytes = round_up(sizeof(long long) * (count + 1));
+    const size_t need = nb_bytes + 4 * pf_bytes + 256;
     void *dmem = nullptr;
-    HIPCHK(h0, hipMalloc(&dmem, nb_bytes + 4 * pf_bytes + 256));
-    std::unique_ptr<void, void (*)(void *)> guard(dmem, [](void *p) { (void)hipFree(p); });
+    if (no_alloc) {
+        if (need > ws_bytes) return fail(h0, QAP_EINVAL, "batch tables exceed the static workspace");
+        dmem = ws;
+    } else {
+        HIPCHK(h0, hipMalloc(&dmem, need));
+    }
+    std::unique_ptr<void, void (*)(void *)> guard(no_alloc ? nullptr : dmem, [](void *p) {
+        if (p) (void)hipFree(p);
+    });
     char *dp = (char *)dmem;
     BNode *dnodes = (BNode *)dp;
     long long *dzl = (long long *)(dp + nb_bytes), *dyl = (long long *)(dp + nb_bytes + pf_bytes);
@@ -302,7 +359,8 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
     HIPCHK(h0, hipGetLastError());
     BatchPrefix pf{dzl, dyl, dsw, dsc};
     BatchCtl ctl{bp->ub_cut, bp->min_improve, bp->window, count, dnstop};
-    const int Lz = tuned_batch_lanes(h0->prm.device, stream, mz);  // measured once per tile size
+    // measured once per tile size (looked up only, without allocating)
+    const int Lz = no_alloc ? known_batch_lanes(h0->prm.device, mz) : tuned_batch_lanes(h0->prm.device, stream, mz);
     const int Ly = my <= 8 ? 8 : my <= 16 ? 16 : my <= 32 ? 32 : 64;
     auto launch_all = [&]() -> hipError_t {
         hipError_t e;
@@ -344,7 +402,7 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
         // one captured graph per batch, replayed; the legacy null stream
         // cannot be captured, there every replay launches the kernels
         hipGraphExec_t ge = nullptr;
-        if (stream != nullptr) {
+        if (stream != nullptr && !no_alloc) {
             hipGraph_t g = nullptr;
             HIPCHK(h0, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
             hipError_t le = launch_all();
@@ -401,6 +459,27 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
         hs[b]->t_host = s.t;
     }
     return QAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_stats *st)
+{
+    return batch_core(hs, count, bp, st, false, nullptr, 0);
+}
+
+int qap_batch_dual_ascent_static(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_stats *st)
+{
+    if (count < 0 || count > QAP_BATCH_STATIC_MAX_NODES || (count > 0 && (!hs || !bp)))
+        return fail(nullptr, QAP_EINVAL, "bad batch arguments (count must be 0..QAP_BATCH_STATIC_MAX_NODES)");
+    if (count == 0) return QAP_OK;
+    if (!hs[0]) return QAP_EINVAL;
+    char *ws = nullptr;
+    const int rc = static_workspace(hs[0], &ws);
+    if (rc != QAP_OK) return rc;
+    return batch_core(hs, count, bp, st, true, ws, QAP_BATCH_STATIC_BYTES);
 }
 
 int qap_node_status(qap_handle h, int *t, double *lb, double *ub, int *stopped, int *reason)

@@ -293,6 +293,24 @@ void tune_handle_zlap(qap_ctx *h)
     h->zl_tuned = true;
 }
 
+// The batched Z-LAP mapping for tile size m without measuring (nothing is
+// allocated): this process's or the cache file's choice, else the smallest
+// lane group that holds m.
+int known_batch_lanes(int device, int m)
+{
+    const std::string key = tune_key(device, "bzlap", m);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second.lanes;
+    const char *path = std::getenv("QAP_TUNE_CACHE");
+    if (path && *path) {
+        const auto file = read_tune_file(path);
+        const auto fit = file.find(key);
+        if (fit != file.end()) return fit->second.lanes;
+    }
+    return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 64;
+}
+
 // Batched Z-LAP kernel for a batch whose largest tile is m: a lane count of
 // k_bzlap, or -1 for k_bzlap_s.
 int tuned_batch_lanes(int device, hipStream_t stream, int m)
