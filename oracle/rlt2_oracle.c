@@ -29,6 +29,7 @@
 #endif
 
 #define ORC_MAXM 128
+#define ORC_MAXLAP 1024 /* largest LAP orc_lap takes (the LAP batch entry point goes to 1024) */
 #define ORC_ROOT (-1)
 
 #define IX2(n, i, p) ((size_t)(i) * (size_t)(n) + (size_t)(p))
@@ -83,9 +84,9 @@ int orc_max_threads(void)
 int orc_lap(int m, const double *M, double *u, double *v, int *row_of_col,
             double *theta, long long *steps)
 {
-    double minv[ORC_MAXM];
-    int used[ORC_MAXM], way[ORC_MAXM], prop[ORC_MAXM], owner[ORC_MAXM];
-    if (m < 1 || m > ORC_MAXM) return -1;
+    double minv[ORC_MAXLAP];
+    int used[ORC_MAXLAP], way[ORC_MAXLAP], prop[ORC_MAXLAP], owner[ORC_MAXLAP];
+    if (m < 1 || m > ORC_MAXLAP) return -1;
     for (int i = 0; i < m; ++i) { u[i] = 0.0; owner[i] = -1; }
     for (int j = 0; j < m; ++j) {
         int arg = 0;

@@ -39,7 +39,7 @@ def test_lap_value_equals_brute_force(m):
         assert sorted(rc.tolist()) == list(range(m))
 
 
-@pytest.mark.parametrize("m", [8, 13, 28, 40, 64])
+@pytest.mark.parametrize("m", [8, 13, 28, 40, 64, 65, 129, 300, 1024])
 def test_lap_value_equals_scipy(m):
     rng = np.random.default_rng(7 * m)
     for trial in range(6):
@@ -50,7 +50,12 @@ def test_lap_value_equals_scipy(m):
         assert abs(th - opt) <= 1e-9 * max(1.0, abs(opt))
 
 
-@pytest.mark.parametrize("m", [3, 9, 28])
+def test_lap_refuses_beyond_its_size_limit():
+    with pytest.raises(ValueError):
+        O.lap(np.zeros((1025, 1025)))
+
+
+@pytest.mark.parametrize("m", [3, 9, 28, 200])
 def test_lap_duals_complementary_slackness(m):
     """Dual feasibility u_i + v_j <= M_ij and pi = 0 on the assignment
     (Eq. compslack); the dual objective equals the LAP value."""
