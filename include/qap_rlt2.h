@@ -390,8 +390,12 @@ int qap_node_status(qap_handle h, int *t, double *lb, double *ub, int *stopped, 
  * (count*m, row duals), v (count*m, column duals), theta (count, optimal
  * values), row_of_col (count*m, the row assigned to each column).  All
  * pointers device memory; stream is a hipStream_t or NULL.  lanes/cols select
- * the mapping (0 = default).  Errors: QAP_EINVAL (m < 1 or m > 64, count < 0,
- * NULL pointer), QAP_EDEVICE. */
+ * the mapping of LAPs with m <= 64 (0 = default): one LAP per wavefront or
+ * per lane group, the matrix in LDS.  LAPs with 64 < m <= 1024 run one per
+ * block of 256 threads (block-per-LAP; lanes/cols ignored), the matrix read
+ * from global memory; the results are the same algorithm's, bitwise.
+ * Errors: QAP_EINVAL (m < 1 or m > 1024, count < 0, NULL pointer),
+ * QAP_EDEVICE. */
 int qap_lap_batch(const double *cost, int count, int m, double *u, double *v, double *theta,
                   int32_t *row_of_col, int lanes, int cols, void *stream);
 

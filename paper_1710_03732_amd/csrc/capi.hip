@@ -16,6 +16,7 @@
 
 #include "../../include/qap_rlt2.h"
 #include "kernels.hpp"
+#include "lap_block.hpp"
 
 using namespace qap;
 
@@ -928,12 +929,26 @@ int qap_import_state(qap_handle h, const qap_state_header *hdr, const double *x,
 int qap_lap_batch(const double *cost, int count, int m, double *u, double *v, double *theta,
                   int32_t *row_of_col, int lanes, int cols, void *stream)
 {
-    if (m < 1 || m > 64 || count < 0) return fail(nullptr, QAP_EINVAL, "m must be 1..64, count >= 0");
+    if (m < 1 || m > kBlockLap * 4 || count < 0) return fail(nullptr, QAP_EINVAL, "m must be 1..1024, count >= 0");
     if (count == 0) return QAP_OK;
     if (!cost || !u || !v || !theta || !row_of_col) return fail(nullptr, QAP_EINVAL, "NULL pointer");
+    hipStream_t s = (hipStream_t)stream;
+    if (m > 64) {
+        // larger than a wavefront: one LAP per block of kBlockLap threads,
+        // the matrix read from global memory
+        const int Cb = (m + kBlockLap - 1) / kBlockLap;
+        const size_t lb = block_lap_lds_bytes(m);
+#define QAP_LBB(CC)                                                                                             \
+    if (Cb == CC)                                                                                               \
+        hipLaunchKernelGGL((k_lap_block<CC>), dim3((unsigned)count), dim3(kBlockLap), lb, s, cost, count, m, u, v, \
+                           theta, (int *)row_of_col);
+        QAP_LBB(1) QAP_LBB(2) QAP_LBB(3) QAP_LBB(4)
+#undef QAP_LBB
+        HIPCHK(nullptr, hipGetLastError());
+        return QAP_OK;
+    }
     int L, C;
     pick_zlap(m, lanes, cols, L, C);
-    hipStream_t s = (hipStream_t)stream;
     const size_t per = ((size_t)m * m + 2 * m) * sizeof(double);
     int G = 256 / L;
     while (G > 1 && (size_t)G * per > 65536) --G;

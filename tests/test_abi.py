@@ -95,7 +95,8 @@ def test_half_parameters_are_validated_before_any_device_call():
 def test_lap_batch_rejects_bad_sizes():
     lib = B.lib()
     assert lib.qap_lap_batch(None, 1, 0, None, None, None, None, 0, 0, None) == -1
-    assert lib.qap_lap_batch(None, 1, 65, None, None, None, None, 0, 0, None) == -1
+    assert lib.qap_lap_batch(None, 1, 1025, None, None, None, None, 0, 0, None) == -1
+    assert lib.qap_lap_batch(None, 1, 65, None, None, None, None, 0, 0, None) == -1  # NULL pointers
     assert lib.qap_lap_batch(None, 0, 5, None, None, None, None, 0, 0, None) == 0
 
 

@@ -46,6 +46,28 @@ def _batch(rng, count, m, kind):
     raise ValueError(kind)
 
 
+@pytest.mark.parametrize("m", [65, 100, 128, 200, 256, 257, 300, 513, 1024])
+def test_lap_block_bitwise(m):
+    """LAPs larger than a wavefront (one LAP per 256-thread block, the matrix
+    read from global memory) against the oracle: duals, values and
+    assignments bit for bit, including all-tie and all-zero matrices."""
+    torch = _torch()
+    rng = np.random.default_rng(2000 + m)
+    for kind in ("float", "ties", "neg", "zeros"):
+        count = 3 if m <= 300 else 2
+        cost = _batch(rng, count, m, kind)
+        ref = [O.lap(cost[b]) for b in range(count)]
+        th, u, v, rc = B.lap_batch(torch.from_numpy(cost).cuda())
+        torch.cuda.synchronize()
+        th, u, v, rc = th.cpu().numpy(), u.cpu().numpy(), v.cpu().numpy(), rc.cpu().numpy()
+        for b in range(count):
+            r_th, r_u, r_v, r_rc, _, _ = ref[b]
+            assert th[b] == r_th, (m, kind, b)
+            assert np.array_equal(u[b], r_u), (m, kind, b)
+            assert np.array_equal(v[b], r_v), (m, kind, b)
+            assert np.array_equal(rc[b], r_rc), (m, kind, b)
+
+
 @pytest.mark.parametrize("m", [1, 2, 3, 5, 6, 8, 9, 12, 13, 16, 17, 27, 28, 31, 32, 33, 40, 41, 63, 64])
 def test_lap_batch_bitwise(m):
     torch = _torch()
