@@ -202,6 +202,12 @@ typedef struct qap_batch_params {
     int window;
     double min_improve;
     double ub_cut;         /* +inf for none */
+    int zlap_lanes;        /* Z-LAP mapping: 0 = chosen by timing per tile
+                              size; 8, 16, 32, 64 = lane groups of that many
+                              lanes (>= the largest m); -1 = one tile per
+                              wavefront, -2 = two (m <= 32).  Every mapping
+                              gives the same results.  QAP_EINVAL otherwise. */
+    int reserved;          /* 0 */
 } qap_batch_params;
 
 typedef struct qap_batch_stats {
@@ -209,7 +215,8 @@ typedef struct qap_batch_stats {
     int stopped;           /* handles stopped */
     int fathomed;          /* ... by rule (a) or (b) */
     int window_stops;      /* ... by rule (c) */
-    int pad;
+    int compactions;       /* times the stopped nodes were dropped from the
+                              batch's launches (no effect on results) */
     double seconds;
 } qap_batch_stats;
 
@@ -354,14 +361,17 @@ int qap_fold_child(qap_handle h, int l, int s, qap_handle *child);
 /* Advance `count` independent handles (sizes may differ, one device) by one
  * set of batched kernels per phase and iteration, replayed from one HIP
  * graph, with the node rules above.  Each handle's trajectory is exactly the
- * one qap_dual_ascent would produce until it stops.  hs: host array of
- * handles; st nullable. */
+ * one qap_dual_ascent would produce until it stops.  Every 4 iterations the
+ * host reads how many handles have stopped: it returns once all have, and
+ * once the stopped ones hold an eighth of the launched work it drops them
+ * from the launches (a handle already stopped at the call is never launched).
+ * hs: host array of handles; st nullable. */
 int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_stats *st);
 
 /* qap_batch_dual_ascent for callers that cannot allocate device memory: code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc.  Same arguments and the same results, bitwise; it allocates
- * nothing.  Its node table, prefix tables and stop counter live in a
+ * nothing.  Its node table, prefix tables, stop counter and stop flags live in a
  * file-scope device array of QAP_BATCH_STATIC_BYTES per GPU (held by each GPU
  * the library runs on until the process ends), set up on the first call on
  * a device; the iterations are launched one by one (no graph is captured or

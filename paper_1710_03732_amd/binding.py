@@ -63,12 +63,12 @@ class QapBnbStats(C.Structure):
 
 class QapBatchParams(C.Structure):
     _fields_ = [("iters", C.c_int), ("window", C.c_int), ("min_improve", C.c_double),
-                ("ub_cut", C.c_double)]
+                ("ub_cut", C.c_double), ("zlap_lanes", C.c_int), ("reserved", C.c_int)]
 
 
 class QapBatchStats(C.Structure):
     _fields_ = [("iterations", C.c_longlong), ("stopped", C.c_int), ("fathomed", C.c_int),
-                ("window_stops", C.c_int), ("pad", C.c_int), ("seconds", C.c_double)]
+                ("window_stops", C.c_int), ("compactions", C.c_int), ("seconds", C.c_double)]
 
 
 class QapStateHeader(C.Structure):
@@ -566,18 +566,19 @@ class Mlp:
 
 
 def batch_run(handles, iters: int, window: int = 0, min_improve: float = 0.0,
-              ub_cut: float = float("inf"), static: bool = False):
+              ub_cut: float = float("inf"), static: bool = False, zlap_lanes: int = 0):
     """Advance several DualAscent handles (any sizes) with the batched kernels;
     static=True calls the entry point that allocates nothing
-    (qap_batch_dual_ascent_static)."""
+    (qap_batch_dual_ascent_static); zlap_lanes picks the Z-LAP mapping (0:
+    timed choice; 8..64 lane groups; -1, -2 one or two tiles per wavefront)."""
     arr = (C.c_void_p * len(handles))(*[hd.h.value for hd in handles])
-    bp = QapBatchParams(int(iters), int(window), float(min_improve), float(ub_cut))
+    bp = QapBatchParams(int(iters), int(window), float(min_improve), float(ub_cut), int(zlap_lanes), 0)
     st = QapBatchStats()
     fn = lib().qap_batch_dual_ascent_static if static else lib().qap_batch_dual_ascent
     code = fn(arr, len(handles), C.byref(bp), C.byref(st))
     _check(code, handles[0].h if handles else None)
     return {"iterations": st.iterations, "stopped": st.stopped, "fathomed": st.fathomed,
-            "window_stops": st.window_stops, "seconds": st.seconds}
+            "window_stops": st.window_stops, "compactions": st.compactions, "seconds": st.seconds}
 
 
 def lap_batch(cost, lanes: int = 0, cols: int = 0, stream: int | None = None):

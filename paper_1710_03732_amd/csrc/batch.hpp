@@ -8,7 +8,8 @@
 // block or lane group finds its node by binary search in a prefix table.
 // Every node keeps its own iteration counter and stop flag in its DevScalars,
 // so the same kernel sequence serves every iteration and is replayed from one
-// HIP graph; stopped nodes cost one flag read per job.
+// HIP graph; a stopped node's jobs read its flag and leave, and the host drops
+// stopped nodes from the tables as they accumulate.
 //
 // The arithmetic of every node is exactly that of the single-instance kernels
 // in kernels.hpp (same expressions, same order), so a node's trajectory does
@@ -54,12 +55,27 @@ struct BatchPrefix {
     const long long *sc;  // scale elements (T + n^2)
 };
 
+// A node's arrays are reached through pointers held in the node table, which
+// the compiler cannot place in an address space: used as they are, their
+// accesses are flat operations, and a flat access holds up every later LDS
+// wait as well.  Held as global-space pointers they compile to global loads
+// and stores.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> glob(T *p)
+{
+    return (gptr<T>)p;
+}
+
 __device__ __forceinline__ int find_node(const long long *pre, int nnodes, long long j)
 {
+    const gptr<const long long> p = glob(pre);
     int lo = 0, hi = nnodes - 1;  // largest b with pre[b] <= j
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= j)
+        if (p[mid] <= j)
             lo = mid;
         else
             hi = mid - 1;
@@ -71,21 +87,27 @@ __device__ __forceinline__ int find_node(const long long *pre, int nnodes, long 
 __global__ __launch_bounds__(256) void k_bsweep(const BNode *__restrict__ nodes, BatchPrefix pf, int nnodes)
 {
     __shared__ double gs[6 * SB_CUBE];
-    const long long jb = blockIdx.x;
-    if (jb >= pf.sw[nnodes]) return;
+    // XCD x (blocks are dealt to the 8 XCDs in turn) takes the x-th eighth of
+    // the job numbers in order, so the cubes of one triple run on one XCD back
+    // to back and the partial cache lines at run ends merge in its L2 (as in
+    // k_sweep); the grid is the job count rounded up to a multiple of 8
+    const long long G = glob(pf.sw)[nnodes], per = (G + 7) >> 3;
+    const long long jb = (long long)(blockIdx.x & 7u) * per + (long long)(blockIdx.x >> 3);
+    if (jb >= G) return;
     const int b = find_node(pf.sw, nnodes, jb);
     const BNode &N = nodes[b];
-    if (N.S->stopped || N.S->t < 1) return;
+    if (glob(N.S)->stopped || glob(N.S)->t < 1) return;
     const int nb = N.nb, n = N.n;
-    const int local = (int)(jb - pf.sw[b]);
+    const int local = (int)(jb - glob(pf.sw)[b]);
     const int nb3 = nb * nb * nb;
     const int tri = local / nb3, sub = local % nb3;
     const int base[3] = {(sub / (nb * nb)) * SB, ((sub / nb) % nb) * SB, (sub % nb) * SB};
-    const int packed = N.triples[tri];
+    const int packed = glob(N.triples)[tri];
     const int fi = packed & 0xff, fj = (packed >> 8) & 0xff, fk = (packed >> 16) & 0xff;
     const int m = N.m;
     const long long mm = (long long)m * m;
-    double *Z = N.Z;
+    const gptr<double> Z = glob(N.Z);
+    const gptr<const double> Py = glob((const double *)N.Py), Px = glob((const double *)N.Px);
     const int F1[6] = {fi, fi, fj, fj, fk, fk};
     const int F2[6] = {fj, fk, fi, fk, fi, fj};
     const int F3[6] = {fk, fj, fk, fi, fj, fi};
@@ -106,13 +128,13 @@ __global__ __launch_bounds__(256) void k_bsweep(const BNode *__restrict__ nodes,
             const int f1 = x1 == 0 ? fi : (x1 == 1 ? fj : fk), f2 = x2 == 0 ? fi : (x2 == 1 ? fj : fk);
             const int l1 = (x1 == 0 ? base[0] : (x1 == 1 ? base[1] : base[2])) + a1;
             const int l2 = (x2 == 0 ? base[0] : (x2 == 1 ? base[1] : base[2])) + a2;
-            pys[a] = (l1 < n && l2 < n && l1 != l2) ? N.Py[tile_of(n, f1, l1, f2, l2)] : 0.0;
+            pys[a] = (l1 < n && l2 < n && l1 != l2) ? Py[tile_of(n, f1, l1, f2, l2)] : 0.0;
         }
     }
     if (threadIdx.x < 3 * SB) {
         const int x = threadIdx.x / SB, l = (x == 0 ? base[0] : (x == 1 ? base[1] : base[2])) + threadIdx.x % SB;
         const int f = x == 0 ? fi : (x == 1 ? fj : fk);
-        pxs[threadIdx.x] = l < n ? N.Px[f * n + l] : 0.0;
+        pxs[threadIdx.x] = l < n ? Px[f * n + l] : 0.0;
     }
     long long za[6][PER];
     int li[6][PER];
@@ -143,9 +165,14 @@ __global__ __launch_bounds__(256) void k_bsweep(const BNode *__restrict__ nodes,
             za[e][w] = v ? zrow + (long long)(__umul24((unsigned)l2p, (unsigned)mm) + col) : 0;
             li[e][w] = cube_idx(loc[0] - base[0], loc[1] - base[1], loc[2] - base[2]);
             pz[e][w] = v ? Z[za[e][w]] : 0.0;
-            if (v) gs[e * SB_CUBE + li[e][w]] = pz[e][w];
         }
     }
+    // (every load above is issued before the first LDS write)
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+#pragma unroll
+        for (int w = 0; w < PER; ++w)
+            if (ok[e][w]) gs[e * SB_CUBE + li[e][w]] = pz[e][w];
     __syncthreads();
 #pragma unroll
     for (int w = 0; w < PER; ++w) {
@@ -171,27 +198,40 @@ __global__ __launch_bounds__(256) void k_bsweep(const BNode *__restrict__ nodes,
         }
     }
     __syncthreads();
+    // every new value first, each in registers of its own (each slot's li is
+    // inside the cube, so the reads for slots outside the instance stay in
+    // LDS and are discarded), then the stores.  Computed inside each store's
+    // branch the values would share registers, and each store would wait
+    // for the one before it to complete before its register could be reused.
+    double nz[6][PER];
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+#pragma unroll
+        for (int w = 0; w < PER; ++w) {
+            nz[e][w] = N.okz * pz[e][w] + gs[e * SB_CUBE + li[e][w]];
+            asm volatile("" : "+v"(nz[e][w]));  // (keeps it out of the branch)
+        }
 #pragma unroll
     for (int e = 0; e < 6; ++e)
 #pragma unroll
         for (int w = 0; w < PER; ++w)
-            if (ok[e][w]) Z[za[e][w]] = N.okz * pz[e][w] + gs[e * SB_CUBE + li[e][w]];
+            if (ok[e][w]) Z[za[e][w]] = nz[e][w];
 }
 
 // The x/y scaling after the sweep has read pi_x, pi_y.
 __global__ void k_bscale(const BNode *__restrict__ nodes, BatchPrefix pf, int nnodes)
 {
-    const long long total = pf.sc[nnodes];
+    const long long total = glob(pf.sc)[nnodes];
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
         const int b = find_node(pf.sc, nnodes, e);
         const BNode &N = nodes[b];
-        if (N.S->stopped || N.S->t < 1) continue;
-        const long long a = e - pf.sc[b];
+        if (glob(N.S)->stopped || glob(N.S)->t < 1) continue;
+        const long long a = e - glob(pf.sc)[b];
         if (a < N.T)
-            N.Yc[a] = N.oky * N.Py[a];
+            glob(N.Yc)[a] = N.oky * glob(N.Py)[a];
         else
-            N.Xc[a - N.T] = N.okx * N.Px[a - N.T];
+            glob(N.Xc)[a - N.T] = N.okx * glob(N.Px)[a - N.T];
     }
 }
 
@@ -208,19 +248,19 @@ __global__ __launch_bounds__(256) void k_bzlap(const BNode *__restrict__ nodes, 
     const long long jg = (long long)blockIdx.x * G + g;
     const int per = mmax * mmax + 2 * mmax;
     double *M = lds + (size_t)g * per;
-    bool live = jg < pf.zl[nnodes];
+    bool live = jg < glob(pf.zl)[nnodes];
     int b = 0;
     if (live) {
         b = find_node(pf.zl, nnodes, jg);
-        live = !nodes[b].S->stopped;
+        live = !glob(nodes[b].S)->stopped;
     }
     if (!live) return;  // whole groups leave together; no block barrier below
     const BNode &N = nodes[b];
     const int m = N.m, mm = m * m;
-    const long long t = jg - pf.zl[b];
-    double *src = N.Z + t * mm;
-    copy_to_lds(M, src, mm, l, L);
-    const double yc0 = N.Yc[t];  // read now, added to after the solve
+    const long long t = jg - glob(pf.zl)[b];
+    const gptr<double> src = glob(N.Z) + t * mm, Yc = glob(N.Yc);
+    copy_to_lds(M, (const double *)src, mm, l, L);
+    const double yc0 = Yc[t];  // read now, added to after the solve
     double *lu = M + mm;
     int *lp = (int *)(lu + m);
     int *lw = lp + m;
@@ -234,8 +274,8 @@ __global__ __launch_bounds__(256) void k_bzlap(const BNode *__restrict__ nodes, 
     __builtin_amdgcn_wave_barrier();
     for (int e = l; e < mm; e += L) src[e] = (M[e] - lu[e / m]) - vs[e % m];
     if (l == 0) {
-        N.Yc[t] = yc0 + th;
-        atomicAdd(&N.bins[jg & (kStepBins - 1)], (unsigned long long)st);
+        Yc[t] = yc0 + th;
+        atomicAdd((unsigned long long *)(glob(N.bins) + (jg & (kStepBins - 1))), (unsigned long long)st);
     }
 }
 
@@ -246,16 +286,16 @@ __global__ __launch_bounds__(64) void k_bzlap_s(const BNode *__restrict__ nodes,
 {
     extern __shared__ double lds[];
     const long long jg = blockIdx.x;
-    if (jg >= pf.zl[nnodes]) return;
+    if (jg >= glob(pf.zl)[nnodes]) return;
     const int b = find_node(pf.zl, nnodes, jg);
     const BNode &N = nodes[b];
-    if (N.S->stopped) return;  // the whole block (one wave) leaves together
+    if (glob(N.S)->stopped) return;  // the whole block (one wave) leaves together
     const int lane = threadIdx.x;
     const int m = N.m, mm = m * m;
-    const long long t = jg - pf.zl[b];
-    double *src = N.Z + t * mm;
-    copy_to_lds(lds, src, mm, lane, 64);
-    const double yc0 = N.Yc[t];  // read now, added to after the solve
+    const long long t = jg - glob(pf.zl)[b];
+    const gptr<double> src = glob(N.Z) + t * mm, Yc = glob(N.Yc);
+    copy_to_lds(lds, (const double *)src, mm, lane, 64);
+    const double yc0 = Yc[t];  // read now, added to after the solve
     __syncthreads();
     double u, v, th;
     int p, st;
@@ -271,9 +311,48 @@ __global__ __launch_bounds__(64) void k_bzlap_s(const BNode *__restrict__ nodes,
         for (int r = sub; r < m; r += 2) src[r * m + col] = (lds[r * m + col] - scr[r]) - vc;
     }
     if (lane == 0) {
-        N.Yc[t] = yc0 + th;
-        atomicAdd(&N.bins[jg & (kStepBins - 1)], (unsigned long long)st);
+        Yc[t] = yc0 + th;
+        atomicAdd((unsigned long long *)(glob(N.bins) + (jg & (kStepBins - 1))), (unsigned long long)st);
     }
+}
+
+// Two tiles per wavefront (m <= 32): wave w takes tiles 2w and 2w+1, which
+// belong to one node (every node has an even number of tiles, n^2 (n-1)^2,
+// so every node's first tile is even); the work per tile is k_zlap_s<2>'s.
+__global__ __launch_bounds__(64) void k_bzlap_s2(const BNode *__restrict__ nodes, BatchPrefix pf, int nnodes)
+{
+    extern __shared__ double lds[];
+    const long long j0 = 2 * (long long)blockIdx.x;
+    if (j0 >= glob(pf.zl)[nnodes]) return;
+    const int b = find_node(pf.zl, nnodes, j0);
+    const BNode &N = nodes[b];
+    if (glob(N.S)->stopped) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const int h = lane >> 5, l = lane & 31;
+    const int m = N.m, mm = m * m;
+    const long long t0 = j0 - glob(pf.zl)[b];
+    const gptr<double> src = glob(N.Z) + t0 * mm, Yc = glob(N.Yc);
+    copy_to_lds(lds, (const double *)src, 2 * mm, lane, 64);
+    const double yc0 = Yc[t0 + h];  // read now, added to after the solve
+    double *scr = lds + 2 * mm;
+    const int toff[2] = {0, mm}, soff[2] = {2 * mm, 2 * mm + 2 * m};
+    __syncthreads();
+    double u, v, th;
+    int p, st;
+    lap_solve_scalar2(lds, toff, soff, m, 2, u, v, p, th, st);
+    __builtin_amdgcn_wave_barrier();
+    if (l < m) scr[h * 2 * m + m + l] = v;
+    __syncthreads();
+    if (l < m) {
+        const double *us = scr + h * 2 * m;
+        const double vc = us[m + l];
+        const double *tl = lds + h * mm;
+        const gptr<double> dst = src + h * mm;
+        for (int r = 0; r < m; ++r) dst[r * m + l] = (tl[r * m + l] - us[r]) - vc;
+    }
+    if (l == 0) Yc[t0 + h] = yc0 + th;
+    const int stt = __builtin_amdgcn_readlane(st, 0) + __builtin_amdgcn_readlane(st, 32);
+    if (lane == 0) atomicAdd((unsigned long long *)(glob(N.bins) + (j0 & (kStepBins - 1))), (unsigned long long)stt);
 }
 
 // ----------------------------------------------------------------- Y-LAP --
@@ -288,31 +367,33 @@ __global__ __launch_bounds__(256) void k_bylap(const BNode *__restrict__ nodes, 
     const long long jg = (long long)blockIdx.x * G + g;
     const int per = mmax * mmax + 2 * mmax;
     double *M = lds + (size_t)g * per;
-    bool live = jg < pf.yl[nnodes];
+    bool live = jg < glob(pf.yl)[nnodes];
     int b = 0;
     if (live) {
         b = find_node(pf.yl, nnodes, jg);
-        live = !nodes[b].S->stopped;
+        live = !glob(nodes[b].S)->stopped;
     }
     if (!live) return;
     const BNode &N = nodes[b];
     const int n = N.n, m = n - 1, mm = m * m;
-    const int ip = (int)(jg - pf.yl[b]);
+    const int ip = (int)(jg - glob(pf.yl)[b]);
     const int i = ip / n, p = ip % n;
-    const bool equalize = N.S->t >= 1;
+    const bool equalize = glob(N.S)->t >= 1;
     const long long base = (long long)ip * mm;
-    const double xc0 = N.Xc[ip];  // read now, added to after the solve
+    const gptr<const double> Yc = glob((const double *)N.Yc);
+    const gptr<double> Xc = glob(N.Xc), Py = glob(N.Py);
+    const double xc0 = Xc[ip];  // read now, added to after the solve
     for (int e0 = 0; e0 < mm; e0 += 8 * L) {
         double av[8], bv[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int e = e0 + l + L * k;
             if (e < mm) {
-                av[k] = N.Yc[base + e];
+                av[k] = Yc[base + e];
                 if (equalize) {
                     const int jp = e / m, qp = e % m;
                     const int j = jp + (jp >= i), q = qp + (qp >= p);
-                    bv[k] = N.Yc[((long long)(j * n + q) * m + (i - (i > j))) * m + (p - (p > q))];
+                    bv[k] = Yc[((long long)(j * n + q) * m + (i - (i > j))) * m + (p - (p > q))];
                 }
             }
         }
@@ -333,11 +414,18 @@ __global__ __launch_bounds__(256) void k_bylap(const BNode *__restrict__ nodes, 
     double *vs = lu + m;
     if (l < m) vs[l] = v[0];
     __builtin_amdgcn_wave_barrier();
-    for (int e = l; e < mm; e += L) N.Py[base + e] = (M[e] - lu[e / m]) - vs[e % m];
+    for (int e = l; e < mm; e += L) Py[base + e] = (M[e] - lu[e / m]) - vs[e % m];
     if (l == 0) {
-        N.Xc[ip] = xc0 + th;
-        atomicAdd(&N.bins[jg & (kStepBins - 1)], (unsigned long long)st);
+        Xc[ip] = xc0 + th;
+        atomicAdd((unsigned long long *)(glob(N.bins) + (jg & (kStepBins - 1))), (unsigned long long)st);
     }
+}
+
+// Each node's stop flag, for the host to drop stopped nodes from the tables.
+__global__ void k_bstopped(const BNode *__restrict__ nodes, int nnodes, int *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nnodes) out[i] = glob(nodes[i].S)->stopped;
 }
 
 // ----------------------------------------------------------------- X-LAP --
@@ -348,7 +436,7 @@ __global__ __launch_bounds__(256) void k_bylap(const BNode *__restrict__ nodes, 
 __global__ __launch_bounds__(64) void k_bxlap(const BNode *__restrict__ nodes, BatchCtl ctl)
 {
     const BNode &N = nodes[blockIdx.x];
-    DevScalars *S = N.S;
+    const gptr<DevScalars> S = glob(N.S);
     if (S->stopped) return;
     __shared__ double M[64 * 64];
     __shared__ double lu[64], vs[64];
@@ -357,29 +445,29 @@ __global__ __launch_bounds__(64) void k_bxlap(const BNode *__restrict__ nodes, B
     __shared__ int improved;
     const int l = threadIdx.x;
     const int n = N.n, nn = n * n;
-    copy_to_lds(M, N.Xc, nn, l, 64);
+    copy_to_lds(M, (const double *)glob((const double *)N.Xc), nn, l, 64);
     __syncthreads();
     double u[1], v[1], th;
     int pc[1], st = 0;
     lap_solve<64, 1>(M, n, l, 0, lu, lp, lw, u, v, pc, th, st);
     if (l < n) {
         vs[l] = v[0];
-        N.alpha[l] = u[0];
-        N.beta[l] = v[0];
+        glob(N.alpha)[l] = u[0];
+        glob(N.beta)[l] = v[0];
         sig[pc[0]] = l;
     }
     __syncthreads();
-    for (int e = l; e < nn; e += 64) N.Px[e] = (M[e] - lu[e / n]) - vs[e % n];
+    for (int e = l; e < nn; e += 64) glob(N.Px)[e] = (M[e] - lu[e / n]) - vs[e % n];
     double cd = 0.0;
     long long ci = 0;
     if (l < n) {
         const int si = sig[l];
         if (N.integer_data) {
-            ci = (long long)N.B[l * n + si];
-            for (int jj = 0; jj < n; ++jj) ci += (long long)N.F[l * n + jj] * (long long)N.D[si * n + sig[jj]];
+            ci = (long long)glob(N.B)[l * n + si];
+            for (int jj = 0; jj < n; ++jj) ci += (long long)glob(N.F)[l * n + jj] * (long long)glob(N.D)[si * n + sig[jj]];
         } else {
-            cd = N.B[l * n + si];
-            for (int jj = 0; jj < n; ++jj) cd = cd + N.F[l * n + jj] * N.D[si * n + sig[jj]];
+            cd = glob(N.B)[l * n + si];
+            for (int jj = 0; jj < n; ++jj) cd = cd + glob(N.F)[l * n + jj] * glob(N.D)[si * n + sig[jj]];
         }
     }
 #pragma unroll
@@ -400,7 +488,7 @@ __global__ __launch_bounds__(64) void k_bxlap(const BNode *__restrict__ nodes, B
         S->steps += (unsigned long long)st;
         S->best = fmax(S->best, lb);
         const int t = S->t;
-        if (t < N.trace_cap) N.trace[t] = lb;
+        if (t < N.trace_cap) glob(N.trace)[t] = lb;
         S->t = t + 1;
         int proven = 0;
         if (ub < kInf) {
@@ -425,7 +513,7 @@ __global__ __launch_bounds__(64) void k_bxlap(const BNode *__restrict__ nodes, B
         if (!stop && ctl.min_improve > 0.0 && t + 1 > ctl.window && t + 1 - ctl.window - 1 >= 0 &&
             t + 1 - ctl.window - 1 < N.trace_cap) {
             const double ref = (cut < kInf) ? fabs(cut) : fabs(lb);
-            if (lb - N.trace[t - ctl.window] < ctl.min_improve * fmax(1.0, ref)) {
+            if (lb - glob(N.trace)[t - ctl.window] < ctl.min_improve * fmax(1.0, ref)) {
                 stop = 1;
                 reason = 2;
             }
@@ -437,8 +525,8 @@ __global__ __launch_bounds__(64) void k_bxlap(const BNode *__restrict__ nodes, B
     }
     __syncthreads();
     if (l < n) {
-        N.xperm[l] = sig[l];
-        if (improved) N.bestperm[l] = sig[l];
+        glob(N.xperm)[l] = sig[l];
+        if (improved) glob(N.bestperm)[l] = sig[l];
     }
 }
 

@@ -258,6 +258,11 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
     if (count < 0 || (count > 0 && (!hs || !bp))) return fail(nullptr, QAP_EINVAL, "bad batch arguments");
     if (count == 0) return QAP_OK;
     if (bp->iters < 0 || bp->window < 0 || bp->window > 1000) return fail(hs[0], QAP_EINVAL, "bad batch params");
+    {
+        const int zl = bp->zlap_lanes;
+        if (!(zl == 0 || zl == -1 || zl == -2 || zl == 8 || zl == 16 || zl == 32 || zl == 64))
+            return fail(hs[0], QAP_EINVAL, "zlap_lanes must be 0, -1, -2, 8, 16, 32 or 64");
+    }
     qap_ctx *h0 = hs[0];
     if (!h0) return QAP_EINVAL;
     hipStream_t stream = h0->stream;
@@ -273,9 +278,11 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
     auto t0 = std::chrono::steady_clock::now();
     HIPCHK(h0, hipSetDevice(h0->prm.device));
     for (int b = 0; b < count; ++b) HIPCHK(h0, hipStreamSynchronize(hs[b]->stream));
-    // node table and prefix tables
-    std::vector<BNode> nodes(count);
-    std::vector<long long> zl(count + 1, 0), yl(count + 1, 0), sw(count + 1, 0), sc(count + 1, 0);
+    // node descriptors of every handle; the tables hold the nodes still
+    // running (a stopped node's jobs would only read its flag and leave)
+    std::vector<BNode> all(count);
+    std::vector<int> ids;
+    std::vector<long long> work(count, 0);
     int mz = 1, my = 1, stopped0 = 0;
     for (int b = 0; b < count; ++b) {
         qap_ctx *h = hs[b];
@@ -290,7 +297,7 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
             int rc = ensure_trace(h, s.t + bp->iters + 1);
             if (rc != QAP_OK) return rc;
         }
-        BNode &N = nodes[b];
+        BNode &N = all[b];
         N.Z = h->Z;
         N.Yc = h->Yc;
         N.Py = h->Py;
@@ -325,16 +332,17 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
         N.okx = h->okx;
         N.phy = h->phy;
         N.ophy = h->ophy;
-        zl[b + 1] = zl[b] + h->T;
-        yl[b + 1] = yl[b] + (long long)h->n * h->n;
-        sw[b + 1] = sw[b] + (long long)h->ntriples * N.nb * N.nb * N.nb;
-        sc[b + 1] = sc[b] + h->T + (long long)h->n * h->n;
-        mz = std::max(mz, h->m);
-        my = std::max(my, h->n - 1);
+        work[b] = h->T * (long long)h->m * h->m + h->T + (long long)h->n * h->n;
+        if (!s.stopped) {
+            ids.push_back(b);
+            mz = std::max(mz, h->m);
+            my = std::max(my, h->n - 1);
+        }
     }
-    // device copies (one allocation): node table, prefix tables, stop counter
+    // device copies (one allocation): node table, prefix tables, stop
+    // counter, per-node stop flags
     const size_t nb_bytes = round_up(sizeof(BNode) * count), pf_bytes = round_up(sizeof(long long) * (count + 1));
-    const size_t need = nb_bytes + 4 * pf_bytes + 256;
+    const size_t need = nb_bytes + 4 * pf_bytes + 256 + round_up(sizeof(int) * count);
     void *dmem = nullptr;
     if (no_alloc) {
         if (need > ws_bytes) return fail(h0, QAP_EINVAL, "batch tables exceed the static workspace");
@@ -349,23 +357,57 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
     BNode *dnodes = (BNode *)dp;
     long long *dzl = (long long *)(dp + nb_bytes), *dyl = (long long *)(dp + nb_bytes + pf_bytes);
     long long *dsw = (long long *)(dp + nb_bytes + 2 * pf_bytes), *dsc = (long long *)(dp + nb_bytes + 3 * pf_bytes);
-    HIPCHK(h0, hipMemcpyAsync(dnodes, nodes.data(), sizeof(BNode) * count, hipMemcpyHostToDevice, stream));
-    HIPCHK(h0, hipMemcpyAsync(dzl, zl.data(), sizeof(long long) * (count + 1), hipMemcpyHostToDevice, stream));
-    HIPCHK(h0, hipMemcpyAsync(dyl, yl.data(), sizeof(long long) * (count + 1), hipMemcpyHostToDevice, stream));
-    HIPCHK(h0, hipMemcpyAsync(dsw, sw.data(), sizeof(long long) * (count + 1), hipMemcpyHostToDevice, stream));
-    HIPCHK(h0, hipMemcpyAsync(dsc, sc.data(), sizeof(long long) * (count + 1), hipMemcpyHostToDevice, stream));
     int *dnstop = (int *)(dp + nb_bytes + 4 * pf_bytes);
+    int *dflags = (int *)(dp + nb_bytes + 4 * pf_bytes + 256);
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, stream, (double *)dnstop, (size_t)1, 0.0);  // zeroes the counter
     HIPCHK(h0, hipGetLastError());
+    // the tables of the nodes in ids; their host copies stay unchanged until
+    // the stream has drained (the next poll)
+    std::vector<BNode> nodes;
+    std::vector<long long> zl, yl, sw, sc;
+    int cur = 0;
+    auto upload = [&]() -> hipError_t {
+        cur = (int)ids.size();
+        nodes.resize(cur);
+        zl.assign(cur + 1, 0);
+        yl.assign(cur + 1, 0);
+        sw.assign(cur + 1, 0);
+        sc.assign(cur + 1, 0);
+        for (int i = 0; i < cur; ++i) {
+            const BNode &N = all[ids[i]];
+            nodes[i] = N;
+            zl[i + 1] = zl[i] + N.T;
+            yl[i + 1] = yl[i] + (long long)N.n * N.n;
+            sw[i + 1] = sw[i] + (long long)N.ntri * N.nb * N.nb * N.nb;
+            sc[i + 1] = sc[i] + N.T + (long long)N.n * N.n;
+        }
+        if (cur == 0) return hipSuccess;
+        hipError_t e;
+        if ((e = hipMemcpyAsync(dnodes, nodes.data(), sizeof(BNode) * cur, hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return e;
+        const size_t pb = sizeof(long long) * (cur + 1);
+        if ((e = hipMemcpyAsync(dzl, zl.data(), pb, hipMemcpyHostToDevice, stream)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(dyl, yl.data(), pb, hipMemcpyHostToDevice, stream)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(dsw, sw.data(), pb, hipMemcpyHostToDevice, stream)) != hipSuccess) return e;
+        return hipMemcpyAsync(dsc, sc.data(), pb, hipMemcpyHostToDevice, stream);
+    };
+    HIPCHK(h0, upload());
     BatchPrefix pf{dzl, dyl, dsw, dsc};
     BatchCtl ctl{bp->ub_cut, bp->min_improve, bp->window, count, dnstop};
     // measured once per tile size (looked up only, without allocating)
-    const int Lz = no_alloc ? known_batch_lanes(h0->prm.device, mz) : tuned_batch_lanes(h0->prm.device, stream, mz);
+    if ((bp->zlap_lanes > 0 && bp->zlap_lanes < mz) || (bp->zlap_lanes < 0 && mz > 32))
+        return fail(h0, QAP_EINVAL, "zlap_lanes does not hold the batch's largest tile");
+    const int Lz = cur == 0 ? -1
+                   : bp->zlap_lanes != 0 ? bp->zlap_lanes
+                   : no_alloc ? known_batch_lanes(h0->prm.device, mz)
+                              : tuned_batch_lanes(h0->prm.device, stream, mz);
     const int Ly = my <= 8 ? 8 : my <= 16 ? 16 : my <= 32 ? 32 : 64;
     auto launch_all = [&]() -> hipError_t {
         hipError_t e;
+        const int count = cur;  // the nodes in the tables
         if (sw[count] > 0) {
-            hipLaunchKernelGGL(k_bsweep, dim3((unsigned)sw[count]), dim3(256), 0, stream, dnodes, pf, count);
+            const unsigned grid = (unsigned)((sw[count] + 7) / 8 * 8);  // k_bsweep deals eighths to the XCDs
+            hipLaunchKernelGGL(k_bsweep, dim3(grid), dim3(256), 0, stream, dnodes, pf, count);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         const unsigned sb = (unsigned)std::min<long long>((sc[count] + 255) / 256, 65535);
@@ -382,6 +424,9 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
 #undef QAP_BZ
             if (Lz == -1)  // one tile per wavefront
                 hipLaunchKernelGGL(k_bzlap_s, dim3((unsigned)zl[count]), dim3(64), per, stream, dnodes, pf, count);
+            if (Lz == -2)  // two tiles per wavefront (every node's tile count is even)
+                hipLaunchKernelGGL(k_bzlap_s2, dim3((unsigned)(zl[count] / 2)), dim3(64), 2 * per, stream, dnodes, pf,
+                                   count);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         {
@@ -398,46 +443,88 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
         hipLaunchKernelGGL(k_bxlap, dim3(count), dim3(64), 0, stream, dnodes, ctl);
         return hipGetLastError();
     };
-    if (bp->iters > 0) {
-        // one captured graph per batch, replayed; the legacy null stream
-        // cannot be captured, there every replay launches the kernels
+    int compactions = 0;
+    if (bp->iters > 0 && cur > 0) {
+        // one captured graph of the tables' kernels, replayed; the legacy
+        // null stream cannot be captured, there every replay launches the
+        // kernels
         hipGraphExec_t ge = nullptr;
-        if (stream != nullptr && !no_alloc) {
+        const bool use_graph = stream != nullptr && !no_alloc;
+        auto capture = [&]() -> std::string {
             hipGraph_t g = nullptr;
-            HIPCHK(h0, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            hipError_t be = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+            if (be != hipSuccess) return std::string("batch capture: ") + hipGetErrorString(be);
             hipError_t le = launch_all();
             hipError_t ce = hipStreamEndCapture(stream, &g);
-            if (le != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch launch: ") + hipGetErrorString(le));
-            if (ce != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch capture: ") + hipGetErrorString(ce));
+            if (le != hipSuccess) return std::string("batch launch: ") + hipGetErrorString(le);
+            if (ce != hipSuccess) return std::string("batch capture: ") + hipGetErrorString(ce);
             hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
-            if (ie != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch graph: ") + hipGetErrorString(ie));
+            if (ie != hipSuccess) {
+                ge = nullptr;
+                return std::string("batch graph: ") + hipGetErrorString(ie);
+            }
+            return std::string();
+        };
+        if (use_graph) {
+            const std::string err = capture();
+            if (!err.empty()) return fail(h0, QAP_EDEVICE, err);
         }
         // replays; every kPoll of them the host reads how many nodes have
-        // stopped and ends the batch once all have (further replays would
-        // only launch jobs that find their node stopped)
+        // stopped and ends the batch once all have.  When nodes stopped since
+        // the last look, it reads which, and once they hold at least an
+        // eighth of the tables' work it drops them from the tables (and
+        // captures the smaller graph): a node's arithmetic does not depend
+        // on which other nodes share its launches.
         constexpr int kPoll = 4;
-        for (int it = 0; it < bp->iters; ++it) {
+        int seen = 0;
+        std::vector<int> flags;
+        std::string err;
+        for (int it = 0; it < bp->iters && err.empty(); ++it) {
             hipError_t e2 = ge ? hipGraphLaunch(ge, stream) : launch_all();
             if (e2 == hipSuccess && (it + 1) % kPoll == 0 && it + 1 < bp->iters) {
                 int ns = 0;
                 e2 = hipMemcpyAsync(&ns, dnstop, sizeof(int), hipMemcpyDeviceToHost, stream);
                 if (e2 == hipSuccess) e2 = hipStreamSynchronize(stream);
                 if (e2 == hipSuccess && stopped0 + ns >= count) break;
+                if (e2 == hipSuccess && ns > seen) {
+                    seen = ns;
+                    flags.assign(cur, 0);
+                    hipLaunchKernelGGL(k_bstopped, dim3((cur + 255) / 256), dim3(256), 0, stream, dnodes, cur, dflags);
+                    e2 = hipGetLastError();
+                    if (e2 == hipSuccess)
+                        e2 = hipMemcpyAsync(flags.data(), dflags, sizeof(int) * cur, hipMemcpyDeviceToHost, stream);
+                    if (e2 == hipSuccess) e2 = hipStreamSynchronize(stream);
+                    long long w_all = 0, w_live = 0;
+                    std::vector<int> keep;
+                    for (int i = 0; e2 == hipSuccess && i < cur; ++i) {
+                        w_all += work[ids[i]];
+                        if (!flags[i]) {
+                            keep.push_back(ids[i]);
+                            w_live += work[ids[i]];
+                        }
+                    }
+                    if (e2 == hipSuccess && 8 * (w_all - w_live) >= w_all) {
+                        // the stream has drained: no replay reads the old
+                        // tables or the old exec's arguments any more
+                        if (ge) (void)hipGraphExecDestroy(ge);
+                        ge = nullptr;
+                        ids.swap(keep);
+                        ++compactions;
+                        e2 = upload();
+                        if (e2 == hipSuccess && cur == 0) break;
+                        if (e2 == hipSuccess && use_graph) err = capture();
+                    }
+                }
             }
-            if (e2 != hipSuccess) {
-                // replays already queued still read the exec's kernel
-                // arguments: drain the stream before destroying it
-                (void)hipStreamSynchronize(stream);
-                if (ge) (void)hipGraphExecDestroy(ge);
-                return fail(h0, QAP_EDEVICE, std::string("batch replay: ") + hipGetErrorString(e2));
-            }
+            if (e2 != hipSuccess) err = std::string("batch replay: ") + hipGetErrorString(e2);
         }
         // the graph exec owns the kernel arguments of its nodes; replays
         // still in the stream's queue read them when they are dispatched,
         // so the exec is destroyed only after the stream has drained
         const hipError_t se = hipStreamSynchronize(stream);
         if (ge) (void)hipGraphExecDestroy(ge);
+        if (!err.empty()) return fail(h0, QAP_EDEVICE, err);
         if (se != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch sync: ") + hipGetErrorString(se));
     }
     HIPCHK(h0, hipStreamSynchronize(stream));
@@ -451,6 +538,7 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
             st->fathomed += s.reason == 1 ? 1 : 0;
             st->window_stops += s.reason == 2 ? 1 : 0;
         }
+        st->compactions = compactions;
         st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     for (int b = 0; b < count; ++b) {

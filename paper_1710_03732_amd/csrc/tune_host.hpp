@@ -225,8 +225,9 @@ TuneChoice measure_zlap(hipStream_t stream, int m, int zlap_waves)
 }
 
 // Fastest batched Z-LAP kernel for tiles of size m (one node): lane groups
-// of 8..64 (k_bzlap<L>, L >= m) or one tile per wavefront (k_bzlap_s, lanes
-// -1, m <= 32); falls back to the smallest group that holds m.
+// of 8..64 (k_bzlap<L>, L >= m), or one or two tiles per wavefront
+// (k_bzlap_s, lanes -1, and k_bzlap_s2, lanes -2; m <= 32); falls back to
+// the smallest group that holds m.
 TuneChoice measure_bzlap(hipStream_t stream, int m)
 {
     TuneChoice best{m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 64, 1, -1.0};
@@ -277,6 +278,12 @@ TuneChoice measure_bzlap(hipStream_t stream, int m)
         };
         const double us = time_launches(stream, work, src, count, launch);
         if (us >= 0.0 && (best.us < 0.0 || us < best.us)) best = TuneChoice{-1, 1, us};
+        auto launch2 = [&]() -> hipError_t {
+            hipLaunchKernelGGL(k_bzlap_s2, dim3((unsigned)(N / 2)), dim3(64), 2 * per, stream, dnode, pf, 1);
+            return hipGetLastError();
+        };
+        const double us2 = time_launches(stream, work, src, count, launch2);
+        if (us2 >= 0.0 && (best.us < 0.0 || us2 < best.us)) best = TuneChoice{-2, 1, us2};
     }
     (void)hipStreamSynchronize(stream);
     return best;
@@ -312,7 +319,7 @@ int known_batch_lanes(int device, int m)
 }
 
 // Batched Z-LAP kernel for a batch whose largest tile is m: a lane count of
-// k_bzlap, or -1 for k_bzlap_s.
+// k_bzlap, -1 for k_bzlap_s or -2 for k_bzlap_s2.
 int tuned_batch_lanes(int device, hipStream_t stream, int m)
 {
     return tuned_choice(tune_key(device, "bzlap", m), [&] { return measure_bzlap(stream, m); }).lanes;

@@ -133,6 +133,85 @@ def test_batch_of_mixed_depth_children_bitwise():
         g.close()
 
 
+@pytest.mark.parametrize("lanes", [-2, -1, 16, 32])
+def test_batch_zlap_mappings_bitwise(lanes):
+    """Each batched Z-LAP mapping (two or one tiles per wavefront, 16- and
+    32-lane groups) over 15 children of the n = 14 dense instance (reduced
+    sizes 13, 12, 11: tiles of 11, 10, 9) gives every child exactly the
+    oracle's trace and state after 4 iterations."""
+    F, D, Bm = I.dense_n14().arrays()
+    gpu, cpu = _mixed_depth_children(F, D, Bm, [6, 5, 4], seed=5)
+    st = B.batch_run(gpu, iters=4, zlap_lanes=lanes)
+    for k, (g, c) in enumerate(zip(gpu, cpu)):
+        c.run(4)
+        assert np.array_equal(g.trace(), c.trace()), (k, g.n)
+        _state_equal(g, c)
+    assert st["iterations"] == 4 * len(gpu)
+    for g in gpu:
+        g.close()
+
+
+def test_batch_zlap_mapping_refused_when_too_small():
+    """A lane group narrower than the largest tile, or a lane count that is
+    no mapping, is refused before any iteration runs."""
+    F, D, Bm = I.dense_instance(12, 3).arrays()  # tiles of 10
+    g = B.DualAscent(F, D, Bm)
+    for lanes in (8, 5, -3):
+        with pytest.raises(B.QapError):
+            B.batch_run([g], iters=2, zlap_lanes=lanes)
+        assert g.status()["t"] == 0
+    g.close()
+
+
+def _oracle_node_under_batch_rules(c, iters, window, min_improve):
+    """The oracle's node run one iteration at a time under the batch's node
+    rules with no incumbent cut (Section 4's fathoming, which for integer
+    data is ceil(LB) >= UB, and Section 5.4's window rule: stop when the
+    bound rose by less than min_improve * max(1, |UB|) over the last `window`
+    iterations).  Returns (iterations run, reason: 0 none, 1 fathomed, 2
+    window)."""
+    lbs = []
+    for t in range(iters):
+        c.iterate()
+        lb, ub = float(c.trace()[-1]), c.UB
+        lbs.append(lb)
+        tol = 1e-9 * max(1.0, abs(ub))
+        if np.ceil(lb - tol) >= ub:
+            return t + 1, 1
+        if t + 1 > window and lb - lbs[t - window] < min_improve * max(1.0, abs(ub)):
+            return t + 1, 2
+    return iters, 0
+
+
+@pytest.mark.parametrize("static", [False, True], ids=["graph", "static"])
+def test_batch_nodes_stopping_apart_bitwise(static):
+    """34 children of an n = 11 dense instance (reduced sizes 10 down to 7)
+    under the window rule stop between iterations 2 and 24, so the host drops
+    stopped nodes from the launches while the others run on.  Every node
+    stops at the iteration, and for the reason, that the oracle's run under
+    the same rules gives, with the same bound trace and final state, bit for
+    bit."""
+    F, D, Bm = I.dense_instance(11, 1).arrays()
+    assert np.array_equal(F, np.round(F)) and np.array_equal(D, np.round(D))
+    gpu, cpu = _mixed_depth_children(F, D, Bm, [10, 10, 8, 6], seed=1)
+    iters, window, mi = 24, 3, 5e-4
+    st = B.batch_run(gpu, iters=iters, window=window, min_improve=mi, static=static)
+    ran = []
+    for k, (g, c) in enumerate(zip(gpu, cpu)):
+        t, reason = _oracle_node_under_batch_rules(c, iters, window, mi)
+        s = g.status()
+        assert (s["t"], s["reason"], bool(s["stopped"])) == (t, reason, reason != 0), (k, g.n, s, t, reason)
+        assert np.array_equal(g.trace(), c.trace()), (k, g.n)
+        _state_equal(g, c)
+        ran.append(t)
+    # the stops are spread out: some nodes stop early, some run to the end
+    assert min(ran) <= 4 and max(ran) == iters and len(set(ran)) >= 8
+    assert st["iterations"] == sum(ran)
+    assert st["compactions"] >= 1
+    for g in gpu:
+        g.close()
+
+
 def test_batch_window_rule_stops_nodes():
     F, D, Bm = I.dense_instance(11, 70).arrays()
     g = B.DualAscent(F, D, Bm)
@@ -235,7 +314,7 @@ def test_batched_lane_counts_are_tuned(tmp_path, monkeypatch):
     for k, (lanes, cols, us) in tuned.items():
         m = int(k.split("/m")[1].split("/")[0])
         assert cols == 1 and us > 0.0
-        assert (lanes == -1 and m <= 32) or (lanes in (8, 16, 32, 64) and lanes >= m)
+        assert (lanes in (-1, -2) and m <= 32) or (lanes in (8, 16, 32, 64) and lanes >= m)
 
 
 @pytest.mark.parametrize("inst", [I.grid_n8(), I.grid_instance(9, 3, 3, 0.4, 1, 10, 2)], ids=lambda x: x.name)
