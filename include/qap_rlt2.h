@@ -114,7 +114,10 @@ typedef struct qap_params {
                               its old slack minus its new one.  FULL, not with
                               annealing; import, multiplier setting, warm starts,
                               folds, batched and B&B ascent refuse S1/S2 handles */
-    qap_alloc_fn alloc;    /* optional device allocator */
+    qap_alloc_fn alloc;    /* optional device allocator of the handle's arena
+                              and bound trace (the branch-and-bound search
+                              gives its node handles one that reuses the
+                              arenas of finished nodes) */
     qap_free_fn free_fn;
     void *alloc_ctx;
 } qap_params;
@@ -444,8 +447,8 @@ const char *qap_last_error(qap_handle h);
 int qap_track(qap_handle h, int on);
 
 /* Device allocator for this handle's later allocations: tracking arrays
- * and the temporary buffers of the learned calls (the arena keeps the
- * allocator of qap_params it was created with).  alloc NULL selects
+ * and the temporary buffers of the learned calls (the arena and the bound
+ * trace keep the allocator of qap_params the handle was created with).  alloc NULL selects
  * hipMalloc/hipFree; a non-NULL alloc needs free_fn.
  * Errors: QAP_EINVAL, QAP_ESTATE (tracking arrays live). */
 int qap_set_allocator(qap_handle h, qap_alloc_fn alloc, qap_free_fn free_fn, void *ctx);

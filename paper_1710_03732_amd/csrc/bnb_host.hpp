@@ -5,10 +5,60 @@
 #include <algorithm>
 #include <memory>
 #include <mutex>
+#include <unordered_map>
 
 #include "batch.hpp"
 
 namespace {
+
+// Device arenas of a search's node handles: an arena freed by a finished node
+// is kept by its size and handed to a later node of the same size (all nodes
+// of one size need the same bytes), so a batch of nodes does not hipMalloc
+// and hipFree each arena.  At most kCap bytes are kept; the rest is freed
+// at once, and everything kept is freed when the search ends.
+struct NodeArenaPool {
+    static constexpr size_t kCap = (size_t)32 << 30;
+    std::unordered_map<size_t, std::vector<void *>> kept;
+    std::unordered_map<void *, size_t> size_of;
+    size_t kept_bytes = 0;
+
+    static void *alloc(size_t bytes, void *ctx)
+    {
+        NodeArenaPool &P = *(NodeArenaPool *)ctx;
+        auto it = P.kept.find(bytes);
+        if (it != P.kept.end() && !it->second.empty()) {
+            void *p = it->second.back();
+            it->second.pop_back();
+            P.kept_bytes -= bytes;
+            return p;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        P.size_of[p] = bytes;
+        return p;
+    }
+    static void release(void *p, void *ctx)
+    {
+        NodeArenaPool &P = *(NodeArenaPool *)ctx;
+        const auto it = P.size_of.find(p);
+        if (it == P.size_of.end()) return;
+        if (P.kept_bytes + it->second > kCap) {
+            (void)hipFree(p);
+            P.size_of.erase(it);
+            return;
+        }
+        P.kept[it->second].push_back(p);
+        P.kept_bytes += it->second;
+    }
+    NodeArenaPool() = default;
+    NodeArenaPool(const NodeArenaPool &) = delete;
+    NodeArenaPool &operator=(const NodeArenaPool &) = delete;
+    ~NodeArenaPool()
+    {
+        for (auto &kv : kept)
+            for (void *p : kv.second) (void)hipFree(p);
+    }
+};
 
 bool fathomed_host(double lb, double ub, bool integer_data)
 {
@@ -662,6 +712,16 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
     std::vector<int> best(n, -1);
     long long nodes_done = 0, da_iters = 0, batches = 0, enumerated = 0;
     double node_bytes = 0.0;
+    // node handles take their arenas from the pool unless h has an allocator
+    // of its own (children inherit the parameters of their parent); declared
+    // before every handle of the search, so it outlives them
+    NodeArenaPool pool;
+    qap_params cprm = h->prm;
+    if (!cprm.alloc) {
+        cprm.alloc = NodeArenaPool::alloc;
+        cprm.free_fn = NodeArenaPool::release;
+        cprm.alloc_ctx = &pool;
+    }
 
     struct Node {
         std::shared_ptr<qap_ctx> parent;  // materialised parent state (shared by siblings)
@@ -725,14 +785,14 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
         for (auto &nd : batch) {
             qap_ctx *c = nullptr;
             if (nd.l < 0) {
-                rc = create_ctx(n, h->hF.data(), h->hD.data(), h->hB.data(), h->prm, 0.0, h->stream, true, &c);
+                rc = create_ctx(n, h->hF.data(), h->hD.data(), h->hB.data(), cprm, 0.0, h->stream, true, &c);
                 if (rc != QAP_OK) h->err = g_init_error;
             } else if (!nd.parent) {
                 // past the depth cap: the restricted QAP of the node, from scratch
                 std::vector<double> Fc, Dc, Bc;
                 double off = 0.0;
                 restricted_qap(h, nd.fac, nd.loc, nd.fixed, Fc, Dc, Bc, off);
-                rc = create_ctx((int)nd.fac.size(), Fc.data(), Dc.data(), Bc.data(), h->prm, off, h->stream, true,
+                rc = create_ctx((int)nd.fac.size(), Fc.data(), Dc.data(), Bc.data(), cprm, off, h->stream, true,
                                 &c);
                 if (rc != QAP_OK)
                     h->err = g_init_error;

@@ -66,13 +66,32 @@ struct qap_ctx {
     hipGraphExec_t graph = nullptr;  // one full iteration (t >= 1)
     // multiplier tracking (Vz entries like Z, T entries like Yc), or null
     double *Vt = nullptr, *Ut = nullptr;
-    // allocator the arena came from (prm.alloc may change later)
+    // allocator the arena and the bound trace come from (prm.alloc may
+    // change later)
     qap_alloc_fn arena_alloc = nullptr;
     qap_free_fn arena_free = nullptr;
     void *arena_ctx = nullptr;
 };
 
 namespace {
+
+// Device memory from the handle's arena allocator (hipMalloc without one),
+// and back: a caller's allocator without a free function keeps what it gave.
+void *arena_mem(qap_ctx *h, size_t bytes)
+{
+    if (h->arena_alloc) return h->arena_alloc(bytes, h->arena_ctx);
+    void *p = nullptr;
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+
+void arena_mem_free(qap_ctx *h, void *p)
+{
+    if (!p) return;
+    if (!h->arena_alloc)
+        (void)hipFree(p);
+    else if (h->arena_free)
+        h->arena_free(p, h->arena_ctx);
+}
 
 int fail(qap_ctx *h, int code, const std::string &msg)
 {
@@ -355,13 +374,16 @@ int ensure_trace(qap_ctx *h, int need)
 {
     if (need <= h->trace_cap) return QAP_OK;
     int cap = std::max(need, 2 * h->trace_cap);
-    double *nt = nullptr;
-    HIPCHK(h, hipMalloc(&nt, sizeof(double) * cap));
+    double *nt = (double *)arena_mem(h, sizeof(double) * cap);
+    if (!nt) return fail(h, QAP_ENOMEM, "trace allocation failed");
     if (h->trace) {
-        HIPCHK(h, hipMemcpyAsync(nt, h->trace, sizeof(double) * h->trace_cap, hipMemcpyDeviceToDevice,
-                                 h->stream));
-        HIPCHK(h, hipStreamSynchronize(h->stream));
-        HIPCHK(h, hipFree(h->trace));
+        hipError_t e = hipMemcpyAsync(nt, h->trace, sizeof(double) * h->trace_cap, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) {
+            arena_mem_free(h, nt);
+            return fail(h, QAP_EDEVICE, std::string("trace copy: ") + hipGetErrorString(e));
+        }
+        arena_mem_free(h, h->trace);
     }
     h->trace = nt;
     h->trace_cap = cap;
@@ -474,9 +496,11 @@ int create_ctx(int n, const double *F, const double *D, const double *B, const q
 
     const int trace_cap = 1024;
     Sizes sz = sizes_for(n, trace_cap);
+    // (a caller's allocator may serve the arena from memory it already holds)
     size_t freeb = 0, totalb = 0;
-    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) return fail(nullptr, QAP_EDEVICE, "hipMemGetInfo failed");
-    if (sz.total + sz.trace > freeb) {
+    if (!prm.alloc && hipMemGetInfo(&freeb, &totalb) != hipSuccess)
+        return fail(nullptr, QAP_EDEVICE, "hipMemGetInfo failed");
+    if (!prm.alloc && sz.total + sz.trace > freeb) {
         char buf[160];
         std::snprintf(buf, sizeof buf, "arena of %zu bytes exceeds free device memory (%zu)", sz.total + sz.trace,
                       freeb);
@@ -555,7 +579,8 @@ int create_ctx(int n, const double *F, const double *D, const double *B, const q
     h->triples = (int *)take(sz.tri);
     h->S = (DevScalars *)take(round_up(sizeof(DevScalars)));
     h->bins = (unsigned long long *)take(round_up(sizeof(unsigned long long) * kStepBins));
-    if (hipMalloc(&h->trace, sizeof(double) * trace_cap) != hipSuccess) {
+    h->trace = (double *)arena_mem(h, sizeof(double) * trace_cap);
+    if (!h->trace) {
         g_init_error = "trace allocation failed";
         return cleanup(QAP_ENOMEM);
     }
@@ -666,7 +691,7 @@ int qap_destroy(qap_handle h)
         else if (!h->arena_alloc)
             (void)hipFree(h->arena);
     }
-    if (h->trace) (void)hipFree(h->trace);
+    arena_mem_free(h, h->trace);
     for (double *a : {h->Vt, h->Ut}) {
         if (!a) continue;
         if (h->prm.alloc && h->prm.free_fn)
