@@ -394,8 +394,9 @@ def test_zero_flows_reduce_to_a_lap_on_b():
 
 
 def test_arena_from_a_caller_allocator():
-    """qap_params.alloc: the whole arena comes from torch's caching allocator;
-    the run is bitwise the default one, and destroy hands the arena back."""
+    """qap_params.alloc: the whole arena and the bound trace (together the
+    qap_workspace_bytes) come from torch's caching allocator; the run is
+    bitwise the default one, and destroy hands both back."""
     import torch
 
     F, D, Bm = I.grid_n8().arrays()
@@ -409,9 +410,9 @@ def test_arena_from_a_caller_allocator():
     b = B.DualAscent(F, D, Bm)
     b.run(6)
     assert np.array_equal(a.trace(), b.trace())
-    assert got and got[0] == B.workspace_bytes(8) - 8 * 1024
+    assert got == [B.workspace_bytes(8) - 8 * 1024, 8 * 1024]
     a.close()
-    assert len(freed) == 1
+    assert len(freed) == 2
 
 
 def test_autotuned_mapping_is_bitwise_the_requested_one(tmp_path, monkeypatch):
