@@ -11,52 +11,49 @@
 
 namespace {
 
-// Device arenas of a search's node handles: an arena freed by a finished node
-// is kept by its size and handed to a later node of the same size (all nodes
-// of one size need the same bytes), so a batch of nodes does not hipMalloc
-// and hipFree each arena.  At most kCap bytes are kept; the rest is freed
-// at once, and everything kept is freed when the search ends.
+// Device memory of a search's node handles (arenas and bound traces).  A
+// hipFree costs a few hundred microseconds, so blocks come from slabs of up
+// to 1 GiB that hold several blocks of one size (all nodes of one size need
+// the same bytes); a block freed by a finished node goes back to its size's
+// free list for a later node, and the slabs are freed when the search ends.
 struct NodeArenaPool {
-    static constexpr size_t kCap = (size_t)32 << 30;
-    std::unordered_map<size_t, std::vector<void *>> kept;
-    std::unordered_map<void *, size_t> size_of;
-    size_t kept_bytes = 0;
+    static constexpr size_t kSlab = (size_t)1 << 30;
+    static constexpr size_t kMaxPerSlab = 64;
+    std::unordered_map<size_t, std::vector<void *>> free_blocks;  // by block size
+    std::unordered_map<void *, size_t> size_of;                  // block -> its size
+    std::vector<void *> slabs;
 
     static void *alloc(size_t bytes, void *ctx)
     {
         NodeArenaPool &P = *(NodeArenaPool *)ctx;
-        auto it = P.kept.find(bytes);
-        if (it != P.kept.end() && !it->second.empty()) {
-            void *p = it->second.back();
-            it->second.pop_back();
-            P.kept_bytes -= bytes;
-            return p;
+        const size_t bsz = round_up(bytes);
+        std::vector<void *> &fl = P.free_blocks[bsz];
+        if (fl.empty()) {
+            const size_t k = std::max<size_t>(1, std::min(kMaxPerSlab, kSlab / bsz));
+            char *slab = nullptr;
+            if (hipMalloc((void **)&slab, k * bsz) != hipSuccess) return nullptr;
+            P.slabs.push_back(slab);
+            for (size_t i = k; i-- > 0;) {
+                fl.push_back(slab + i * bsz);
+                P.size_of[slab + i * bsz] = bsz;
+            }
         }
-        void *p = nullptr;
-        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
-        P.size_of[p] = bytes;
+        void *p = fl.back();
+        fl.pop_back();
         return p;
     }
     static void release(void *p, void *ctx)
     {
         NodeArenaPool &P = *(NodeArenaPool *)ctx;
         const auto it = P.size_of.find(p);
-        if (it == P.size_of.end()) return;
-        if (P.kept_bytes + it->second > kCap) {
-            (void)hipFree(p);
-            P.size_of.erase(it);
-            return;
-        }
-        P.kept[it->second].push_back(p);
-        P.kept_bytes += it->second;
+        if (it != P.size_of.end()) P.free_blocks[it->second].push_back(p);
     }
     NodeArenaPool() = default;
     NodeArenaPool(const NodeArenaPool &) = delete;
     NodeArenaPool &operator=(const NodeArenaPool &) = delete;
     ~NodeArenaPool()
     {
-        for (auto &kv : kept)
-            for (void *p : kv.second) (void)hipFree(p);
+        for (void *s : slabs) (void)hipFree(s);
     }
 };
 
