@@ -198,18 +198,20 @@ __global__ __launch_bounds__(256) void k_bsweep(const BNode *__restrict__ nodes,
         }
     }
     __syncthreads();
-    // every new value first, each in registers of its own (each slot's li is
-    // inside the cube, so the reads for slots outside the instance stay in
-    // LDS and are discarded), then the stores.  Computed inside each store's
-    // branch the values would share registers, and each store would wait
-    // for the one before it to complete before its register could be reused.
+    // every new value first (each slot's li is inside the cube, so the reads
+    // for slots outside the instance stay in LDS and are discarded), then the
+    // stores.  A new value needs pz, whose load was conditional: computed
+    // inside its store's branch, it could only be waited for by waiting for
+    // every outstanding memory operation, the earlier stores included, which
+    // serialised the twelve stores.  The empty asm keeps each value out of
+    // its store's branch.
     double nz[6][PER];
 #pragma unroll
     for (int e = 0; e < 6; ++e)
 #pragma unroll
         for (int w = 0; w < PER; ++w) {
             nz[e][w] = N.okz * pz[e][w] + gs[e * SB_CUBE + li[e][w]];
-            asm volatile("" : "+v"(nz[e][w]));  // (keeps it out of the branch)
+            asm volatile("" : "+v"(nz[e][w]));
         }
 #pragma unroll
     for (int e = 0; e < 6; ++e)
