@@ -219,25 +219,31 @@ __global__ __launch_bounds__(Cube<CB>::NT) void k_sweep(double *__restrict__ Z, 
     // pi_y of the block's tiles and pi_x of its (facility, location) pairs,
     // read once per block: member e's tile is fixed by its first two cube
     // coordinates (a1 along axis X1[e], a2 along X2[e]), its x parent by the
-    // first.  Entries outside the instance hold 0 and are never used.
+    // first.  Entries outside the instance hold 0 and are never used.  They
+    // are loaded into registers here and written to LDS after the z loads
+    // below have been issued, so the block waits for all of them at once.
     __shared__ double pys[6 * CB * CB];
     __shared__ double pxs[3 * CB];
+    constexpr int YREP = POOL ? 0 : (6 * CB * CB + NT - 1) / NT;
+    double yv[YREP > 0 ? YREP : 1];
+    double xv = 0.0;
 #pragma unroll
-    for (int rep = 0; rep < (POOL ? 0 : (6 * CB * CB + NT - 1) / NT); ++rep) {
+    for (int rep = 0; rep < YREP; ++rep) {
         const int a = threadIdx.x + NT * rep;
+        yv[rep] = 0.0;
         if (a < 6 * CB * CB) {
             const int e = a / (CB * CB), a1 = (a / CB) % CB, a2 = a % CB;
             const int x1 = e >> 1, x2 = (0x102021 >> (4 * e)) & 0xf;  // X1[e], X2[e]
             const int f1 = x1 == 0 ? fi : (x1 == 1 ? fj : fk), f2 = x2 == 0 ? fi : (x2 == 1 ? fj : fk);
             const int l1 = (x1 == 0 ? base[0] : (x1 == 1 ? base[1] : base[2])) + a1;
             const int l2 = (x2 == 0 ? base[0] : (x2 == 1 ? base[1] : base[2])) + a2;
-            pys[a] = (l1 < n && l2 < n && l1 != l2) ? Py[tile_of(n, f1, l1, f2, l2)] : 0.0;
+            yv[rep] = (l1 < n && l2 < n && l1 != l2) ? Py[tile_of(n, f1, l1, f2, l2)] : 0.0;
         }
     }
     if (!POOL && threadIdx.x < 3 * CB) {
         const int x = threadIdx.x / CB, l = (x == 0 ? base[0] : (x == 1 ? base[1] : base[2])) + threadIdx.x % CB;
         const int f = x == 0 ? fi : (x == 1 ? fj : fk);
-        pxs[threadIdx.x] = l < n ? Px[f * n + l] : 0.0;
+        xv = l < n ? Px[f * n + l] : 0.0;
     }
     constexpr int PER = 1;  // one orbit per thread
     long long za[6][PER];
@@ -278,6 +284,12 @@ __global__ __launch_bounds__(Cube<CB>::NT) void k_sweep(double *__restrict__ Z, 
             pz[e][w] = Z[za[e][w]];
         }
     }
+#pragma unroll
+    for (int rep = 0; rep < YREP; ++rep) {
+        const int a = threadIdx.x + NT * rep;
+        if (a < 6 * CB * CB) pys[a] = yv[rep];
+    }
+    if (!POOL && threadIdx.x < 3 * CB) pxs[threadIdx.x] = xv;
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
         if (HALF && (e == 2 || e == 4 || e == 5)) continue;
@@ -343,7 +355,32 @@ __global__ __launch_bounds__(Cube<CB>::NT) void k_sweep(double *__restrict__ Z, 
         }
     }
     __syncthreads();
-    // store phase: new_e = okz*pi_z(e) + phi*sum, back along the same runs
+    // store phase: new_e = okz*pi_z(e) + phi*sum, back along the same runs.
+    // Without tracking, pooling or the slow variant every new value is formed
+    // before the first store (the empty asm keeps each out of its store's
+    // branch).  Formed inside the branches, each value's wait for its z load
+    // counted the stores issued before it, and the later stores waited for
+    // the earlier ones to complete.
+    if constexpr (!TRACK && !SLOW && !POOL) {
+        double nz[6][PER];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            if (HALF && (e == 2 || e == 4 || e == 5)) continue;
+#pragma unroll
+            for (int w = 0; w < PER; ++w) {
+                nz[e][w] = K.okz * pz[e][w] + gs[e * C::SIZE + li[e][w]];
+                asm volatile("" : "+v"(nz[e][w]));
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            if (HALF && (e == 2 || e == 4 || e == 5)) continue;
+#pragma unroll
+            for (int w = 0; w < PER; ++w)
+                if (ok[e][w]) Z[za[e][w]] = nz[e][w];
+        }
+        return;
+    }
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
         if (HALF && (e == 2 || e == 4 || e == 5)) continue;
