@@ -250,6 +250,7 @@ __global__ __launch_bounds__(Cube<CB>::NT) void k_sweep(double *__restrict__ Z, 
     int li[6][PER];
     bool ok[6][PER];
     double pz[6][PER];
+    double pv[6][PER];  // TRACK: the entries' multipliers, read with pi_z
     // this thread's member-major elements (runs along each member's own last
     // location axis); pi_z goes to the cube for the orbit phase.  Thread
     // tid < CB^3 takes cube coordinates (a1, a2, a3) = (tid / CB^2,
@@ -282,6 +283,7 @@ __global__ __launch_bounds__(Cube<CB>::NT) void k_sweep(double *__restrict__ Z, 
             za[e][w] = v ? zrow + (long long)(__umul24((unsigned)l2p, (unsigned)mm) + col) : 0;
             li[e][w] = C::idx(loc[0] - base[0], loc[1] - base[1], loc[2] - base[2]);
             pz[e][w] = Z[za[e][w]];
+            if constexpr (TRACK) pv[e][w] = Vt[za[e][w]];
         }
     }
 #pragma unroll
@@ -355,55 +357,50 @@ __global__ __launch_bounds__(Cube<CB>::NT) void k_sweep(double *__restrict__ Z, 
         }
     }
     __syncthreads();
-    // store phase: new_e = okz*pi_z(e) + phi*sum, back along the same runs.
-    // Without tracking, pooling or the slow variant every new value is formed
-    // before the first store (the empty asm keeps each out of its store's
-    // branch).  Formed inside the branches, each value's wait for its z load
-    // counted the stores issued before it, and the later stores waited for
-    // the earlier ones to complete.
-    if constexpr (!TRACK && !SLOW && !POOL) {
-        double nz[6][PER];
+    // store phase, back along the same runs.  Every output is formed first,
+    // each in registers of its own (the empty asm keeps it out of its store's
+    // branch), then the stores: formed inside the branches, each value's wait
+    // for its loads also counted the stores issued before it, so the later
+    // stores waited for the earlier ones to complete.
+    //   plain:  new_e = okz*pi_z(e) + phi*sum
+    //   POOL:   the pooled value, stored only where its bits changed (most
+    //           orbits have no zero slack among the six and stay as they are)
+    //   TRACK:  v_e += g_e - phi*sum; with POOL, v_e += old slack - new slack
+    //   SLOW:   z_e = -v_e (the S-form cost of the tracked multiplier)
+    double zo[6][PER], vo[6][PER];
+    bool so[6][PER];
 #pragma unroll
-        for (int e = 0; e < 6; ++e) {
-            if (HALF && (e == 2 || e == 4 || e == 5)) continue;
+    for (int e = 0; e < 6; ++e) {
+        if (HALF && (e == 2 || e == 4 || e == 5)) continue;
 #pragma unroll
-            for (int w = 0; w < PER; ++w) {
-                nz[e][w] = K.okz * pz[e][w] + gs[e * C::SIZE + li[e][w]];
-                asm volatile("" : "+v"(nz[e][w]));
+        for (int w = 0; w < PER; ++w) {
+            const double share = gs[e * C::SIZE + li[e][w]];
+            so[e][w] = ok[e][w] && !(POOL && __double_as_longlong(share) == __double_as_longlong(pz[e][w]));
+            double v = 0.0;
+            if constexpr (TRACK && POOL) {
+                v = pv[e][w] + (pz[e][w] - share);
+            } else if constexpr (TRACK) {
+                const int u = threadIdx.x + NT * w;
+                const int a2 = (u / CB) % CB, a1 = u / (CB * CB);
+                const double y = pys[(e * CB + a1) * CB + a2];
+                const double x = pxs[X1[e] * CB + a1];
+                const double g = (K.kz * pz[e][w] + K.ky2 * y) + K.kx3 * x;
+                v = pv[e][w] + (g - share);
             }
+            zo[e][w] = SLOW ? -v : (POOL ? share : K.okz * pz[e][w] + share);
+            vo[e][w] = v;
+            asm volatile("" : "+v"(zo[e][w]));
+            if constexpr (TRACK) asm volatile("" : "+v"(vo[e][w]));
         }
-#pragma unroll
-        for (int e = 0; e < 6; ++e) {
-            if (HALF && (e == 2 || e == 4 || e == 5)) continue;
-#pragma unroll
-            for (int w = 0; w < PER; ++w)
-                if (ok[e][w]) Z[za[e][w]] = nz[e][w];
-        }
-        return;
     }
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
         if (HALF && (e == 2 || e == 4 || e == 5)) continue;
 #pragma unroll
         for (int w = 0; w < PER; ++w)
-            if (ok[e][w]) {
-                const double share = gs[e * C::SIZE + li[e][w]];
-                // POOL leaves most orbits as they are (no zero slack among
-                // the six): store only entries whose bits changed
-                if (POOL && __double_as_longlong(share) == __double_as_longlong(pz[e][w])) continue;
-                if (!SLOW) Z[za[e][w]] = POOL ? share : K.okz * pz[e][w] + share;
-                if (TRACK && POOL) {
-                    Vt[za[e][w]] = Vt[za[e][w]] + (pz[e][w] - share);
-                } else if (TRACK) {
-                    const int u = threadIdx.x + NT * w;
-                    const int a2 = (u / CB) % CB, a1 = u / (CB * CB);
-                    const double y = pys[(e * CB + a1) * CB + a2];
-                    const double x = pxs[X1[e] * CB + a1];
-                    const double g = (K.kz * pz[e][w] + K.ky2 * y) + K.kx3 * x;
-                    const double vnew = Vt[za[e][w]] + (g - share);
-                    Vt[za[e][w]] = vnew;
-                    if (SLOW) Z[za[e][w]] = -vnew;
-                }
+            if (so[e][w]) {
+                Z[za[e][w]] = zo[e][w];
+                if constexpr (TRACK) Vt[za[e][w]] = vo[e][w];
             }
     }
 }
