@@ -116,25 +116,30 @@ __global__ __launch_bounds__(256) void k_bsweep(const BNode *__restrict__ nodes,
     const int X3[6] = {2, 1, 2, 0, 1, 0};
     constexpr int PER = (SB * SB * SB) / 256;
     // pi_y of the block's tiles and pi_x of its (facility, location) pairs,
-    // read once per block into LDS (as k_sweep)
+    // read once per block into registers and written to LDS after the z
+    // loads have been issued (as k_sweep)
     __shared__ double pys[6 * SB * SB];
     __shared__ double pxs[3 * SB];
+    constexpr int YREP = (6 * SB * SB + 255) / 256;
+    double yv[YREP];
+    double xv = 0.0;
 #pragma unroll
-    for (int rep = 0; rep < (6 * SB * SB + 255) / 256; ++rep) {
+    for (int rep = 0; rep < YREP; ++rep) {
         const int a = threadIdx.x + 256 * rep;
+        yv[rep] = 0.0;
         if (a < 6 * SB * SB) {
             const int e = a / (SB * SB), a1 = (a / SB) % SB, a2 = a % SB;
             const int x1 = e >> 1, x2 = (0x102021 >> (4 * e)) & 0xf;  // X1[e], X2[e]
             const int f1 = x1 == 0 ? fi : (x1 == 1 ? fj : fk), f2 = x2 == 0 ? fi : (x2 == 1 ? fj : fk);
             const int l1 = (x1 == 0 ? base[0] : (x1 == 1 ? base[1] : base[2])) + a1;
             const int l2 = (x2 == 0 ? base[0] : (x2 == 1 ? base[1] : base[2])) + a2;
-            pys[a] = (l1 < n && l2 < n && l1 != l2) ? Py[tile_of(n, f1, l1, f2, l2)] : 0.0;
+            yv[rep] = (l1 < n && l2 < n && l1 != l2) ? Py[tile_of(n, f1, l1, f2, l2)] : 0.0;
         }
     }
     if (threadIdx.x < 3 * SB) {
         const int x = threadIdx.x / SB, l = (x == 0 ? base[0] : (x == 1 ? base[1] : base[2])) + threadIdx.x % SB;
         const int f = x == 0 ? fi : (x == 1 ? fj : fk);
-        pxs[threadIdx.x] = l < n ? Px[f * n + l] : 0.0;
+        xv = l < n ? Px[f * n + l] : 0.0;
     }
     long long za[6][PER];
     int li[6][PER];
@@ -168,6 +173,12 @@ __global__ __launch_bounds__(256) void k_bsweep(const BNode *__restrict__ nodes,
         }
     }
     // (every load above is issued before the first LDS write)
+#pragma unroll
+    for (int rep = 0; rep < YREP; ++rep) {
+        const int a = threadIdx.x + 256 * rep;
+        if (a < 6 * SB * SB) pys[a] = yv[rep];
+    }
+    if (threadIdx.x < 3 * SB) pxs[threadIdx.x] = xv;
 #pragma unroll
     for (int e = 0; e < 6; ++e)
 #pragma unroll
