@@ -374,8 +374,9 @@ int qap_batch_dual_ascent(qap_handle *hs, int count, const qap_batch_params *bp,
 /* qap_batch_dual_ascent for callers that cannot allocate device memory: code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc.  Same arguments and the same results, bitwise; it allocates
- * nothing.  Its node table, prefix tables, stop counter and stop flags live in a
- * file-scope device array of QAP_BATCH_STATIC_BYTES per GPU (held by each GPU
+ * nothing.  Its node table, prefix tables, stop counter, stop flags and a
+ * copy of the handles' scalar blocks live in a file-scope device array of
+ * QAP_BATCH_STATIC_BYTES per GPU (held by each GPU
  * the library runs on until the process ends), set up on the first call on
  * a device; the iterations are launched one by one (no graph is captured or
  * instantiated), and the batched Z-LAP mapping is the one the autotuner

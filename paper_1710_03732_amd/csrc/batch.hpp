@@ -434,6 +434,14 @@ __global__ __launch_bounds__(256) void k_bylap(const BNode *__restrict__ nodes, 
     }
 }
 
+// Scalar blocks of several handles gathered into one array, for one copy to
+// the host.
+__global__ void k_bgather_scalars(DevScalars *const *__restrict__ src, int count, DevScalars *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = *src[i];
+}
+
 // Each node's stop flag, for the host to drop stopped nodes from the tables.
 __global__ void k_bstopped(const BNode *__restrict__ nodes, int nnodes, int *__restrict__ out)
 {

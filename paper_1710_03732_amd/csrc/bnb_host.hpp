@@ -230,23 +230,16 @@ int qap_location_automorphisms(int n, const double *D, const double *B, int cap,
     return QAP_OK;
 }
 
+}  // extern "C"
 
-int qap_fold_child(qap_handle h, int l, int s, qap_handle *child)
+namespace {
+
+// The child fold once the parent's bound plus pi_x[l][s] (the child's
+// starting bound) is known on the host; arguments already checked.  Every
+// step is queued on the parent's stream, which the child shares.
+int fold_core(qap_ctx *h, int l, int s, double child_lb, qap_ctx **child)
 {
-    if (!h || !child) return QAP_EINVAL;
-    if (h->half) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound children are FULL-scheme only");
-    if (h->prm.two_phase) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound children are F1 only");
-    if (h->sa_on) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound children run without annealing");
-    if (h->prm.slow) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound children are F1 only");
     const int n = h->n, n1 = n - 1;
-    if (n1 < 3) return fail(h, QAP_EUNSUPPORTED, "a child needs n >= 4");
-    if (l < 0 || l >= n || s < 0 || s >= n) return fail(h, QAP_EINVAL, "facility/location out of range");
-    DevScalars ps{};
-    HIPCHK(h, hipMemcpyAsync(&ps, h->S, sizeof(ps), hipMemcpyDeviceToHost, h->stream));
-    double px = 0.0;
-    HIPCHK(h, hipMemcpyAsync(&px, h->Px + (size_t)l * n + s, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    if (ps.t < 1) return fail(h, QAP_ESTATE, "the parent has run no iteration yet");
     // the child's own QAP: F, D restricted, fixed pair folded into B, constant
     const double *F = h->hF.data(), *D = h->hD.data(), *B = h->hB.data();
     std::vector<double> Fc((size_t)n1 * n1), Dc((size_t)n1 * n1), Bc((size_t)n1 * n1);
@@ -277,7 +270,7 @@ int qap_fold_child(qap_handle h, int l, int s, qap_handle *child)
         qap_destroy(c);
         return fail(h, QAP_EDEVICE, std::string("fold: ") + hipGetErrorString(e));
     }
-    rc = upload_scalars(c, ps.lb + px);
+    rc = upload_scalars(c, child_lb, false);
     if (rc != QAP_OK) {
         h->err = c->err;
         qap_destroy(c);
@@ -285,6 +278,29 @@ int qap_fold_child(qap_handle h, int l, int s, qap_handle *child)
     }
     *child = c;
     return QAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qap_fold_child(qap_handle h, int l, int s, qap_handle *child)
+{
+    if (!h || !child) return QAP_EINVAL;
+    if (h->half) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound children are FULL-scheme only");
+    if (h->prm.two_phase) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound children are F1 only");
+    if (h->sa_on) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound children run without annealing");
+    if (h->prm.slow) return fail(h, QAP_EUNSUPPORTED, "branch-and-bound children are F1 only");
+    const int n = h->n;
+    if (n - 1 < 3) return fail(h, QAP_EUNSUPPORTED, "a child needs n >= 4");
+    if (l < 0 || l >= n || s < 0 || s >= n) return fail(h, QAP_EINVAL, "facility/location out of range");
+    DevScalars ps{};
+    HIPCHK(h, hipMemcpyAsync(&ps, h->S, sizeof(ps), hipMemcpyDeviceToHost, h->stream));
+    double px = 0.0;
+    HIPCHK(h, hipMemcpyAsync(&px, h->Px + (size_t)l * n + s, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (ps.t < 1) return fail(h, QAP_ESTATE, "the parent has run no iteration yet");
+    return fold_core(h, l, s, ps.lb + px, child);
 }
 
 }  // extern "C"
@@ -300,7 +316,7 @@ namespace {
 // gives the same results), and a handle whose trace has no room for the
 // iterations is refused instead of grown.
 int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_stats *st, bool no_alloc,
-               char *ws, size_t ws_bytes)
+               char *ws, size_t ws_bytes, std::vector<DevScalars> *scal_out = nullptr)
 {
     if (count < 0 || (count > 0 && (!hs || !bp))) return fail(nullptr, QAP_EINVAL, "bad batch arguments");
     if (count == 0) return QAP_OK;
@@ -324,7 +340,45 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
     }
     auto t0 = std::chrono::steady_clock::now();
     HIPCHK(h0, hipSetDevice(h0->prm.device));
-    for (int b = 0; b < count; ++b) HIPCHK(h0, hipStreamSynchronize(hs[b]->stream));
+    {  // every handle's queued work first (each distinct stream once)
+        std::vector<hipStream_t> streams;
+        for (int b = 0; b < count; ++b)
+            if (std::find(streams.begin(), streams.end(), hs[b]->stream) == streams.end())
+                streams.push_back(hs[b]->stream);
+        for (hipStream_t sm : streams) HIPCHK(h0, hipStreamSynchronize(sm));
+    }
+    // device copies (one allocation): node table, prefix tables, stop
+    // counter, per-node stop flags, the handles' scalar-block addresses and
+    // the gathered scalar blocks
+    const size_t nb_bytes = round_up(sizeof(BNode) * count), pf_bytes = round_up(sizeof(long long) * (count + 1));
+    const size_t fl_bytes = round_up(sizeof(int) * count), sp_bytes = round_up(sizeof(DevScalars *) * count);
+    const size_t need = nb_bytes + 4 * pf_bytes + 256 + fl_bytes + sp_bytes + round_up(sizeof(DevScalars) * count);
+    void *dmem = nullptr;
+    if (no_alloc) {
+        if (need > ws_bytes) return fail(h0, QAP_EINVAL, "batch tables exceed the static workspace");
+        dmem = ws;
+    } else {
+        HIPCHK(h0, hipMalloc(&dmem, need));
+    }
+    std::unique_ptr<void, void (*)(void *)> guard(no_alloc ? nullptr : dmem, [](void *p) {
+        if (p) (void)hipFree(p);
+    });
+    char *dp = (char *)dmem;
+    DevScalars **dsptr = (DevScalars **)(dp + nb_bytes + 4 * pf_bytes + 256 + fl_bytes);
+    DevScalars *dscal = (DevScalars *)(dp + nb_bytes + 4 * pf_bytes + 256 + fl_bytes + sp_bytes);
+    // every handle's scalar block in one copy (gathered on the device)
+    std::vector<DevScalars *> sptrs(count);
+    for (int b = 0; b < count; ++b) sptrs[b] = hs[b]->S;
+    std::vector<DevScalars> scal(count);
+    auto gather_scalars = [&]() -> hipError_t {
+        hipLaunchKernelGGL(k_bgather_scalars, dim3((count + 255) / 256), dim3(256), 0, stream, dsptr, count, dscal);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(scal.data(), dscal, sizeof(DevScalars) * count, hipMemcpyDeviceToHost, stream);
+        return e == hipSuccess ? hipStreamSynchronize(stream) : e;
+    };
+    HIPCHK(h0, hipMemcpyAsync(dsptr, sptrs.data(), sizeof(DevScalars *) * count, hipMemcpyHostToDevice, stream));
+    HIPCHK(h0, gather_scalars());
     // node descriptors of every handle; the tables hold the nodes still
     // running (a stopped node's jobs would only read its flag and leave)
     std::vector<BNode> all(count);
@@ -333,8 +387,7 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
     int mz = 1, my = 1, stopped0 = 0;
     for (int b = 0; b < count; ++b) {
         qap_ctx *h = hs[b];
-        DevScalars s{};
-        HIPCHK(h0, hipMemcpy(&s, h->S, sizeof(s), hipMemcpyDeviceToHost));
+        const DevScalars &s = scal[b];
         stopped0 += s.stopped ? 1 : 0;
         if (no_alloc) {
             if (s.t + bp->iters + 1 > h->trace_cap)
@@ -386,21 +439,6 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
             my = std::max(my, h->n - 1);
         }
     }
-    // device copies (one allocation): node table, prefix tables, stop
-    // counter, per-node stop flags
-    const size_t nb_bytes = round_up(sizeof(BNode) * count), pf_bytes = round_up(sizeof(long long) * (count + 1));
-    const size_t need = nb_bytes + 4 * pf_bytes + 256 + round_up(sizeof(int) * count);
-    void *dmem = nullptr;
-    if (no_alloc) {
-        if (need > ws_bytes) return fail(h0, QAP_EINVAL, "batch tables exceed the static workspace");
-        dmem = ws;
-    } else {
-        HIPCHK(h0, hipMalloc(&dmem, need));
-    }
-    std::unique_ptr<void, void (*)(void *)> guard(no_alloc ? nullptr : dmem, [](void *p) {
-        if (p) (void)hipFree(p);
-    });
-    char *dp = (char *)dmem;
     BNode *dnodes = (BNode *)dp;
     long long *dzl = (long long *)(dp + nb_bytes), *dyl = (long long *)(dp + nb_bytes + pf_bytes);
     long long *dsw = (long long *)(dp + nb_bytes + 2 * pf_bytes), *dsc = (long long *)(dp + nb_bytes + 3 * pf_bytes);
@@ -574,12 +612,11 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
         if (!err.empty()) return fail(h0, QAP_EDEVICE, err);
         if (se != hipSuccess) return fail(h0, QAP_EDEVICE, std::string("batch sync: ") + hipGetErrorString(se));
     }
-    HIPCHK(h0, hipStreamSynchronize(stream));
+    HIPCHK(h0, gather_scalars());
     if (st) {
         std::memset(st, 0, sizeof(*st));
         for (int b = 0; b < count; ++b) {
-            DevScalars s{};
-            HIPCHK(h0, hipMemcpy(&s, hs[b]->S, sizeof(s), hipMemcpyDeviceToHost));
+            const DevScalars &s = scal[b];
             st->iterations += s.t;
             st->stopped += s.stopped ? 1 : 0;
             st->fathomed += s.reason == 1 ? 1 : 0;
@@ -588,11 +625,8 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
         st->compactions = compactions;
         st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
-    for (int b = 0; b < count; ++b) {
-        DevScalars s{};
-        HIPCHK(h0, hipMemcpy(&s, hs[b]->S, sizeof(s), hipMemcpyDeviceToHost));
-        hs[b]->t_host = s.t;
-    }
+    for (int b = 0; b < count; ++b) hs[b]->t_host = scal[b].t;
+    if (scal_out) scal_out->swap(scal);
     return QAP_OK;
 }
 
@@ -796,7 +830,9 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
                 else if ((rc = upload_scalars(c, off)) != QAP_OK)  // the bound counts the fixed part too
                     h->err = c->err;
             } else {
-                rc = qap_fold_child(nd.parent.get(), nd.l, nd.s, &c);
+                // the child's starting bound is the parent's bound plus
+                // pi_x[l][s], read after the parent's batch (lb_hint)
+                rc = fold_core(nd.parent.get(), nd.l, nd.s, nd.lb_hint, &c);
                 if (rc != QAP_OK) h->err = nd.parent->err;
             }
             if (rc != QAP_OK) break;
@@ -807,20 +843,17 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
         if (rc != QAP_OK) break;
         const int iters = (batch.size() == 1 && batch[0].depth == 0) ? P.root_iters : P.node_iters;
         qap_batch_params bp{iters, P.window, P.min_improve, UB};
-        rc = qap_batch_dual_ascent(hs.data(), (int)hs.size(), &bp, nullptr);
+        // (the nodes' scalar blocks come back with the batch, in one copy)
+        std::vector<DevScalars> sv;
+        rc = batch_core(hs.data(), (int)hs.size(), &bp, nullptr, false, nullptr, 0, &sv);
         if (rc != QAP_OK) {
             h->err = hs[0]->err;
             break;
         }
         ++batches;
         // incumbents first, then branching with the improved UB
-        std::vector<DevScalars> sv(hs.size());
         for (size_t b = 0; b < hs.size(); ++b) {
             qap_ctx *c = hs[b];
-            if (hipMemcpy(&sv[b], c->S, sizeof(DevScalars), hipMemcpyDeviceToHost) != hipSuccess) {
-                rc = fail(h, QAP_EDEVICE, "reading node state failed");
-                break;
-            }
             da_iters += sv[b].t;
             {
                 const double nn = c->n, T1 = nn * nn * (nn - 1) * (nn - 1), V1 = T1 * (nn - 2) * (nn - 2);
@@ -843,6 +876,10 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
             ++nodes_done;
             Node &nd = batch[b];
             if (fathomed_host(sv[b].lb, UB, integer_data)) continue;
+            if (sv[b].t < 1) {  // (every batch runs at least one iteration of a fresh node)
+                rc = fail(h, QAP_ESTATE, "a node to branch on has run no iteration");
+                break;
+            }
             const int nl = (int)nd.fac.size();
             const int f = order[nd.depth];
             int l = -1;

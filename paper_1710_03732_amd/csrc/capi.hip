@@ -62,6 +62,10 @@ struct qap_ctx {
     double zl_tune_us = -1.0; // its time over the tuner's synthetic tiles (< 0: rule-based)
     double offset = 0.0; // constant added to every permutation cost (B&B nodes)
     std::vector<double> hF, hD, hB;
+    // host sources of the asynchronous uploads at creation and reset, kept
+    // while the handle lives so no upload needs a stream synchronisation
+    std::vector<int> htri, hident;
+    DevScalars hscal{};
     std::string err;
     hipGraphExec_t graph = nullptr;  // one full iteration (t >= 1)
     // multiplier tracking (Vz entries like Z, T entries like Yc), or null
@@ -410,15 +414,13 @@ void derive_constants(qap_ctx *h)
     h->ophy = 1.0 - h->prm.phi_y;
 }
 
-int upload_scalars(qap_ctx *h, double lb);
+int upload_scalars(qap_ctx *h, double lb, bool sync = true);
 
+// Algorithm 1's initial state (F, D and B are on the device already).
 int upload_initial(qap_ctx *h)
 {
     const int n = h->n;
     const int nn = n * n;
-    HIPCHK(h, hipMemcpyAsync(h->F, h->hF.data(), sizeof(double) * nn, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->D, h->hD.data(), sizeof(double) * nn, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->B, h->hB.data(), sizeof(double) * nn, hipMemcpyHostToDevice, h->stream));
     const unsigned fb = 4096;
     hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, h->stream, h->Z, h->Vz, 0.0);
     hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, h->stream, h->Py, (size_t)h->T, 0.0);
@@ -430,17 +432,18 @@ int upload_initial(qap_ctx *h)
     return upload_scalars(h, 0.0);
 }
 
-// Reset the scalar block (bound lb, no incumbent, t = 0) and the matchings;
-// uploads F, D, B too.
-int upload_scalars(qap_ctx *h, double lb)
+// Reset the scalar block (bound lb, no incumbent, t = 0), the step counters
+// and the matchings.  The host sources live in the handle, so without sync
+// the uploads stay queued on the handle's stream, ahead of its next work.
+int upload_scalars(qap_ctx *h, double lb, bool sync)
 {
     const int n = h->n;
-    const int nn = n * n;
-    HIPCHK(h, hipMemcpyAsync(h->F, h->hF.data(), sizeof(double) * nn, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->D, h->hD.data(), sizeof(double) * nn, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->B, h->hB.data(), sizeof(double) * nn, hipMemcpyHostToDevice, h->stream));
     hipLaunchKernelGGL(k_fill, dim3(16), dim3(256), 0, h->stream, (double *)h->bins, (size_t)kStepBins, 0.0);
-    DevScalars s{};
+    HIPCHK(h, hipGetLastError());
+    // (an earlier reset's upload may still be queued: it writes the same
+    // block to the same place first, so rewriting the host block is safe)
+    DevScalars &s = h->hscal;
+    s = DevScalars{};
     s.lb = lb;
     s.ub = HUGE_VAL;
     s.t = 0;
@@ -450,11 +453,11 @@ int upload_scalars(qap_ctx *h, double lb)
     s.steps = 0;
     s.best = -HUGE_VAL;
     HIPCHK(h, hipMemcpyAsync(h->S, &s, sizeof(s), hipMemcpyHostToDevice, h->stream));
-    std::vector<int> ident(n);
-    for (int i = 0; i < n; ++i) ident[i] = i;
-    HIPCHK(h, hipMemcpyAsync(h->bestperm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->xperm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->hident.resize(n);
+    for (int i = 0; i < n; ++i) h->hident[i] = i;
+    HIPCHK(h, hipMemcpyAsync(h->bestperm, h->hident.data(), sizeof(int) * n, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->xperm, h->hident.data(), sizeof(int) * n, hipMemcpyHostToDevice, h->stream));
+    if (sync) HIPCHK(h, hipStreamSynchronize(h->stream));
     h->t_host = 0;
     return QAP_OK;
 }
@@ -485,7 +488,7 @@ uint64_t fnv1a(uint64_t hsh, const void *data, size_t bytes)
 // Allocate and (optionally) initialise a context of size n.  stream: a
 // caller stream to share (not owned) or nullptr for a new one.  With init the
 // state is Algorithm 1's initial one; otherwise the caller fills Xc, Yc and Z
-// (the child fold) and only the scalars are reset.
+// (the child fold) and resets the scalars (upload_scalars).
 int create_ctx(int n, const double *F, const double *D, const double *B, const qap_params &prm, double offset,
                hipStream_t stream, bool init, qap_ctx **out)
 {
@@ -586,20 +589,27 @@ int create_ctx(int n, const double *F, const double *D, const double *B, const q
     }
     h->trace_cap = trace_cap;
 
-    // facility triples i<j<k, packed 8 bits each
-    std::vector<int> tri;
+    // facility triples i<j<k, packed 8 bits each; F, D, B (they never change
+    // on the device).  The host sources live in the handle.
+    std::vector<int> &tri = h->htri;
     for (int i = 0; i < n; ++i)
         for (int j = i + 1; j < n; ++j)
             for (int k = j + 1; k < n; ++k) tri.push_back(i | (j << 8) | (k << 16));
     h->ntriples = (int)tri.size();
+    const size_t nnb = sizeof(double) * (size_t)n * n;
     if (hipMemcpyAsync(h->triples, tri.data(), sizeof(int) * tri.size(), hipMemcpyHostToDevice, h->stream) !=
             hipSuccess ||
-        hipStreamSynchronize(h->stream) != hipSuccess) {
+        hipMemcpyAsync(h->F, h->hF.data(), nnb, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->D, h->hD.data(), nnb, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->B, h->hB.data(), nnb, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
         g_init_error = "upload failed";
         return cleanup(QAP_EDEVICE);
     }
-    int rc = init ? upload_initial(h) : upload_scalars(h, 0.0);
-    if (rc != QAP_OK) return cleanup(rc);
+    // without init the caller fills the arrays and resets the scalars
+    if (init) {
+        const int rc = upload_initial(h);
+        if (rc != QAP_OK) return cleanup(rc);
+    }
     *out = h;
     return QAP_OK;
 }
