@@ -276,6 +276,7 @@ int fold_core(qap_ctx *h, int l, int s, double child_lb, qap_ctx **child)
         qap_destroy(c);
         return rc;
     }
+    c->folded = true;
     *child = c;
     return QAP_OK;
 }
@@ -482,10 +483,21 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
     // measured once per tile size (looked up only, without allocating)
     if ((bp->zlap_lanes > 0 && bp->zlap_lanes < mz) || (bp->zlap_lanes < 0 && mz > 32))
         return fail(h0, QAP_EINVAL, "zlap_lanes does not hold the batch's largest tile");
+    // real tiles for a first timing of the mappings at this tile size: a
+    // node of the largest m whose z holds reduced costs (it has iterated, or
+    // it was folded from its parent), else none (synthetic tiles)
+    const double *tune_src = nullptr;
+    long long tune_tiles_n = 0;
+    for (int b : ids)
+        if (hs[b]->m == mz && (scal[b].t >= 1 || hs[b]->folded)) {
+            tune_src = hs[b]->Z;
+            tune_tiles_n = hs[b]->T;
+            break;
+        }
     const int Lz = cur == 0 ? -1
                    : bp->zlap_lanes != 0 ? bp->zlap_lanes
                    : no_alloc ? known_batch_lanes(h0->prm.device, mz)
-                              : tuned_batch_lanes(h0->prm.device, stream, mz);
+                              : tuned_batch_lanes(h0->prm.device, stream, mz, tune_src, tune_tiles_n);
     const int Ly = my <= 8 ? 8 : my <= 16 ? 16 : my <= 32 ? 32 : 64;
     auto launch_all = [&]() -> hipError_t {
         hipError_t e;

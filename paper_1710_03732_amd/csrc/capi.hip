@@ -66,6 +66,7 @@ struct qap_ctx {
     // while the handle lives so no upload needs a stream synchronisation
     std::vector<int> htri, hident;
     DevScalars hscal{};
+    bool folded = false;  // a branch-and-bound child: z holds its parent's reduced costs
     std::string err;
     hipGraphExec_t graph = nullptr;  // one full iteration (t >= 1)
     // multiplier tracking (Vz entries like Z, T entries like Yc), or null

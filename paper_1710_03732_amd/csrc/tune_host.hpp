@@ -40,7 +40,7 @@ __global__ void k_tune_fill(double *__restrict__ a, size_t count)
 
 namespace {
 
-constexpr int kTuneRev = 2;                          // revision of the tuned kernels and candidates
+constexpr int kTuneRev = 3;                          // revision of the tuned kernels and candidates
 constexpr long long kTuneTiles = 32768;              // synthetic tiles per timing (fewer for large m)
 constexpr size_t kTuneBytes = (size_t)256 << 20;     // cap on the synthetic tile bytes
 constexpr int kTuneReps = 3;                         // timed launches per mapping, after one warm-up
@@ -227,11 +227,16 @@ TuneChoice measure_zlap(hipStream_t stream, int m, int zlap_waves)
 // Fastest batched Z-LAP kernel for tiles of size m (one node): lane groups
 // of 8..64 (k_bzlap<L>, L >= m), or one or two tiles per wavefront
 // (k_bzlap_s, lanes -1, and k_bzlap_s2, lanes -2; m <= 32); falls back to
-// the smallest group that holds m.
-TuneChoice measure_bzlap(hipStream_t stream, int m)
+// the smallest group that holds m.  real (nullable): real_tiles tiles of
+// size m of a node about to be solved, timed instead of the synthetic ones
+// when there are enough of them (a node's tiles after a few iterations
+// solve in far fewer Dijkstra steps than random ones, and the mappings'
+// order can differ between the two).
+TuneChoice measure_bzlap(hipStream_t stream, int m, const double *real = nullptr, long long real_tiles = 0)
 {
     TuneChoice best{m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 64, 1, -1.0};
-    const long long N = tune_tiles(m);
+    const bool use_real = real && real_tiles >= 1024;
+    const long long N = use_real ? std::min(tune_tiles(m), real_tiles) / 2 * 2 : tune_tiles(m);
     const size_t count = (size_t)N * m * m;
     TuneScratch mem;
     double *src = (double *)mem.get(sizeof(double) * count), *work = (double *)mem.get(sizeof(double) * count);
@@ -241,6 +246,8 @@ TuneChoice measure_bzlap(hipStream_t stream, int m)
     BNode *dnode = (BNode *)mem.get(sizeof(BNode));
     long long *dzl = (long long *)mem.get(2 * sizeof(long long));
     if (!src || !work || !Yc || !S || !bins || !dnode || !dzl || !tune_inputs(stream, src, count, S, bins))
+        return best;
+    if (use_real && hipMemcpyAsync(src, real, sizeof(double) * count, hipMemcpyDeviceToDevice, stream) != hipSuccess)
         return best;
     BNode node{};
     node.Z = work;
@@ -319,10 +326,12 @@ int known_batch_lanes(int device, int m)
 }
 
 // Batched Z-LAP kernel for a batch whose largest tile is m: a lane count of
-// k_bzlap, -1 for k_bzlap_s or -2 for k_bzlap_s2.
-int tuned_batch_lanes(int device, hipStream_t stream, int m)
+// k_bzlap, -1 for k_bzlap_s or -2 for k_bzlap_s2.  real, real_tiles: as for
+// measure_bzlap (used only when the choice for m is not known yet).
+int tuned_batch_lanes(int device, hipStream_t stream, int m, const double *real = nullptr, long long real_tiles = 0)
 {
-    return tuned_choice(tune_key(device, "bzlap", m), [&] { return measure_bzlap(stream, m); }).lanes;
+    return tuned_choice(tune_key(device, "bzlap", m), [&] { return measure_bzlap(stream, m, real, real_tiles); })
+        .lanes;
 }
 
 }  // namespace
