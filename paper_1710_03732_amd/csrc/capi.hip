@@ -62,10 +62,11 @@ struct qap_ctx {
     double zl_tune_us = -1.0; // its time over the tuner's synthetic tiles (< 0: rule-based)
     double offset = 0.0; // constant added to every permutation cost (B&B nodes)
     std::vector<double> hF, hD, hB;
-    // host sources of the asynchronous uploads at creation and reset, kept
-    // while the handle lives so no upload needs a stream synchronisation
-    std::vector<int> htri, hident;
-    DevScalars hscal{};
+    // host mirror of the arena's small arrays, from F to the step counters
+    // (F, D, B, alpha, beta, the two matchings, the triples, the scalar
+    // block, the counters: contiguous in the arena), uploaded in one copy at
+    // every reset; it lives while the handle does, so no upload waits
+    std::vector<char> hsmall;
     bool folded = false;  // a branch-and-bound child: z holds its parent's reduced costs
     std::string err;
     hipGraphExec_t graph = nullptr;  // one full iteration (t >= 1)
@@ -417,34 +418,34 @@ void derive_constants(qap_ctx *h)
 
 int upload_scalars(qap_ctx *h, double lb, bool sync = true);
 
-// Algorithm 1's initial state (F, D and B are on the device already).
+// Algorithm 1's initial state.
 int upload_initial(qap_ctx *h)
 {
     const int n = h->n;
     const int nn = n * n;
+    // F, D and B (with the reset scalars) before k_init_xy reads them
+    const int rc = upload_scalars(h, 0.0, false);
+    if (rc != QAP_OK) return rc;
     const unsigned fb = 4096;
     hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, h->stream, h->Z, h->Vz, 0.0);
     hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, h->stream, h->Py, (size_t)h->T, 0.0);
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, h->stream, h->Px, (size_t)nn, 0.0);
-    hipLaunchKernelGGL(k_fill, dim3(16), dim3(256), 0, h->stream, (double *)h->bins, (size_t)kStepBins, 0.0);
     hipLaunchKernelGGL(k_init_xy, dim3(std::min<long long>((h->T + 255) / 256, 65535)), dim3(256), 0,
                        h->stream, h->F, h->D, h->B, h->Xc, h->Yc, n);
     HIPCHK(h, hipGetLastError());
-    return upload_scalars(h, 0.0);
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return QAP_OK;
 }
 
 // Reset the scalar block (bound lb, no incumbent, t = 0), the step counters
-// and the matchings.  The host sources live in the handle, so without sync
-// the uploads stay queued on the handle's stream, ahead of its next work.
+// and the matchings, in one upload of the small arrays (F, D, B and the
+// triples come along unchanged).  The source is the handle's host mirror,
+// so without sync the upload stays queued on the handle's stream, ahead of
+// its next work.  (An earlier reset's upload may still be queued: it writes
+// the same region first, so rewriting the mirror is safe.)
 int upload_scalars(qap_ctx *h, double lb, bool sync)
 {
-    const int n = h->n;
-    hipLaunchKernelGGL(k_fill, dim3(16), dim3(256), 0, h->stream, (double *)h->bins, (size_t)kStepBins, 0.0);
-    HIPCHK(h, hipGetLastError());
-    // (an earlier reset's upload may still be queued: it writes the same
-    // block to the same place first, so rewriting the host block is safe)
-    DevScalars &s = h->hscal;
-    s = DevScalars{};
+    DevScalars s{};
     s.lb = lb;
     s.ub = HUGE_VAL;
     s.t = 0;
@@ -453,11 +454,9 @@ int upload_scalars(qap_ctx *h, double lb, bool sync)
     s.stopped = 0;
     s.steps = 0;
     s.best = -HUGE_VAL;
-    HIPCHK(h, hipMemcpyAsync(h->S, &s, sizeof(s), hipMemcpyHostToDevice, h->stream));
-    h->hident.resize(n);
-    for (int i = 0; i < n; ++i) h->hident[i] = i;
-    HIPCHK(h, hipMemcpyAsync(h->bestperm, h->hident.data(), sizeof(int) * n, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->xperm, h->hident.data(), sizeof(int) * n, hipMemcpyHostToDevice, h->stream));
+    char *base = h->hsmall.data();
+    std::memcpy(base + ((char *)h->S - (char *)h->F), &s, sizeof(s));
+    HIPCHK(h, hipMemcpyAsync(h->F, base, h->hsmall.size(), hipMemcpyHostToDevice, h->stream));
     if (sync) HIPCHK(h, hipStreamSynchronize(h->stream));
     h->t_host = 0;
     return QAP_OK;
@@ -590,23 +589,28 @@ int create_ctx(int n, const double *F, const double *D, const double *B, const q
     }
     h->trace_cap = trace_cap;
 
-    // facility triples i<j<k, packed 8 bits each; F, D, B (they never change
-    // on the device).  The host sources live in the handle.
-    std::vector<int> &tri = h->htri;
-    for (int i = 0; i < n; ++i)
-        for (int j = i + 1; j < n; ++j)
-            for (int k = j + 1; k < n; ++k) tri.push_back(i | (j << 8) | (k << 16));
-    h->ntriples = (int)tri.size();
-    const size_t nnb = sizeof(double) * (size_t)n * n;
-    if (hipMemcpyAsync(h->triples, tri.data(), sizeof(int) * tri.size(), hipMemcpyHostToDevice, h->stream) !=
-            hipSuccess ||
-        hipMemcpyAsync(h->F, h->hF.data(), nnb, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-        hipMemcpyAsync(h->D, h->hD.data(), nnb, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-        hipMemcpyAsync(h->B, h->hB.data(), nnb, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
-        g_init_error = "upload failed";
-        return cleanup(QAP_EDEVICE);
+    // the host mirror of the small arrays: F, D, B, zero duals, identity
+    // matchings, the facility triples i<j<k (packed 8 bits each), a scalar
+    // block (set by each reset), zero step counters
+    h->hsmall.assign((char *)(h->bins + kStepBins) - (char *)h->F, 0);
+    {
+        char *base = h->hsmall.data();
+        auto at = [&](const void *dev) { return base + ((const char *)dev - (const char *)h->F); };
+        const size_t nnb = sizeof(double) * (size_t)n * n;
+        std::memcpy(at(h->F), h->hF.data(), nnb);
+        std::memcpy(at(h->D), h->hD.data(), nnb);
+        std::memcpy(at(h->B), h->hB.data(), nnb);
+        int *xp = (int *)at(h->xperm), *bp = (int *)at(h->bestperm);
+        for (int i = 0; i < n; ++i) xp[i] = bp[i] = i;
+        int *tp = (int *)at(h->triples);
+        int nt = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j)
+                for (int k = j + 1; k < n; ++k) tp[nt++] = i | (j << 8) | (k << 16);
+        h->ntriples = nt;
     }
-    // without init the caller fills the arrays and resets the scalars
+    // without init the caller fills the arrays and resets the scalars (the
+    // reset uploads the mirror)
     if (init) {
         const int rc = upload_initial(h);
         if (rc != QAP_OK) return cleanup(rc);
