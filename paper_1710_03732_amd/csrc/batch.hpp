@@ -459,25 +459,29 @@ __global__ __launch_bounds__(64) void k_bxlap(const BNode *__restrict__ nodes, B
     const BNode &N = nodes[blockIdx.x];
     const gptr<DevScalars> S = glob(N.S);
     if (S->stopped) return;
-    __shared__ double M[64 * 64];
-    __shared__ double lu[64], vs[64];
-    __shared__ int lp[64], lw[64];
+    // the cost matrix, then the solver's scratch (as k_xlap)
+    __shared__ double M[64 * 64 + 64 + 32];
+    __shared__ double vs[64];
     __shared__ int sig[64];
     __shared__ int improved;
     const int l = threadIdx.x;
     const int n = N.n, nn = n * n;
     copy_to_lds(M, (const double *)glob((const double *)N.Xc), nn, l, 64);
     __syncthreads();
-    double u[1], v[1], th;
-    int pc[1], st = 0;
-    lap_solve<64, 1>(M, n, l, 0, lu, lp, lw, u, v, pc, th, st);
+    double u, v, th;
+    int pc, st;
+    if (n <= 32)
+        lap_solve_scalar1<32>(M, 0, nn, n, u, v, pc, th, st);
+    else
+        lap_solve_scalar1<64>(M, 0, nn, n, u, v, pc, th, st);
     if (l < n) {
-        vs[l] = v[0];
-        glob(N.alpha)[l] = u[0];
-        glob(N.beta)[l] = v[0];
-        sig[pc[0]] = l;
+        vs[l] = v;
+        glob(N.alpha)[l] = u;
+        glob(N.beta)[l] = v;
+        sig[pc] = l;
     }
     __syncthreads();
+    const double *lu = M + nn;  // the row potentials
     for (int e = l; e < nn; e += 64) glob(N.Px)[e] = (M[e] - lu[e / n]) - vs[e % n];
     double cd = 0.0;
     long long ci = 0;

@@ -238,26 +238,14 @@ hipError_t launch_zlap(qap_ctx *h)
     return hipErrorInvalidValue;
 }
 
-template <int L, int C>
-hipError_t launch_ylap_t(qap_ctx *h, int equalize)
-{
-    const int n = h->n, m = n - 1;
-    const size_t per = ((size_t)m * m + 2 * m) * sizeof(double);
-    int G = 256 / L;
-    while (G > 1 && (size_t)G * per > 65536) --G;
-    const int blocks = (n * n + G - 1) / G;
-    hipLaunchKernelGGL((k_ylap<L, C>), dim3(blocks), dim3(G * L), G * per, h->stream, h->Yc, h->Py,
-                       h->Xc, n, equalize, h->ophy, h->phy, h->S, h->bins, h->Ut);
-    return hipGetLastError();
-}
-
 hipError_t launch_ylap(qap_ctx *h, int equalize)
 {
-    const int m = h->n - 1;
-    if (m <= 8) return launch_ylap_t<8, 1>(h, equalize);
-    if (m <= 16) return launch_ylap_t<16, 1>(h, equalize);
-    if (m <= 32) return launch_ylap_t<16, 2>(h, equalize);
-    return launch_ylap_t<16, 4>(h, equalize);
+    const int n = h->n, m = n - 1;
+    // one Y-LAP per wavefront, scalar-controlled solver
+    const size_t per = ((size_t)m * m + m) * sizeof(double) + ((size_t)m * sizeof(int) + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_ylap_s, dim3((unsigned)(n * n)), dim3(64), per, h->stream, h->Yc, h->Py, h->Xc, n,
+                       equalize, h->ophy, h->phy, h->S, h->bins, h->Ut);
+    return hipGetLastError();
 }
 
 // Cube edge of the sweep for size n: 10 when its cubes cover the n^3

@@ -8,7 +8,7 @@
 //                 orbit of six symmetric z variables (Eq. rlt2:con3)
 //   k_scale_xy    the x and y levels keep (1-kappa) of their slack
 //   k_zlap        Z-LAPs (Theta_ijpq, xi, psi), one lane group per tile
-//   k_ylap        y-pair rule (Eq. da:yrule1) fused into the load, then the
+//   k_ylap_s      y-pair rule (Eq. da:yrule1) fused into the load, then the
 //                 Y-LAPs (Delta_ip, gamma, delta)
 //   k_xlap        the X-LAP, bound, incumbent, feasibility check, stop flag
 //
@@ -625,93 +625,84 @@ __global__ __launch_bounds__(64) void k_lap_batch_s(const double *__restrict__ c
 }
 
 // ----------------------------------------------------------------- Y-LAP --
-// One group per (i,p); its (n-1)x(n-1) block of R_y is contiguous.  For
+// One Y-LAP per (i,p); its (n-1)x(n-1) block of R_y is contiguous.  For
 // t >= 1 every entry is first replaced by ophy*R_y[ijpq] + phy*R_y[jiqp]
 // (the y-pair rule applied by both members of the pair).  Writes pi_y to Py
 // and adds Delta_ip to R_x.  With Ut (same layout as Yc) each entry's
 // multiplier moves by phy * (own - partner) (Eq. da:yrule1).
-template <int L, int C>
-__global__ __launch_bounds__(256) void k_ylap(const double *__restrict__ Yc, double *__restrict__ Py,
-                                              double *__restrict__ Xc, int n, int equalize,
-                                              double ophy, double phy, DevScalars *__restrict__ S,
-                                              unsigned long long *__restrict__ bins,
-                                              double *__restrict__ Ut)
+//
+// One wavefront per Y-LAP (i,p) with the scalar-controlled solver.  A Y-LAP
+// phase has only n^2 LAPs, one or a few per SIMD: what counts is how fast one
+// LAP is solved, and a step of this solver is the shortest (a lane-group
+// mapping took 2.6 times as long at n = 30).
+__global__ __launch_bounds__(64) void k_ylap_s(const double *__restrict__ Yc, double *__restrict__ Py,
+                                               double *__restrict__ Xc, int n, int equalize, double ophy,
+                                               double phy, DevScalars *__restrict__ S,
+                                               unsigned long long *__restrict__ bins, double *__restrict__ Ut)
 {
     if (S->stopped) return;
     extern __shared__ double lds[];
-    __shared__ unsigned long long bsteps;
+    const int lane = (int)(threadIdx.x & 63);
     const int m = n - 1, mm = m * m;
-    const int G = blockDim.x / L;
-    const int g = threadIdx.x / L, l = threadIdx.x % L;
-    const int gbase = (threadIdx.x & 63) - l;
-    const int ip = blockIdx.x * G + g;
-    double *M = lds + (size_t)g * (mm + 2 * m);
-    double *lu = M + mm;
-    int *lp = (int *)(lu + m);
-    int *lw = lp + m;
-    if (threadIdx.x == 0) bsteps = 0ull;
-    const bool active = ip < n * n;
-    const double xc0 = active ? Xc[ip] : 0.0;  // read now, added to after the solve
-    if (active) {
-        const int i = ip / n, p = ip % n;
-        const long long base = (long long)ip * mm;
-        // batches of loads (own entry, and the partner entry of the y-pair
-        // rule) issued before their use, as in copy_to_lds
-        for (int e0 = 0; e0 < mm; e0 += 8 * L) {
-            double av[8], bv[8];
+    const int ip = blockIdx.x;
+    const int i = ip / n, p = ip % n;
+    const long long base = (long long)ip * mm;
+    const double xc0 = Xc[ip];  // read now, added to after the solve
+    for (int e0 = 0; e0 < mm; e0 += 8 * 64) {
+        double av[8], bv[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int e = e0 + l + L * k;
-                if (e < mm) {
-                    av[k] = Yc[base + e];
-                    if (equalize) {
-                        const int jp = e / m, qp = e % m;
-                        const int j = jp + (jp >= i), q = qp + (qp >= p);
-                        bv[k] = Yc[((long long)(j * n + q) * m + (i - (i > j))) * m + (p - (p > q))];
-                    }
+        for (int k = 0; k < 8; ++k) {
+            const int e = e0 + lane + 64 * k;
+            if (e < mm) {
+                av[k] = Yc[base + e];
+                if (equalize) {
+                    const int jp = e / m, qp = e % m;
+                    const int j = jp + (jp >= i), q = qp + (qp >= p);
+                    bv[k] = Yc[((long long)(j * n + q) * m + (i - (i > j))) * m + (p - (p > q))];
                 }
             }
+        }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int e = e0 + l + L * k;
-                if (e < mm) {
-                    double a = av[k];
-                    if (equalize) {
-                        const double b = bv[k];
-                        if (Ut) Ut[base + e] = Ut[base + e] + phy * (a - b);
-                        a = ophy * a + phy * b;
-                    }
-                    M[e] = a;
+        for (int k = 0; k < 8; ++k) {
+            const int e = e0 + lane + 64 * k;
+            if (e < mm) {
+                double a = av[k];
+                if (equalize) {
+                    const double b = bv[k];
+                    if (Ut) Ut[base + e] = Ut[base + e] + phy * (a - b);
+                    a = ophy * a + phy * b;
                 }
+                lds[e] = a;
             }
         }
     }
     __syncthreads();
-    if (active) {
-        double u[C], v[C], th;
-        int pc[C], st = 0;
-        lap_solve<L, C>(M, m, l, gbase, lu, lp, lw, u, v, pc, th, st);
-        __builtin_amdgcn_wave_barrier();
-        double *vs = lu + m;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int j = l + L * c;
-            if (j < m) vs[j] = v[c];
-        }
-        __builtin_amdgcn_wave_barrier();
-        const long long base = (long long)ip * mm;
-        for (int e = l; e < mm; e += L) Py[base + e] = (M[e] - lu[e / m]) - vs[e % m];
-        if (l == 0) {
-            Xc[ip] = xc0 + th;
-            atomicAdd(&bsteps, (unsigned long long)st);
-        }
+    double u, v, th;
+    int pc, st;
+    if (m <= 32)
+        lap_solve_scalar1<32>(lds, 0, mm, m, u, v, pc, th, st);
+    else
+        lap_solve_scalar1<64>(lds, 0, mm, m, u, v, pc, th, st);
+    __builtin_amdgcn_wave_barrier();
+    // slacks out row by row (the scratch holds the row potentials); with
+    // m <= 32 the two half-waves take alternate rows
+    const bool two = m <= 32;
+    const int sub = two ? (lane >> 5) : 0, col = two ? (lane & 31) : lane;
+    const double vc = __shfl(v, col);  // every lane takes part
+    if (col < m) {
+        const double *us = lds + mm;
+        const int step = two ? 2 : 1;
+        for (int r = sub; r < m; r += step) Py[base + r * m + col] = (lds[r * m + col] - us[r]) - vc;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(&bins[blockIdx.x & (kStepBins - 1)], bsteps);
+    if (lane == 0) {
+        Xc[ip] = xc0 + th;
+        atomicAdd(&bins[blockIdx.x & (kStepBins - 1)], (unsigned long long)st);
+    }
 }
 
 // ----------------------------------------------------------------- X-LAP --
-// One wave.  LB += theta_x; pi_x -> Px; alpha/beta; the assignment is a QAP
+// One wave (scalar-controlled solver).  LB += theta_x; pi_x -> Px;
+// alpha/beta; the assignment is a QAP
 // solution whose exact cost (int64 for integer data) updates the incumbent;
 // feasibility check and gap test set the stop flag.
 __global__ __launch_bounds__(64) void k_xlap(const double *__restrict__ Xc, double *__restrict__ Px,
@@ -723,25 +714,30 @@ __global__ __launch_bounds__(64) void k_xlap(const double *__restrict__ Xc, doub
                                              DevScalars *__restrict__ S)
 {
     if (S->stopped) return;
-    __shared__ double M[64 * 64];
-    __shared__ double lu[64], vs[64];
-    __shared__ int lp[64], lw[64];
+    // the cost matrix, then the solver's scratch (row potentials, one int
+    // per column)
+    __shared__ double M[64 * 64 + 64 + 32];
+    __shared__ double vs[64];
     __shared__ int sig[64];
     __shared__ int improved;
     const int l = threadIdx.x;
     const int nn = n * n;
     copy_to_lds(M, Xc, nn, l, 64);
     __syncthreads();
-    double u[1], v[1], th;
-    int pc[1], st = 0;
-    lap_solve<64, 1>(M, n, l, 0, lu, lp, lw, u, v, pc, th, st);
+    double u, v, th;
+    int pc, st;
+    if (n <= 32)
+        lap_solve_scalar1<32>(M, 0, nn, n, u, v, pc, th, st);
+    else
+        lap_solve_scalar1<64>(M, 0, nn, n, u, v, pc, th, st);
     if (l < n) {
-        vs[l] = v[0];
-        alpha[l] = u[0];
-        beta[l] = v[0];
-        sig[pc[0]] = l;
+        vs[l] = v;
+        alpha[l] = u;
+        beta[l] = v;
+        sig[pc] = l;
     }
     __syncthreads();
+    const double *lu = M + nn;  // the row potentials
     for (int e = l; e < nn; e += 64) Px[e] = (M[e] - lu[e / n]) - vs[e % n];
     // exact cost of the assignment
     double cd = 0.0;
