@@ -189,6 +189,76 @@ def cpu_baseline(inst, threads: int | None, gpu_trace, budget_s: float = 10.0):
             "lb_after": lb, "gpu_parity": parity}
 
 
+def mem_available_gb() -> float:
+    """MemAvailable of /proc/meminfo in GB (0 if unreadable)."""
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemAvailable:"):
+                    return int(line.split()[1]) * 1024 / 1e9
+    except OSError:
+        pass
+    return 0.0
+
+
+def oracle_sizes_leg():
+    """The CPU oracle at the other sizes of the measurement plan, beside the
+    GPU on the same iterations: the n = 15 grid (3x5, 200 iterations after
+    iteration 0 on all threads, then 10 on one thread) and the n = 42 dense
+    instance (2 iterations after iteration 0 on all threads; its dense z
+    array takes 43.9 GB, so it runs only with at least 48 GB of host memory
+    available).  The GPU runs the same iterations on graph replay; the bounds
+    are compared bitwise."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1710_03732_amd import binding, instances as insts
+
+    used = O.max_threads()
+    out = {"cores": used, "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+    def one(inst, iters_all: int, iters_single: int):
+        F, D, B = inst.arrays()
+        nn = inst.n
+        laps = nn * nn * (nn - 1) ** 2 + nn * nn + 1
+        cpu = O.DualAscent(F, D, B)
+        cpu.run(1)  # iteration 0, untimed
+        t0 = time.perf_counter()
+        cpu.run(iters_all)
+        el = time.perf_counter() - t0
+        res = {"n": nn, "instance": inst.name, "iterations": iters_all, "seconds": el,
+               "iterations_per_s": iters_all / el, "laps_per_s": iters_all * laps / el, "threads": used}
+        if iters_single:
+            O.set_threads(1)
+            t0 = time.perf_counter()
+            cpu.run(iters_single)
+            one_s = time.perf_counter() - t0
+            O.set_threads(used)
+            res["single_thread"] = {"iterations": iters_single, "seconds": one_s,
+                                    "iterations_per_s": iters_single / one_s}
+        total = 1 + iters_all + iters_single
+        gpu = binding.DualAscent(F, D, B)
+        gpu.run(1)
+        t0 = time.perf_counter()
+        gpu.run(total - 1)
+        gel = time.perf_counter() - t0
+        gt = gpu.trace()
+        res["gpu"] = {"iterations": total - 1, "seconds": gel, "iterations_per_s": (total - 1) / gel}
+        res["bound_after"] = cpu.LB
+        res["gpu_trace_equal"] = bool(np.array_equal(np.asarray(gt[:total]), np.asarray(cpu.trace())))
+        gpu.close()
+        del cpu
+        return res
+
+    out["n15"] = one(insts.grid_n15(), 200, 10)
+    avail = mem_available_gb()
+    if avail >= 48.0:
+        out["n42"] = one(insts.dense_instance(42, 0), 2, 0)
+    else:
+        out["n42"] = {"skipped": f"{avail:.1f} GB of host memory available, 48 GB needed"}
+    return out
+
+
 def warm_vs_cold(inst, cold_iters: int):
     """Time-to-bound: wall time of `cold_iters` cold F1 iterations (W, bound
     LB_cold) against the learned warm start (features, inference and z
@@ -546,6 +616,8 @@ def main(argv=None):
                     help="cold iterations whose bound the learned warm start must reach")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 2 GiB device copy (PMC counter calibration)")
+    ap.add_argument("--oracle-sizes", action="store_true",
+                    help="also time the CPU oracle at n = 15 (200 iterations) and n = 42 (2 iterations)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -653,6 +725,7 @@ def main(argv=None):
         "time_to_bound": None,
         "n42": None,
         "cpu_baseline": None,
+        "oracle_sizes": None,
     }
     da.close()
     out["graph_replay"] = graph_replay_leg(inst, args.steps, args.warmup, full_trace)
@@ -672,6 +745,8 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_threads or None, full_trace)
+    if args.oracle_sizes:
+        out["oracle_sizes"] = oracle_sizes_leg()
     print(json.dumps(out), flush=True)
     par = (out["cpu_baseline"] or {}).get("gpu_parity")
     if par is not None and par["gpu_lb"] is not None and not par["within_1e-9"]:
