@@ -197,24 +197,32 @@ hipError_t launch_zlap_t(qap_ctx *h)
     return hipGetLastError();
 }
 
+// Tile rows held in registers by the kernels compiled for m = 28 and m = 40
+// (k_zlap_s, k_lap_batch_s).  With the whole tile in LDS, LDS limits a CU to
+// 24 resident LAPs at m = 28 and 12 at m = 40; with these rows in registers
+// the limits are 32 (the wave limit; 54 VGPRs) and 28 (70 VGPRs).
+constexpr int kRegRows28 = 16, kRegRows40 = 24;
+
 template <int H>
 hipError_t launch_zlap_s(qap_ctx *h)
 {
     const int m = h->m;
-    // one LAP: tile, row potentials and one int per column (the solver's
-    // proposal and matching slots share it); two LAPs: also v for the epilogue
-    const size_t per = H == 1 ? ((size_t)m * m + m) * sizeof(double) + ((size_t)m * sizeof(int) + 7) / 8 * 8
+    const int kr = (H == 1 && m == 28) ? kRegRows28 : (H == 1 && m == 40) ? kRegRows40 : 0;
+    // one LAP: the tile's LDS rows, row potentials and one int per column
+    // (the solver's proposal and matching slots share it); two LAPs: also v
+    // for the epilogue
+    const size_t per = H == 1 ? ((size_t)(m - kr) * m + m) * sizeof(double) + ((size_t)m * sizeof(int) + 7) / 8 * 8
                               : ((size_t)m * m + 2 * m) * sizeof(double) * H;
     // HALF: one block per tile with i < j (half of them; H = 1 only)
     const int half = (H == 1 && h->half) ? 1 : 0;
     const long long blocks = half ? h->T / 2 : (h->T + H - 1) / H;
     // the tile sizes of the n = 30 and n = 42 workloads have kernels compiled for them
     if (H == 1 && m == 28)
-        hipLaunchKernelGGL((k_zlap_s<1, 28>), dim3((unsigned)blocks), dim3(64), per, h->stream, h->Z, h->Yc, m,
-                           h->T, h->S, h->bins, half);
+        hipLaunchKernelGGL((k_zlap_s<1, 28, kRegRows28>), dim3((unsigned)blocks), dim3(64), per, h->stream, h->Z,
+                           h->Yc, m, h->T, h->S, h->bins, half);
     else if (H == 1 && m == 40)
-        hipLaunchKernelGGL((k_zlap_s<1, 40>), dim3((unsigned)blocks), dim3(64), per, h->stream, h->Z, h->Yc, m,
-                           h->T, h->S, h->bins, half);
+        hipLaunchKernelGGL((k_zlap_s<1, 40, kRegRows40>), dim3((unsigned)blocks), dim3(64), per, h->stream, h->Z,
+                           h->Yc, m, h->T, h->S, h->bins, half);
     else
         hipLaunchKernelGGL((k_zlap_s<H>), dim3((unsigned)blocks), dim3(64), per, h->stream, h->Z, h->Yc, m,
                            h->T, h->S, h->bins, half);
@@ -996,11 +1004,11 @@ int qap_lap_batch(const double *cost, int count, int m, double *u, double *v, do
             hipLaunchKernelGGL((k_lap_batch_s<2>), dim3(bs), dim3(64), pers, s, cost, count, m, u, v, theta,
                                (int *)row_of_col);
         else if (m == 28)  // the tile sizes with kernels compiled for them (k_zlap_s)
-            hipLaunchKernelGGL((k_lap_batch_s<1, 28>), dim3(bs), dim3(64), pers, s, cost, count, m, u, v, theta,
-                               (int *)row_of_col);
+            hipLaunchKernelGGL((k_lap_batch_s<1, 28, kRegRows28>), dim3(bs), dim3(64), pers, s, cost, count, m, u, v,
+                               theta, (int *)row_of_col);
         else if (m == 40)
-            hipLaunchKernelGGL((k_lap_batch_s<1, 40>), dim3(bs), dim3(64), pers, s, cost, count, m, u, v, theta,
-                               (int *)row_of_col);
+            hipLaunchKernelGGL((k_lap_batch_s<1, 40, kRegRows40>), dim3(bs), dim3(64), pers, s, cost, count, m, u, v,
+                               theta, (int *)row_of_col);
         else
             hipLaunchKernelGGL((k_lap_batch_s<1>), dim3(bs), dim3(64), pers, s, cost, count, m, u, v, theta,
                                (int *)row_of_col);

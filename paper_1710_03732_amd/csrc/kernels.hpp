@@ -505,11 +505,15 @@ __global__ __launch_bounds__(256) void k_zlap(double *__restrict__ Z, double *__
 // MC > 0 compiles the kernel for tiles of size MC (m must equal it): the
 // tile copy, the column reduction and the write-back then run with constant
 // trip counts and immediate offsets.  Same arithmetic in the same order.
-template <int H, int MC = 0>
+// KR > 0 (one LAP of a fixed size): the tile's first KR rows go to registers
+// rather than LDS (see lap_solve_scalar1), so a LAP takes KR*m*8 bytes less
+// LDS and more of them are resident on a CU.
+template <int H, int MC = 0, int KR = 0>
 __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *__restrict__ Yc, int m_in,
                                                long long T, DevScalars *__restrict__ S,
                                                unsigned long long *__restrict__ bins, int half)
 {
+    static_assert(KR == 0 || (H == 1 && MC >= KR && KR <= 24), "register rows need one LAP of a fixed size");
     if (S->stopped) return;
     extern __shared__ double lds[];
     constexpr int W = 64 / H;
@@ -524,24 +528,36 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
     // (one tile per block: every block of the grid has its tile)
     const int nt = (H == 1) ? 1 : (int)(left < H ? left : H);
     double *src = Z + t0 * mm;
-    copy_to_lds(lds, src, nt * mm, lane, 64);
+    dreg16 R = {};
+    dreg8 R2 = {};
+    if constexpr (KR > 0) {
+        const int cl = lane < m ? lane : 0;  // lanes past m hold a copy of column 0 (never used)
+#pragma unroll
+        for (int r = 0; r < KR; ++r) {
+            if (r < 16)
+                R[r] = src[r * m + cl];
+            else
+                R2[r - 16] = src[r * m + cl];
+        }
+    }
+    copy_to_lds(lds, src + KR * m, nt * mm - KR * m, lane, 64);
     const double yc0 = (h < nt) ? Yc[t0 + h] : 0.0;  // read now, added to after the solve
-    double *scr = lds + (size_t)H * mm;
+    double *scr = lds + (size_t)H * mm - KR * m;
     int toff[H], soff[H];
 #pragma unroll
     for (int q = 0; q < H; ++q) {
         const int qq = q < nt ? q : 0;
         toff[q] = qq * mm;
-        soff[q] = H * mm + qq * 2 * m;
+        soff[q] = H * mm - KR * m + qq * 2 * m;
     }
     __syncthreads();
     double u, v, th;
     int p, st;
     if constexpr (H == 1) {
         if (m <= 32)
-            lap_solve_scalar1<32>(lds, toff[0], soff[0], m, u, v, p, th, st);
+            lap_solve_scalar1<32, KR>(lds, toff[0], soff[0], m, u, v, p, th, st, R, R2);
         else
-            lap_solve_scalar1<64>(lds, toff[0], soff[0], m, u, v, p, th, st);
+            lap_solve_scalar1<64, KR>(lds, toff[0], soff[0], m, u, v, p, th, st, R, R2);
     } else {
         lap_solve_scalar2(lds, toff, soff, m, nt, u, v, p, th, st);
     }
@@ -559,15 +575,22 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
         const int sub = two ? (lane >> 5) : 0;
         const int col = (H == 1 && !two) ? lane : (lane & 31);
         const double vcol = (H == 1) ? __shfl(v, col) : 0.0;  // every lane takes part
+        const double *us = scr + (size_t)h * 2 * m;
+        double *dst = src + (size_t)h * mm;
+        if constexpr (KR > 0) {
+            // the register rows: lane l holds column l and its v
+            if (lane < m) {
+#pragma unroll
+                for (int r = 0; r < KR; ++r) dst[r * m + lane] = ((r < 16 ? R[r] : R2[r - 16]) - us[r]) - v;
+            }
+        }
         if (h < nt && col < m) {
-            const double *us = scr + (size_t)h * 2 * m;
             const double vc = (H == 1) ? vcol : us[m + col];
-            const double *tl = lds + (size_t)h * mm;
-            double *dst = src + (size_t)h * mm;
+            const double *tl = lds + (size_t)h * mm - KR * m;  // row r >= KR at tl + r*m
             const int step = two ? 2 : 1;
             // a constant trip count (rows past m skipped) lets a fixed m unroll it
-            for (int k = 0; k < (m + step - 1) / step; ++k) {
-                const int r = k * step + sub;
+            for (int k = 0; k < (m - KR + step - 1) / step; ++k) {
+                const int r = KR + k * step + sub;
                 if (r < m) dst[r * m + col] = (tl[r * m + col] - us[r]) - vc;
             }
         }
@@ -579,12 +602,13 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
 }
 
 // LAP batch with the scalar-controlled solver (validation entry point);
-// MC > 0 as for k_zlap_s.
-template <int H, int MC = 0>
+// MC > 0 and KR > 0 as for k_zlap_s.
+template <int H, int MC = 0, int KR = 0>
 __global__ __launch_bounds__(64) void k_lap_batch_s(const double *__restrict__ cost, int count, int m_in,
                                                     double *__restrict__ uo, double *__restrict__ vo,
                                                     double *__restrict__ tho, int *__restrict__ rco)
 {
+    static_assert(KR == 0 || (H == 1 && MC >= KR && KR <= 24), "register rows need one LAP of a fixed size");
     extern __shared__ double lds[];
     constexpr int W = 64 / H;
     const int m = MC > 0 ? MC : m_in;
@@ -596,22 +620,34 @@ __global__ __launch_bounds__(64) void k_lap_batch_s(const double *__restrict__ c
     const long long left = count - t0;
     const int nt = (int)(left < H ? left : H);
     const double *src = cost + t0 * mm;
-    copy_to_lds(lds, src, nt * mm, lane, 64);
+    dreg16 R = {};
+    dreg8 R2 = {};
+    if constexpr (KR > 0) {
+        const int cl = lane < m ? lane : 0;
+#pragma unroll
+        for (int r = 0; r < KR; ++r) {
+            if (r < 16)
+                R[r] = src[r * m + cl];
+            else
+                R2[r - 16] = src[r * m + cl];
+        }
+    }
+    copy_to_lds(lds, src + KR * m, nt * mm - KR * m, lane, 64);
     int toff[H], soff[H];
 #pragma unroll
     for (int q = 0; q < H; ++q) {
         const int qq = q < nt ? q : 0;
         toff[q] = qq * mm;
-        soff[q] = H * mm + qq * 2 * m;
+        soff[q] = H * mm - KR * m + qq * 2 * m;
     }
     __syncthreads();
     double u, v, th;
     int p, st;
     if constexpr (H == 1) {
         if (m <= 32)
-            lap_solve_scalar1<32>(lds, toff[0], soff[0], m, u, v, p, th, st);
+            lap_solve_scalar1<32, KR>(lds, toff[0], soff[0], m, u, v, p, th, st, R, R2);
         else
-            lap_solve_scalar1<64>(lds, toff[0], soff[0], m, u, v, p, th, st);
+            lap_solve_scalar1<64, KR>(lds, toff[0], soff[0], m, u, v, p, th, st, R, R2);
     } else {
         lap_solve_scalar2(lds, toff, soff, m, nt, u, v, p, th, st);
     }

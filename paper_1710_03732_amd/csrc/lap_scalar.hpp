@@ -27,6 +27,11 @@
 
 namespace qap {
 
+// Sixteen (eight) doubles per lane, indexed by a wave-uniform row in
+// registers.
+typedef double dreg16 __attribute__((ext_vector_type(16)));
+typedef double dreg8 __attribute__((ext_vector_type(8)));
+
 __device__ __forceinline__ double vmin_f64(double a, double b)
 {
     double r;
@@ -74,10 +79,20 @@ __device__ __forceinline__ double part_min(double x)
 // directly.
 // Tile at lds + toff, scratch at lds + soff; m <= RW (RW = 32: every live
 // column sits in the lower half-wave and the minimum stops after 32 lanes).
-template <int RW>
+//
+// KR > 0 (KR <= m, KR <= 24): rows 0..KR-1 of the tile are held in
+// registers instead, lane l holding entry (r, l) of row r in R[r] (r < 16)
+// or R2[r - 16], and the LDS at lds + toff holds rows KR..m-1 only.  A
+// Dijkstra step reads a register row by a wave-uniform register index (the
+// row is in an SGPR), so the values and the order of the arithmetic are
+// those of the all-LDS solver.  It trades VGPRs for LDS, which sets the
+// number of resident LAPs when m is large.
+template <int RW, int KR = 0>
 __device__ void lap_solve_scalar1(double *lds, int toff, int soff, int m, double &u, double &v, int &p,
-                                  double &theta, int &steps)
+                                  double &theta, int &steps, dreg16 R = {}, dreg8 R2 = {})
 {
+    static_assert(KR <= 24, "at most 24 register rows");
+    constexpr int KR1 = KR < 16 ? KR : 16, KR2 = KR - KR1;
     const int l = (int)(threadIdx.x & 63);
     const bool valid = l < m;
     const double *M = lds + toff;
@@ -93,12 +108,32 @@ __device__ void lap_solve_scalar1(double *lds, int toff, int soff, int m, double
     p = -1;
     int prop = 0;
     if (valid) {
-        double best = M[l];
-        for (int i = 1; i < m; ++i) {
-            const double x = M[i * m + l];
-            if (x < best) {
-                best = x;
-                prop = i;
+        double best;
+        if constexpr (KR > 0) {
+            best = R[0];
+#pragma unroll
+            for (int i = 1; i < KR; ++i) {
+                const double x = i < 16 ? R[i] : R2[i - 16];
+                if (x < best) {
+                    best = x;
+                    prop = i;
+                }
+            }
+            for (int i = KR; i < m; ++i) {
+                const double x = M[(i - KR) * m + l];
+                if (x < best) {
+                    best = x;
+                    prop = i;
+                }
+            }
+        } else {
+            best = M[l];
+            for (int i = 1; i < m; ++i) {
+                const double x = M[i * m + l];
+                if (x < best) {
+                    best = x;
+                    prop = i;
+                }
             }
         }
         v = best;
@@ -110,7 +145,14 @@ __device__ void lap_solve_scalar1(double *lds, int toff, int soff, int m, double
     __builtin_amdgcn_wave_barrier();
     // the LAP value starts at the left fold of the column minima
     double th = mlu[0];
-    for (int j = 1; j < m; ++j) th = th + mlu[j];
+    if constexpr (KR > 0) {
+        // (a short unroll: a fixed m would otherwise hoist all m reads
+        // while the register rows are live)
+#pragma unroll 8
+        for (int j = 1; j < m; ++j) th = th + mlu[j];
+    } else {
+        for (int j = 1; j < m; ++j) th = th + mlu[j];
+    }
     __builtin_amdgcn_wave_barrier();
     int wprop = kNone, wown = kNone;
     if (valid) {
@@ -137,7 +179,13 @@ __device__ void lap_solve_scalar1(double *lds, int toff, int soff, int m, double
             ++st;
             const unsigned long long actm = validm & ~usedm;
             const double ur = mlu[r];
-            const double mv = M[r * m + (valid ? l : 0)];
+            double mv;
+            if (KR1 > 0 && r < KR1)
+                mv = R[r];
+            else if (KR2 > 0 && r < KR)
+                mv = R2[r - 16];
+            else
+                mv = M[(r - KR) * m + (valid ? l : 0)];
             const double s = (mv - ur) - v;
             const unsigned long long bm = __builtin_amdgcn_ballot_w64(s < minv) & actm;
             minv = __builtin_amdgcn_inverse_ballot_w64(bm) ? s : minv;
