@@ -47,6 +47,15 @@ __device__ __forceinline__ double mov_dpp_d(double x)
     return __hiloint2double(hi, lo);
 }
 
+// A copy of x in its own register pair, made by one 64-bit move (the
+// permlane swaps below overwrite both of their operands, and a copy of the
+// two 32-bit halves takes two moves).
+__device__ __forceinline__ double vcopy_d(double x)
+{
+    asm("" : "+v"(x));
+    return x;
+}
+
 // min over each 32-lane half (RW = 32) or the whole wave (RW = 64); every
 // lane receives the minimum of its half / of the wave.  Inputs are never NaN.
 template <int RW>
@@ -57,13 +66,15 @@ __device__ __forceinline__ double part_min(double x)
     x = vmin_f64(x, mov_dpp_d<0x122>(x));  // row_ror:2
     x = vmin_f64(x, mov_dpp_d<0x121>(x));  // row_ror:1
     {
-        const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(x), false, false);
-        const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(x), false, false);
+        const double y = vcopy_d(x);
+        const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
         x = vmin_f64(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
     }
     if constexpr (RW == 64) {
-        const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(x), false, false);
-        const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(x), false, false);
+        const double y = vcopy_d(x);
+        const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false, false);
         x = vmin_f64(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
     }
     return x;
@@ -100,6 +111,7 @@ __device__ void lap_solve_scalar1(double *lds, int toff, int soff, int m, double
     int *mlp = (int *)(mlu + m);
     int *mlw = mlp;  // the rows' proposal winners share the matching's slots: read before it is written
     const unsigned long long validm = (m >= 64) ? ~0ull : ((1ull << m) - 1ull);
+    const int lc = valid ? l : 0;  // lanes past m read column 0 (never used)
 
     // column reduction: lane l scans column l
     constexpr int kNone = 0x7fffffff;
@@ -184,8 +196,13 @@ __device__ void lap_solve_scalar1(double *lds, int toff, int soff, int m, double
                 mv = R[r];
             else if (KR2 > 0 && r < KR)
                 mv = R2[r - 16];
-            else
-                mv = M[(r - KR) * m + (valid ? l : 0)];
+            else {
+                // the row's start as an opaque scalar, so the lane's address
+                // is one add (folding KR * m into it takes a second one)
+                int rb = (r - KR) * m;
+                asm("" : "+s"(rb));
+                mv = M[rb + lc];
+            }
             const double s = (mv - ur) - v;
             const unsigned long long bm = __builtin_amdgcn_ballot_w64(s < minv) & actm;
             minv = __builtin_amdgcn_inverse_ballot_w64(bm) ? s : minv;
@@ -198,10 +215,17 @@ __device__ void lap_solve_scalar1(double *lds, int toff, int soff, int m, double
             // rather than if-converted to add + two selects
             if (__builtin_amdgcn_inverse_ballot_w64(treem)) asm volatile("v_add_f64 %0, %0, %1" : "+v"(u) : "v"(mn));
             if (__builtin_amdgcn_inverse_ballot_w64(usedm)) asm volatile("v_add_f64 %0, %0, -%1" : "+v"(v) : "v"(mn));
-            minv = __builtin_amdgcn_inverse_ballot_w64(1ull << js) ? kInf : minv - mn;
             th = th + mn;
             const int pj = __builtin_amdgcn_readlane(p, js);
             if (pj >= 0) {
+                // the search goes on: minv -= delta, and the chosen column
+                // leaves it.  Its minv - mn is a zero (minv == mn there),
+                // whose low word is 0, so the high word of +inf in that one
+                // lane makes it exactly +inf: one select instead of two.
+                // (When the search ends minv is not read.)
+                minv = minv - mn;
+                const int hi = __builtin_amdgcn_inverse_ballot_w64(1ull << js) ? 0x7ff00000 : __double2hiint(minv);
+                minv = __hiloint2double(hi, __double2loint(minv));
                 usedm |= 1ull << js;
                 treem |= 1ull << pj;
                 r = pj;
