@@ -312,7 +312,10 @@ __global__ __launch_bounds__(64) void k_bzlap_s(const BNode *__restrict__ nodes,
     __syncthreads();
     double u, v, th;
     int p, st;
-    lap_solve_scalar1<32>(lds, 0, mm, m, u, v, p, th, st);
+    if (m <= 16)
+        lap_solve_scalar1<16>(lds, 0, mm, m, u, v, p, th, st);
+    else
+        lap_solve_scalar1<32>(lds, 0, mm, m, u, v, p, th, st);
     __builtin_amdgcn_wave_barrier();
     double *scr = lds + mm;  // row potentials; v over the matching/links area
     if (lane < m) scr[m + lane] = v;
@@ -352,7 +355,10 @@ __global__ __launch_bounds__(64) void k_bzlap_s2(const BNode *__restrict__ nodes
     __syncthreads();
     double u, v, th;
     int p, st;
-    lap_solve_scalar2(lds, toff, soff, m, 2, u, v, p, th, st);
+    if (m <= 16)
+        lap_solve_scalar2<16>(lds, toff, soff, m, 2, u, v, p, th, st);
+    else
+        lap_solve_scalar2<32>(lds, toff, soff, m, 2, u, v, p, th, st);
     __builtin_amdgcn_wave_barrier();
     if (l < m) scr[h * 2 * m + m + l] = v;
     __syncthreads();
@@ -470,7 +476,9 @@ __global__ __launch_bounds__(64) void k_bxlap(const BNode *__restrict__ nodes, B
     __syncthreads();
     double u, v, th;
     int pc, st;
-    if (n <= 32)
+    if (n <= 16)
+        lap_solve_scalar1<16>(M, 0, nn, n, u, v, pc, th, st);
+    else if (n <= 32)
         lap_solve_scalar1<32>(M, 0, nn, n, u, v, pc, th, st);
     else
         lap_solve_scalar1<64>(M, 0, nn, n, u, v, pc, th, st);

@@ -554,12 +554,17 @@ __global__ __launch_bounds__(64) void k_zlap_s(double *__restrict__ Z, double *_
     double u, v, th;
     int p, st;
     if constexpr (H == 1) {
-        if (m <= 32)
+        if (KR == 0 && m <= 16)
+            lap_solve_scalar1<16, KR>(lds, toff[0], soff[0], m, u, v, p, th, st, R, R2);
+        else if (m <= 32)
             lap_solve_scalar1<32, KR>(lds, toff[0], soff[0], m, u, v, p, th, st, R, R2);
         else
             lap_solve_scalar1<64, KR>(lds, toff[0], soff[0], m, u, v, p, th, st, R, R2);
     } else {
-        lap_solve_scalar2(lds, toff, soff, m, nt, u, v, p, th, st);
+        if (m <= 16)
+            lap_solve_scalar2<16>(lds, toff, soff, m, nt, u, v, p, th, st);
+        else
+            lap_solve_scalar2<32>(lds, toff, soff, m, nt, u, v, p, th, st);
     }
     __builtin_amdgcn_wave_barrier();
     // v to the scratch after the potentials (matching and links are done);
@@ -644,12 +649,17 @@ __global__ __launch_bounds__(64) void k_lap_batch_s(const double *__restrict__ c
     double u, v, th;
     int p, st;
     if constexpr (H == 1) {
-        if (m <= 32)
+        if (KR == 0 && m <= 16)
+            lap_solve_scalar1<16, KR>(lds, toff[0], soff[0], m, u, v, p, th, st, R, R2);
+        else if (m <= 32)
             lap_solve_scalar1<32, KR>(lds, toff[0], soff[0], m, u, v, p, th, st, R, R2);
         else
             lap_solve_scalar1<64, KR>(lds, toff[0], soff[0], m, u, v, p, th, st, R, R2);
     } else {
-        lap_solve_scalar2(lds, toff, soff, m, nt, u, v, p, th, st);
+        if (m <= 16)
+            lap_solve_scalar2<16>(lds, toff, soff, m, nt, u, v, p, th, st);
+        else
+            lap_solve_scalar2<32>(lds, toff, soff, m, nt, u, v, p, th, st);
     }
     if (l < m && h < nt) {
         const long long t = t0 + h;
@@ -715,7 +725,9 @@ __global__ __launch_bounds__(64) void k_ylap_s(const double *__restrict__ Yc, do
     __syncthreads();
     double u, v, th;
     int pc, st;
-    if (m <= 32)
+    if (m <= 16)
+        lap_solve_scalar1<16>(lds, 0, mm, m, u, v, pc, th, st);
+    else if (m <= 32)
         lap_solve_scalar1<32>(lds, 0, mm, m, u, v, pc, th, st);
     else
         lap_solve_scalar1<64>(lds, 0, mm, m, u, v, pc, th, st);
@@ -762,7 +774,9 @@ __global__ __launch_bounds__(64) void k_xlap(const double *__restrict__ Xc, doub
     __syncthreads();
     double u, v, th;
     int pc, st;
-    if (n <= 32)
+    if (n <= 16)
+        lap_solve_scalar1<16>(M, 0, nn, n, u, v, pc, th, st);
+    else if (n <= 32)
         lap_solve_scalar1<32>(M, 0, nn, n, u, v, pc, th, st);
     else
         lap_solve_scalar1<64>(M, 0, nn, n, u, v, pc, th, st);

@@ -56,8 +56,11 @@ __device__ __forceinline__ double vcopy_d(double x)
     return x;
 }
 
-// min over each 32-lane half (RW = 32) or the whole wave (RW = 64); every
-// lane receives the minimum of its half / of the wave.  Inputs are never NaN.
+// min over each 16-lane row (RW = 16), each 32-lane half (RW = 32) or the
+// whole wave (RW = 64); every lane receives the minimum of its row / half /
+// wave.  The solvers call it with RW no smaller than the lanes their live
+// columns span, so the lanes that matter get the part's minimum; the others
+// hold +inf or NaN and are never chosen.
 template <int RW>
 __device__ __forceinline__ double part_min(double x)
 {
@@ -65,7 +68,7 @@ __device__ __forceinline__ double part_min(double x)
     x = vmin_f64(x, mov_dpp_d<0x124>(x));  // row_ror:4
     x = vmin_f64(x, mov_dpp_d<0x122>(x));  // row_ror:2
     x = vmin_f64(x, mov_dpp_d<0x121>(x));  // row_ror:1
-    {
+    if constexpr (RW >= 32) {
         const double y = vcopy_d(x);
         const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
         const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
@@ -88,8 +91,9 @@ __device__ __forceinline__ double part_min(double x)
 // and the flag updates are scalar bit operations.  Non-tree valid columns
 // keep minv, every other lane holds +inf, so the step's minimum reads minv
 // directly.
-// Tile at lds + toff, scratch at lds + soff; m <= RW (RW = 32: every live
-// column sits in the lower half-wave and the minimum stops after 32 lanes).
+// Tile at lds + toff, scratch at lds + soff; m <= RW (RW = 32 or 16: every
+// live column sits in the lowest 32 or 16 lanes and the minimum stops
+// there).
 //
 // KR > 0 (KR <= m, KR <= 24): rows 0..KR-1 of the tile are held in
 // registers instead, lane l holding entry (r, l) of row r in R[r] (r < 16)
@@ -273,10 +277,14 @@ __device__ void lap_solve_scalar1(double *lds, int toff, int soff, int m, double
 // live part: the vector work (row scan, relaxation, the 32-lane minimum,
 // masked updates) is shared, the choice of column, the matched row and the
 // path flip are per part in scalar registers.  Part h's tile and scratch
-// are at tile_off[h], scr_off[h]; nparts <= 2 parts are live.
+// are at tile_off[h], scr_off[h]; nparts <= 2 parts are live.  RW = 16 when
+// m <= 16: each part's live columns sit in the first 16 of its lanes and the
+// minimum stops after them.
+template <int RW = 32>
 __device__ void lap_solve_scalar2(double *lds, const int *tile_off, const int *scr_off, int m, int nparts,
                                   double &u, double &v, int &p, double &theta, int &steps)
 {
+    static_assert(RW == 16 || RW == 32, "a part spans at most 32 lanes");
     const int lane = (int)(threadIdx.x & 63);
     const int h = lane >> 5;
     const int l = lane & 31;
@@ -351,7 +359,7 @@ __device__ void lap_solve_scalar2(double *lds, const int *tile_off, const int *s
         minv = __builtin_amdgcn_inverse_ballot_w64(bm) ? s : minv;
         way = __builtin_amdgcn_inverse_ballot_w64(bm) ? (__builtin_amdgcn_inverse_ballot_w64(kUpper) ? last1 : last0)
                                                       : way;
-        const double mn = part_min<32>(minv);
+        const double mn = part_min<RW>(minv);
         const unsigned long long eqm = __builtin_amdgcn_ballot_w64(minv == mn) & actm;
         const unsigned long long bf = eqm & freem;
         const unsigned f0 = (unsigned)bf, c0 = (unsigned)eqm;
