@@ -341,8 +341,12 @@ int qap_set_stream(qap_handle h, void *hip_stream);
  * the parent's reduced costs (qap_fold_child), up to p->batch open nodes of
  * uneven size per batched dual ascent (qap_batch_dual_ascent), taken
  * depth-first from a stack; nodes with at most enum_below free facilities
- * are enumerated.  h's own state is not changed (the root restarts from the
- * initial costs).  perm_out (host, n): optimal permutation; *obj_out its
+ * are enumerated.  The batched Z-LAP mapping of a tile size is measured on
+ * this search's own tiles by its first batch of that size with at least
+ * 1e8 tile iterations of Z-LAP work (smaller batches take the process-wide
+ * choice); results do not depend on it.  h's own state is not changed (the
+ * root restarts from the initial costs).  perm_out (host, n): optimal
+ * permutation; *obj_out its
  * exact cost.  p NULL selects the defaults.  Errors: QAP_EUNSUPPORTED
  * (n > 24), QAP_ESTATE (no permutation below ub0), QAP_EINVAL. */
 int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, double *obj_out,

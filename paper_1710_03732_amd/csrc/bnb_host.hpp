@@ -316,8 +316,20 @@ namespace {
 // the tune cache already holds it (else the rule-based one; every mapping
 // gives the same results), and a handle whose trace has no room for the
 // iterations is refused instead of grown.
+// search_tune (the branch-and-bound's, one per search): Z-LAP mappings
+// measured on this search's own tiles, by tile size.  The process-wide
+// choice for a tile size is measured once, on the tiles of whatever batch
+// first had that size, and suits other instances less well (a grid
+// instance's tiles take the mappings' relative times elsewhere than a dense
+// one's).  A batch whose Z-LAP work is at least kSearchTuneWork tile
+// iterations (the measurement then costs about 2 % of it) is measured on
+// its own tiles once per search and size; smaller batches, and later
+// batches of a measured size, take the stored choice.
+constexpr double kSearchTuneWork = 1e8;
+
 int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_stats *st, bool no_alloc,
-               char *ws, size_t ws_bytes, std::vector<DevScalars> *scal_out = nullptr)
+               char *ws, size_t ws_bytes, std::vector<DevScalars> *scal_out = nullptr,
+               std::map<int, int> *search_tune = nullptr)
 {
     if (count < 0 || (count > 0 && (!hs || !bp))) return fail(nullptr, QAP_EINVAL, "bad batch arguments");
     if (count == 0) return QAP_OK;
@@ -494,10 +506,19 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
             tune_tiles_n = hs[b]->T;
             break;
         }
-    const int Lz = cur == 0 ? -1
-                   : bp->zlap_lanes != 0 ? bp->zlap_lanes
-                   : no_alloc ? known_batch_lanes(h0->prm.device, mz)
-                              : tuned_batch_lanes(h0->prm.device, stream, mz, tune_src, tune_tiles_n);
+    int Lz;
+    if (cur == 0)
+        Lz = -1;
+    else if (bp->zlap_lanes != 0)
+        Lz = bp->zlap_lanes;
+    else if (no_alloc)
+        Lz = known_batch_lanes(h0->prm.device, mz);
+    else if (search_tune && search_tune->count(mz))
+        Lz = (*search_tune)[mz];
+    else if (search_tune && tune_src && (double)zl[cur] * bp->iters >= kSearchTuneWork)
+        Lz = (*search_tune)[mz] = measure_bzlap(stream, mz, tune_src, tune_tiles_n).lanes;
+    else
+        Lz = tuned_batch_lanes(h0->prm.device, stream, mz, tune_src, tune_tiles_n);
     const int Ly = my <= 8 ? 8 : my <= 16 ? 16 : my <= 32 ? 32 : 64;
     auto launch_all = [&]() -> hipError_t {
         hipError_t e;
@@ -754,6 +775,7 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
     double UB = P.ub0;
     std::vector<int> best(n, -1);
     long long nodes_done = 0, da_iters = 0, batches = 0, enumerated = 0;
+    std::map<int, int> search_tune;  // Z-LAP mappings measured on this search's tiles
     double node_bytes = 0.0;
     // node handles take their arenas from the pool unless h has an allocator
     // of its own (children inherit the parameters of their parent); declared
@@ -857,7 +879,7 @@ int qap_bnb_solve(qap_handle h, const qap_bnb_params *p, int32_t *perm_out, doub
         qap_batch_params bp{iters, P.window, P.min_improve, UB};
         // (the nodes' scalar blocks come back with the batch, in one copy)
         std::vector<DevScalars> sv;
-        rc = batch_core(hs.data(), (int)hs.size(), &bp, nullptr, false, nullptr, 0, &sv);
+        rc = batch_core(hs.data(), (int)hs.size(), &bp, nullptr, false, nullptr, 0, &sv, &search_tune);
         if (rc != QAP_OK) {
             h->err = hs[0]->err;
             break;
