@@ -53,18 +53,6 @@ __device__ inline BlockLapLds block_lap_lds(char *base, int m)
     return s;
 }
 
-__device__ __forceinline__ int wave_min_i32(int k)
-{
-    k = min(k, __builtin_amdgcn_mov_dpp(k, 0x128, 0xf, 0xf, true));  // row_ror:8
-    k = min(k, __builtin_amdgcn_mov_dpp(k, 0x124, 0xf, 0xf, true));  // row_ror:4
-    k = min(k, __builtin_amdgcn_mov_dpp(k, 0x122, 0xf, 0xf, true));  // row_ror:2
-    k = min(k, __builtin_amdgcn_mov_dpp(k, 0x121, 0xf, 0xf, true));  // row_ror:1
-    const auto a = __builtin_amdgcn_permlane16_swap(k, k, false, false);
-    k = min((int)a[0], (int)a[1]);
-    const auto b = __builtin_amdgcn_permlane32_swap(k, k, false, false);
-    return min((int)b[0], (int)b[1]);
-}
-
 // Solve the m x m LAP whose row r starts at M + r*m (global memory), with all
 // kBlockLap threads of the block.  Outputs per slot c (row and column
 // j = t + kBlockLap*c): u[c], v[c], p[c] (row assigned to column j, -1 for
@@ -178,8 +166,8 @@ __device__ void lap_solve_block(const double *__restrict__ M, int m, const Block
                     if (p[c] < 0) jf = j;
                 }
             }
-            jf = wave_min_i32(jf);
-            ja = wave_min_i32(ja);
+            jf = group_min_i32<64>(jf);
+            ja = group_min_i32<64>(ja);
             if (lane == 0) {
                 L.red_i[wave] = jf;
                 L.red_i[kBlockWaves + wave] = ja;

@@ -32,20 +32,6 @@ namespace qap {
 typedef double dreg16 __attribute__((ext_vector_type(16)));
 typedef double dreg8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ double vmin_f64(double a, double b)
-{
-    double r;
-    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-
-template <int CTRL>
-__device__ __forceinline__ double mov_dpp_d(double x)
-{
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, true);
-    return __hiloint2double(hi, lo);
-}
 
 // A copy of x in its own register pair, made by one 64-bit move (the
 // permlane swaps below overwrite both of their operands, and a copy of the
@@ -64,21 +50,21 @@ __device__ __forceinline__ double vcopy_d(double x)
 template <int RW>
 __device__ __forceinline__ double part_min(double x)
 {
-    x = vmin_f64(x, mov_dpp_d<0x128>(x));  // row_ror:8
-    x = vmin_f64(x, mov_dpp_d<0x124>(x));  // row_ror:4
-    x = vmin_f64(x, mov_dpp_d<0x122>(x));  // row_ror:2
-    x = vmin_f64(x, mov_dpp_d<0x121>(x));  // row_ror:1
+    x = dmin(x, dpp_d<0x128>(x));  // row_ror:8
+    x = dmin(x, dpp_d<0x124>(x));  // row_ror:4
+    x = dmin(x, dpp_d<0x122>(x));  // row_ror:2
+    x = dmin(x, dpp_d<0x121>(x));  // row_ror:1
     if constexpr (RW >= 32) {
         const double y = vcopy_d(x);
         const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
         const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
-        x = vmin_f64(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
+        x = dmin(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
     }
     if constexpr (RW == 64) {
         const double y = vcopy_d(x);
         const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false, false);
         const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false, false);
-        x = vmin_f64(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
+        x = dmin(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
     }
     return x;
 }

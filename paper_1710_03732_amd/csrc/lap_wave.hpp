@@ -40,15 +40,26 @@ namespace qap {
 
 constexpr double kInf = __builtin_huge_val();
 
+// Lane moves for the group minima.  Every control used here (row
+// rotations, half-row mirror, quad permutes) gives each lane a source lane,
+// so the result does not depend on the old value: bound_ctrl with full masks
+// needs no copy of it.
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x)
 {
-    const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ double dmin(double a, double b) { return __builtin_fmin(a, b); }
+// The minimum of two doubles that are never NaN, as one v_min_f64 (fmin
+// would first quiet each operand, which changes nothing here).
+__device__ __forceinline__ double dmin(double a, double b)
+{
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 
 // min over each 16-lane DPP row (every lane gets the row minimum)
 __device__ __forceinline__ double row16_min(double x)
@@ -93,6 +104,31 @@ __device__ __forceinline__ double group_min(double x)
         if constexpr (L >= 32) x = swap16_min(x);
         if constexpr (L == 64) x = swap32_min(x);
         return x;
+    }
+}
+
+// The same minimum for ints (the chosen column's index).
+template <int L>
+__device__ __forceinline__ int group_min_i32(int k)
+{
+    if constexpr (L == 8) {
+        k = min(k, __builtin_amdgcn_mov_dpp(k, 0x141, 0xf, 0xf, true));  // row_half_mirror
+        k = min(k, __builtin_amdgcn_mov_dpp(k, 0x4E, 0xf, 0xf, true));   // quad_perm [2,3,0,1]
+        return min(k, __builtin_amdgcn_mov_dpp(k, 0xB1, 0xf, 0xf, true));  // quad_perm [1,0,3,2]
+    } else {
+        k = min(k, __builtin_amdgcn_mov_dpp(k, 0x128, 0xf, 0xf, true));  // row_ror:8
+        k = min(k, __builtin_amdgcn_mov_dpp(k, 0x124, 0xf, 0xf, true));  // row_ror:4
+        k = min(k, __builtin_amdgcn_mov_dpp(k, 0x122, 0xf, 0xf, true));  // row_ror:2
+        k = min(k, __builtin_amdgcn_mov_dpp(k, 0x121, 0xf, 0xf, true));  // row_ror:1
+        if constexpr (L >= 32) {
+            const auto a = __builtin_amdgcn_permlane16_swap(k, k, false, false);
+            k = min((int)a[0], (int)a[1]);
+        }
+        if constexpr (L == 64) {
+            const auto b = __builtin_amdgcn_permlane32_swap(k, k, false, false);
+            k = min((int)b[0], (int)b[1]);
+        }
+        return k;
     }
 }
 
@@ -175,7 +211,7 @@ __device__ void lap_solve(const double *__restrict__ M, int m, int l, int gbase,
                 way[c] = -1;
             }
             used = 0u;
-            intree = ((i0 % L) == l) ? (1u << (i0 / L)) : 0u;
+            intree = (((unsigned)i0 % L) == (unsigned)l) ? (1u << ((unsigned)i0 / L)) : 0u;
             r = i0;
             last = -1;
             fresh = false;
@@ -197,18 +233,21 @@ __device__ void lap_solve(const double *__restrict__ M, int m, int l, int gbase,
             }
         }
         const double mn = group_min<L>(best);
-        // chosen column: tied non-tree columns, unmatched first, lowest index
-        int js = -1;
+        // chosen column: tied non-tree columns, unmatched first, lowest
+        // index: each lane offers its lowest tied column (and its lowest
+        // unmatched one), then the group takes the least of the offers
+        int jf = kNone, ja = kNone;
 #pragma unroll
-        for (int pass = 0; pass < 2; ++pass) {
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int j = l + L * c;
-                const bool cand = j < m && !((used >> c) & 1u) && minv[c] == mn && (pass == 1 || p[c] < 0);
-                const unsigned long long b = __builtin_amdgcn_ballot_w64(cand) & gmask;
-                if (js < 0 && b != 0ull) js = (__builtin_ctzll(b) - gbase) + L * c;
+        for (int c = C - 1; c >= 0; --c) {
+            const int j = l + L * c;
+            if (j < m && !((used >> c) & 1u) && minv[c] == mn) {
+                ja = j;
+                if (p[c] < 0) jf = j;
             }
         }
+        jf = group_min_i32<L>(jf);
+        ja = group_min_i32<L>(ja);
+        const int js = (jf != kNone) ? jf : ja;
         const double delta = mn;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -237,7 +276,7 @@ __device__ void lap_solve(const double *__restrict__ M, int m, int l, int gbase,
             unsigned onpath = 0u;
             int j = js;
             while (j >= 0) {
-                if ((j % L) == l) onpath |= 1u << (j / L);
+                if (((unsigned)j % L) == (unsigned)l) onpath |= 1u << ((unsigned)j / L);
                 j = lw[j];
             }
             int np[C];
@@ -259,8 +298,9 @@ __device__ void lap_solve(const double *__restrict__ M, int m, int l, int gbase,
             i0 = unm ? __builtin_ctzll(unm) : m;
             fresh = true;
         } else {
-            if ((js % L) == l) used |= 1u << (js / L);
-            if ((pj % L) == l) intree |= 1u << (pj / L);
+            // (js, pj >= 0: unsigned division by L is a mask and a shift)
+            if (((unsigned)js % L) == (unsigned)l) used |= 1u << ((unsigned)js / L);
+            if (((unsigned)pj % L) == (unsigned)l) intree |= 1u << ((unsigned)pj / L);
             r = pj;
             last = js;
         }
