@@ -285,7 +285,12 @@ __global__ __launch_bounds__(256) void k_bzlap(const BNode *__restrict__ nodes, 
     double *vs = lu + m;
     if (l < m) vs[l] = v[0];
     __builtin_amdgcn_wave_barrier();
-    for (int e = l; e < mm; e += L) src[e] = (M[e] - lu[e / m]) - vs[e % m];
+    // slacks back in place, row by row (no division per element)
+    for (int col = l; col < m; col += L) {
+        const double vc = vs[col];
+#pragma unroll 2
+        for (int r = 0; r < m; ++r) src[r * m + col] = (M[r * m + col] - lu[r]) - vc;
+    }
     if (l == 0) {
         Yc[t] = yc0 + th;
         atomicAdd((unsigned long long *)(glob(N.bins) + (jg & (kStepBins - 1))), (unsigned long long)st);
@@ -433,7 +438,11 @@ __global__ __launch_bounds__(256) void k_bylap(const BNode *__restrict__ nodes, 
     double *vs = lu + m;
     if (l < m) vs[l] = v[0];
     __builtin_amdgcn_wave_barrier();
-    for (int e = l; e < mm; e += L) Py[base + e] = (M[e] - lu[e / m]) - vs[e % m];
+    for (int col = l; col < m; col += L) {
+        const double vc = vs[col];
+#pragma unroll 2
+        for (int r = 0; r < m; ++r) Py[base + r * m + col] = (M[r * m + col] - lu[r]) - vc;
+    }
     if (l == 0) {
         Xc[ip] = xc0 + th;
         atomicAdd((unsigned long long *)(glob(N.bins) + (jg & (kStepBins - 1))), (unsigned long long)st);

@@ -218,7 +218,7 @@ __device__ void lap_solve(const double *__restrict__ M, int m, int l, int gbase,
         }
         ++st;
         const double ur = lu[r];
-        const double *row = M + (size_t)r * m;
+        const double *row = M + __umul24((unsigned)r, (unsigned)m);  // (r * m < 2^24: a full-rate multiply)
         double best = kInf;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
