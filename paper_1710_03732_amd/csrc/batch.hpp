@@ -83,6 +83,19 @@ __device__ __forceinline__ int find_node(const long long *pre, int nnodes, long 
     return lo;
 }
 
+// The node of job j >= the first job of node b0: step over the node ends in
+// between.  Kernels whose lane groups hold different jobs find the node of
+// the wavefront's first job once (find_node on a wave-uniform job runs on
+// scalar loads, which the scalar cache serves) and each group steps from
+// there, rather than each group searching with vector loads in turn.
+__device__ __forceinline__ int find_node_from(const long long *pre, int nnodes, int b0, long long j)
+{
+    const gptr<const long long> p = glob(pre);
+    int b = b0;
+    while (b + 1 < nnodes && p[b + 1] <= j) ++b;
+    return b;
+}
+
 // ----------------------------------------------------------------- sweep --
 __global__ __launch_bounds__(256) void k_bsweep(const BNode *__restrict__ nodes, BatchPrefix pf, int nnodes)
 {
@@ -261,10 +274,16 @@ __global__ __launch_bounds__(256) void k_bzlap(const BNode *__restrict__ nodes, 
     const long long jg = (long long)blockIdx.x * G + g;
     const int per = mmax * mmax + 2 * mmax;
     double *M = lds + (size_t)g * per;
-    bool live = jg < glob(pf.zl)[nnodes];
+    const long long total = glob(pf.zl)[nnodes];
+    // the wavefront finds the node of its first group's tile, each group
+    // steps from there to its own
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const long long jw = (long long)blockIdx.x * G + (long long)wv * (64 / L);
+    const int bw = find_node(pf.zl, nnodes, jw < total ? jw : total - 1);
+    bool live = jg < total;
     int b = 0;
     if (live) {
-        b = find_node(pf.zl, nnodes, jg);
+        b = find_node_from(pf.zl, nnodes, bw, jg);
         live = !glob(nodes[b].S)->stopped;
     }
     if (!live) return;  // whole groups leave together; no block barrier below
@@ -391,10 +410,14 @@ __global__ __launch_bounds__(256) void k_bylap(const BNode *__restrict__ nodes, 
     const long long jg = (long long)blockIdx.x * G + g;
     const int per = mmax * mmax + 2 * mmax;
     double *M = lds + (size_t)g * per;
-    bool live = jg < glob(pf.yl)[nnodes];
+    const long long total = glob(pf.yl)[nnodes];
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const long long jw = (long long)blockIdx.x * G + (long long)wv * (64 / L);
+    const int bw = find_node(pf.yl, nnodes, jw < total ? jw : total - 1);
+    bool live = jg < total;
     int b = 0;
     if (live) {
-        b = find_node(pf.yl, nnodes, jg);
+        b = find_node_from(pf.yl, nnodes, bw, jg);
         live = !glob(nodes[b].S)->stopped;
     }
     if (!live) return;
