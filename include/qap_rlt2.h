@@ -344,7 +344,8 @@ int qap_set_stream(qap_handle h, void *hip_stream);
  * are enumerated.  The batched Z-LAP mapping of a tile size is measured on
  * this search's own tiles by its first batch of that size with at least
  * 1e8 tile iterations of Z-LAP work (smaller batches take the process-wide
- * choice); results do not depend on it.  h's own state is not changed (the
+ * choice; the environment variable QAP_SEARCH_TUNE_WORK replaces 1e8);
+ * results do not depend on it.  h's own state is not changed (the
  * root restarts from the initial costs).  perm_out (host, n): optimal
  * permutation; *obj_out its
  * exact cost.  p NULL selects the defaults.  Errors: QAP_EUNSUPPORTED

@@ -324,8 +324,16 @@ namespace {
 // one's).  A batch whose Z-LAP work is at least kSearchTuneWork tile
 // iterations (the measurement then costs about 2 % of it) is measured on
 // its own tiles once per search and size; smaller batches, and later
-// batches of a measured size, take the stored choice.
+// batches of a measured size, take the stored choice.  QAP_SEARCH_TUNE_WORK
+// replaces the threshold (tests set it low so that small searches take
+// this path).
 constexpr double kSearchTuneWork = 1e8;
+
+double search_tune_work()
+{
+    const char *e = std::getenv("QAP_SEARCH_TUNE_WORK");
+    return (e && *e) ? std::atof(e) : kSearchTuneWork;
+}
 
 int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_stats *st, bool no_alloc,
                char *ws, size_t ws_bytes, std::vector<DevScalars> *scal_out = nullptr,
@@ -515,7 +523,7 @@ int batch_core(qap_handle *hs, int count, const qap_batch_params *bp, qap_batch_
         Lz = known_batch_lanes(h0->prm.device, mz);
     else if (search_tune && search_tune->count(mz))
         Lz = (*search_tune)[mz];
-    else if (search_tune && tune_src && (double)zl[cur] * bp->iters >= kSearchTuneWork)
+    else if (search_tune && tune_src && (double)zl[cur] * bp->iters >= search_tune_work())
         Lz = (*search_tune)[mz] = measure_bzlap(stream, mz, tune_src, tune_tiles_n).lanes;
     else
         Lz = tuned_batch_lanes(h0->prm.device, stream, mz, tune_src, tune_tiles_n);

@@ -256,6 +256,23 @@ def test_bnb_dense_n14_batched():
     assert obj2 == g["optimum"]
 
 
+def test_bnb_search_scoped_mapping_choice_keeps_the_optimum(monkeypatch):
+    """With QAP_SEARCH_TUNE_WORK = 1 every batch of the search times the
+    Z-LAP mappings on its own tiles (once per tile size) instead of taking
+    the process-wide choice; a mapping changes only the speed, so the search
+    ends at the golden optimum with the same nodes as with the default."""
+    with open(os.path.join(GOLDEN, "dense_n14_optimum.json")) as f:
+        g = json.load(f)
+    F, D, Bm = I.dense_n14().arrays()
+    h = B.DualAscent(F, D, Bm)
+    obj0, _, st0 = h.bnb_solve(batch=256, node_iters=4, window=25)
+    monkeypatch.setenv("QAP_SEARCH_TUNE_WORK", "1")
+    obj, perm, st = h.bnb_solve(batch=256, node_iters=4, window=25)
+    assert obj == obj0 == g["optimum"]
+    assert O.qap_cost(F, D, Bm, perm) == g["optimum"]
+    assert (st["nodes"], st["batches"], st["da_iters"]) == (st0["nodes"], st0["batches"], st0["da_iters"])
+
+
 def test_bnb_dense_n16():
     """n = 16 dense symmetric U{0..99}: the optimum both exact solvers of the
     oracle agree on (golden file; the Gilmore-Lawler B&B needed about 1.5e7
