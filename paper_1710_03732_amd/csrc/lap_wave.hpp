@@ -27,8 +27,9 @@
 //   * min over the group: DPP row rotations inside 16-lane rows (half-row
 //     mirror and quad permutes for 8-lane groups), v_permlane16_swap across
 //     the two rows of a 32-lane group, v_permlane32_swap across wave halves;
-//   * the chosen column: wave ballots of the tied columns (unmatched ones
-//     first), masked to the group, lowest set bit;
+//   * the chosen column: each lane offers its lowest tied column (and its
+//     lowest unmatched tied one), and an integer minimum over the group by
+//     the same lane moves picks the lowest index, unmatched columns first;
 //   * the potential of the next row and the row matched to the chosen column
 //     are read from a per-group LDS mirror (u is written back there when a
 //     row's search ends, the matching when a path flips), at a group-uniform
