@@ -366,6 +366,57 @@ def test_full_size_n42_iteration0_and_sampled_tiles():
     gpu.close()
 
 
+def _mem_available_gb():
+    """MemAvailable of /proc/meminfo in GB (0 if unreadable)."""
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemAvailable:"):
+                    return int(line.split()[1]) * 1024 / 1e9
+    except OSError:
+        pass
+    return 0.0
+
+
+@pytest.mark.skipif(_mem_available_gb() < 60, reason="the oracle's dense n = 42 z array takes about 44 GB of host memory")
+def test_full_size_n42_trajectory_bitwise():
+    """n = 42 (tiles of size 40: the Z-LAP kernel holding 24 tile rows in
+    registers) against the oracle's full F1 iterations (Algorithm 1): the
+    bound after each of the first K iterations, and at t = K all of pi_x and
+    pi_y plus 2,000 random pi_z tiles, bit for bit."""
+    K = 3
+    inst = I.dense_n42()
+    F, D, Bm = inst.arrays()
+    n = 42
+    print(f"n42 trajectory: {inst.name}, K={K}", flush=True)
+    gpu = B.DualAscent(F, D, Bm)
+    cpu = O.DualAscent(F, D, Bm)
+    for t in range(K):
+        r = gpu.run(1)
+        cpu.run(1)
+        tg, tc = gpu.trace(), cpu.trace()
+        assert len(tg) == t + 1
+        assert np.array_equal(tg, tc), (t, tg, tc)
+        assert r["ub"] == cpu.UB
+    hdr, x, y, _ = gpu.export_state(with_z=False)
+    X, Y, _ = cpu.export(with_z=False)
+    assert hdr.lb == cpu.LB and hdr.t == K
+    assert np.array_equal(x, X.reshape(-1))
+    assert np.array_equal(y, dense_to_compact_y(n, Y))
+    rng = np.random.default_rng(4242)
+    picks = [(0, 1, 0, 1), (41, 40, 41, 40), (0, 41, 41, 0)]
+    while len(picks) < 2000:
+        i, j = rng.choice(n, 2, replace=False)
+        p, q = rng.choice(n, 2, replace=False)
+        picks.append((int(i), int(j), int(p), int(q)))
+    got = gpu.export_tiles([tile_index(n, i, p, j, q) for (i, j, p, q) in picks])
+    ref = cpu.z_tiles(picks)
+    bad = [a for a in range(len(picks)) if not np.array_equal(got[a], ref[a])]
+    assert not bad, [picks[a] for a in bad[:5]]
+    gpu.close()
+    del cpu
+
+
 def test_size_beyond_device_memory_is_rejected_before_allocation():
     """n = 64 needs a 500 GB z array: init fails with QAP_ENOMEM, cleanly."""
     F = np.ones((64, 64))
